@@ -1,0 +1,225 @@
+"""Assembled sparse operators of the pressure path (test infrastructure only).
+
+All matrices act on the TENSOR layout (see layout.py) and are built with scipy.sparse.kron
+from 1D periodic matrices, following Section 2.1 of arXiv:1602.05806:
+
+  D      1D weak gradient, block row i: -L~ on cell i, R~ on cell i+1           eq. (weakgradientop)
+  H      1D pressure operator D^T M^-1 D (block tridiagonal L, C, R)           eq. (PerPrSyst)
+  K      sum_d h_d^-2 (M on the other directions) (x) H_d                      eq. (pSyst)
+  A_p    dt * K, acting on P^{n+theta}                                         eq. (LOpressure)
+  A_v    M^{xyz} + nu dt K                                                     eqs. (uSDG12), (Ux), (implicitviscosity)
+  B_d    h_d^-1 (M on the other directions) (x) D_d^T: RHS b = sum_d B_d U_d   eq. (LOpressure)
+  G_d    dt h_d^-1 M_d^-1 D_d: velocity update U_d -= G_d q                    eq. (LOvelocityU)
+
+Periodic boundaries in every direction: the block rows wrap (the paper's 1D periodic form,
+eq. (pSyst1d), uses P_{Nx+1} = P_1).
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from .basis import tables
+
+
+class Grid:
+    """Uniform periodic Cartesian grid: cells=(nx,ny[,nz]), lengths=(Lx,Ly[,Lz]), degree N."""
+
+    def __init__(self, cells, lengths, N):
+        self.cells = tuple(int(c) for c in cells)
+        self.lengths = tuple(float(x) for x in lengths)
+        if len(self.cells) not in (2, 3) or len(self.lengths) != len(self.cells):
+            raise ValueError("2D or 3D grids only")
+        self.dim = len(self.cells)
+        self.N = int(N)
+        self.n = self.N + 1
+        self.h = tuple(L / c for L, c in zip(self.lengths, self.cells))
+        self.tab = tables(self.N)
+        self.ndof = int(np.prod(self.cells)) * self.n ** self.dim
+
+    def shape(self):
+        """Tensor-layout shape, axes ordered (z,) y, x."""
+        return tuple(c * self.n for c in reversed(self.cells))
+
+
+# ---------------------------------------------------------------- 1D periodic matrices
+
+def mass_1d(nc, N):
+    """Global 1D mass matrix I_nc (x) diag(w) (GL basis: diagonal, text after eq. pDGpoly)."""
+    return sp.kron(sp.identity(nc), sp.diags(tables(N).w), format="csr")
+
+
+def grad_1d(nc, N):
+    """Periodic weak gradient D of eq. (weakgradientop): (D P)_i = R~ P_{i+1} - L~ P_i.
+
+    Row block i is dual cell i (between main cells i and i+1)."""
+    t = tables(N)
+    n = t.n
+    D = sp.lil_matrix((nc * n, nc * n))
+    for i in range(nc):
+        ip = (i + 1) % nc
+        D[i * n:(i + 1) * n, i * n:(i + 1) * n] = D[i * n:(i + 1) * n, i * n:(i + 1) * n].toarray() - t.Lt
+        D[i * n:(i + 1) * n, ip * n:(ip + 1) * n] = D[i * n:(i + 1) * n, ip * n:(ip + 1) * n].toarray() + t.Rt
+    return D.tocsr()
+
+
+def pressure_1d(nc, N):
+    """H = D^T M^-1 D (eq. PerPrSyst), exactly symmetrised against rounding."""
+    D = grad_1d(nc, N)
+    Minv = sp.kron(sp.identity(nc), sp.diags(1.0 / tables(N).w))
+    H = (D.T @ Minv @ D).tocsr()
+    return ((H + H.T) * 0.5).tocsr()
+
+
+def l2_dual_to_main_1d(nc, N):
+    """pi_{*->#} along the staggered direction, eq. (l2forward):
+    U#_i = M^-1 (M^L U*_{i-1} + M^R U*_i) (dual cell i-1 overlaps the left half of main cell i)."""
+    t = tables(N)
+    n = t.n
+    P = sp.lil_matrix((nc * n, nc * n))
+    Minv = np.diag(1.0 / t.w)
+    for i in range(nc):
+        im = (i - 1) % nc
+        blk = P[i * n:(i + 1) * n, im * n:(im + 1) * n].toarray()
+        P[i * n:(i + 1) * n, im * n:(im + 1) * n] = blk + Minv @ t.ML
+        blk = P[i * n:(i + 1) * n, i * n:(i + 1) * n].toarray()
+        P[i * n:(i + 1) * n, i * n:(i + 1) * n] = blk + Minv @ t.MR
+    return P.tocsr()
+
+
+def l2_main_to_dual_1d(nc, N):
+    """pi_{#->*} along the staggered direction, eq. (l2backward):
+    F*_i = M^-1 (M^L F#_i + M^R F#_{i+1})."""
+    t = tables(N)
+    n = t.n
+    P = sp.lil_matrix((nc * n, nc * n))
+    Minv = np.diag(1.0 / t.w)
+    for i in range(nc):
+        ip = (i + 1) % nc
+        blk = P[i * n:(i + 1) * n, i * n:(i + 1) * n].toarray()
+        P[i * n:(i + 1) * n, i * n:(i + 1) * n] = blk + Minv @ t.ML
+        blk = P[i * n:(i + 1) * n, ip * n:(ip + 1) * n].toarray()
+        P[i * n:(i + 1) * n, ip * n:(ip + 1) * n] = blk + Minv @ t.MR
+    return P.tocsr()
+
+
+# ---------------------------------------------------------------- d-dimensional assembly
+
+def _kron_along(grid, d, mat_d, other):
+    """kron over tensor axes (z,) y, x with mat_d on direction d and other(e) elsewhere."""
+    mats = []
+    for e in reversed(range(grid.dim)):          # tensor axis order: last direction first
+        mats.append(mat_d if e == d else other(e))
+    out = mats[0]
+    for m in mats[1:]:
+        out = sp.kron(out, m, format="csr")
+    return out.tocsr()
+
+
+def stiffness(grid):
+    """K = sum_d h_d^-2 (W on the other directions) (x) H_d  (eq. pSyst without dt)."""
+    K = None
+    for d in range(grid.dim):
+        H = pressure_1d(grid.cells[d], grid.N)
+        term = _kron_along(grid, d, H, lambda e: mass_1d(grid.cells[e], grid.N)) / grid.h[d] ** 2
+        K = term if K is None else K + term
+    return K.tocsr()
+
+
+def full_mass(grid):
+    """M^{xyz}: the d-fold tensor product of the 1D mass (diagonal)."""
+    return _kron_along(grid, 0, mass_1d(grid.cells[0], grid.N),
+                       lambda e: mass_1d(grid.cells[e], grid.N))
+
+
+def pressure_operator(grid, dt):
+    """A_p = dt K acting on q = P^{n+theta} (eq. LOpressure; eq. pSyst divided by theta)."""
+    return (dt * stiffness(grid)).tocsr()
+
+
+def viscous_operator(grid, dt, nu):
+    """A_v = M^{xyz} + nu dt K (eq. implicitviscosity with the dt and h factors of eq. uSDG12)."""
+    return (full_mass(grid) + nu * dt * stiffness(grid)).tocsr()
+
+
+def div_rhs(grid, d):
+    """B_d = h_d^-1 (W on the other directions) (x) D_d^T; b = sum_d B_d U_d (eq. LOpressure).
+
+    The discrete divergence of eq. (pSDG1) is -sum_d B_d U_d."""
+    Dt = grad_1d(grid.cells[d], grid.N).T.tocsr()
+    return (_kron_along(grid, d, Dt, lambda e: mass_1d(grid.cells[e], grid.N)) / grid.h[d]).tocsr()
+
+
+def grad_update(grid, d, dt):
+    """G_d = dt h_d^-1 M_d^-1 D_d (identity on the other directions); eq. (LOvelocityU)."""
+    nc = grid.cells[d]
+    Minv = sp.kron(sp.identity(nc), sp.diags(1.0 / grid.tab.w))
+    G1 = (Minv @ grad_1d(nc, grid.N)).tocsr() * (dt / grid.h[d])
+    return _kron_along(grid, d, G1, lambda e: sp.identity(grid.cells[e] * grid.n))
+
+
+# ---------------------------------------------------------------- null space (Section 2.1, end)
+
+def null_basis_1d(nc, N, tol=1e-10):
+    """Orthonormal basis of null(D) for the periodic 1D weak gradient, by dense SVD.
+
+    The paper states that periodic pressures are defined up to weak solutions of dP = 0."""
+    D = grad_1d(nc, N).toarray()
+    _, s, vt = np.linalg.svd(D)
+    keep = s <= tol * s.max() if s.max() > 0 else np.ones_like(s, dtype=bool)
+    return vt[keep].T.copy()                      # columns
+
+
+def apply_along(mat, X, axis):
+    """Multiply tensor X by the (sparse or dense) matrix `mat` along `axis`."""
+    Xm = np.moveaxis(X, axis, 0)
+    shp = Xm.shape
+    Y = mat @ Xm.reshape(shp[0], -1)
+    Y = np.asarray(Y).reshape((mat.shape[0],) + shp[1:])
+    return np.moveaxis(Y, 0, axis)
+
+
+def project_null(grid, X, Zs):
+    """v <- v - Z Z^T v with Z = kron of the per-direction orthonormal bases Zs[d].
+
+    X is a tensor-layout array; returns the projected copy (range of A_p)."""
+    C = X
+    for d in range(grid.dim):
+        C = apply_along(Zs[d].T, C, grid.dim - 1 - d)
+    back = C
+    for d in range(grid.dim):
+        back = apply_along(Zs[d], back, grid.dim - 1 - d)
+    return X - back
+
+
+def apply_at(grid, X, index, alpha, beta):
+    """(alpha M^{xyz} + beta K) X evaluated at the tensor multi-indices `index` (array of shape
+    (m, dim), axes ordered (z,) y, x), from the block form of eq. (pSyst): along direction d the
+    output node l_d of cell i_d couples to the nodes of cells i_d-1, i_d, i_d+1 through the blocks
+    L, C, R, weighted by the GL masses of the other directions and h_d^-2. Periodic wrap.
+    Used to check single outputs of full-size applications without assembling the matrix."""
+    t = grid.tab
+    n = grid.n
+    X = np.asarray(X)
+    index = np.atleast_2d(np.asarray(index, dtype=np.int64))
+    out = np.zeros(index.shape[0])
+    for r, idx in enumerate(index):
+        g = [int(v) for v in idx]                       # tensor axes (z,) y, x
+        ld = {d: g[grid.dim - 1 - d] % n for d in range(grid.dim)}
+        wall = 1.0
+        for d in range(grid.dim):
+            wall *= t.w[ld[d]]
+        val = alpha * wall * X[tuple(g)]
+        for d in range(grid.dim):
+            ax = grid.dim - 1 - d
+            nc = grid.cells[d]
+            i = g[ax] // n
+            wperp = wall / t.w[ld[d]]
+            acc = 0.0
+            for off, blk in ((-1, t.Lblk), (0, t.Cblk), (1, t.Rblk)):
+                j = (i + off) % nc
+                for m in range(n):
+                    gg = list(g)
+                    gg[ax] = j * n + m
+                    acc += blk[ld[d], m] * X[tuple(gg)]
+            val += beta / grid.h[d] ** 2 * wperp * acc
+        out[r] = val
+    return out
