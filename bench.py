@@ -1,0 +1,194 @@
+"""Benchmark of the pressure-CG hot path on one MI355X.
+
+Workload (default): 2D periodic unit square, 256 x 256 main cells, degree N = 6 (3,211,264
+pressure DoFs), seeded random low-pass velocity (|k| <= 8, max |v| = 0.1), dt = 5e-4, nu = 1e-3,
+theta = 0.6. One "step" is one full semi-implicit fractional step (L2 projections, TVD-RK3
+convection, implicit viscous solves, divergence RHS, null-space projection, pressure CG to
+relative residual 1e-10, velocity update) on device-resident data.
+
+value = pressure DoFs x pressure-CG iterations / wall time of the timed steps (FP64 CG).
+The FP32-inner / FP64-refinement path is timed the same way on the same state and reported
+under "fp32_refine64". The roofline object covers the fused CG operator-apply kernel: its
+duration is measured with HIP events around every launch inside the timed pressure solves.
+The CPU baseline is the oracle's assembled-CSR CG timed in a 1-thread subprocess.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rand2d_256_N6|rand3d_64_N4]
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "pressure-CG DoF-iterations/s + HBM GB/s, FP64 vs FP32+FP64-refine at 1e-10"
+
+
+def initial_state(pd, ctx, cfg, torch):
+    import synthetic
+    xi, _ = pd.pd_nodes(ctx)
+    coords = synthetic.staggered_coords(cfg["cells"], cfg["lengths"], xi)
+    field = synthetic.FourierField(cfg["seed"], len(cfg["cells"]), cfg["kmax"], cfg["lengths"])
+    field.normalise(cfg["vmax"])
+    U = field.eval(coords)
+    n = cfg["N"] + 1
+    return [torch.tensor(synthetic.tensor_to_blocked(u, cfg["cells"], n), dtype=torch.float64,
+                         device="cuda") for u in U]
+
+
+def run_steps(pd, ctx, u, p, nsteps, torch):
+    iters, solves = 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        info = pd.pd_step(ctx, u, p)
+        if info[3]["status"] != pd.PD_OK:
+            raise RuntimeError(f"pressure solve failed: {info[3]}")
+        iters += info[3]["iters"]
+        solves.append(info)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, iters, solves
+
+
+def cpu_baseline(cfg, iters=40):
+    """Time the oracle (assembled CSR + plain CG loop) at the full workload size for a fixed number
+    of iterations in a subprocess limited to one thread."""
+    code = f"""
+import time, json, os, sys
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+from oracle.operators import Grid, pressure_operator
+from oracle.solvers import cg
+g = Grid({tuple(cfg['cells'])!r}, {tuple(cfg['lengths'])!r}, {cfg['N']})
+A = pressure_operator(g, {cfg['dt']})
+b = np.random.default_rng(0).standard_normal(g.ndof)
+t = time.perf_counter()
+cg(A, b, 1e-300, {iters})
+dt = time.perf_counter() - t
+print(json.dumps(dict(value=g.ndof * {iters} / dt, seconds=dt, cores=len(os.sched_getaffinity(0)))))
+"""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=600)
+    if out.returncode != 0:
+        return {"value": None, "unit": "DoF-iterations/s", "cores": 1, "kind": "oracle",
+                "sample": f"failed: {out.stderr[-300:]}"}
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": r["value"], "unit": "DoF-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} CG iterations of the assembled FP64 pressure matrix at the full "
+                      f"workload size ({cfg['cells']} cells, N={cfg['N']}), scipy CSR matvec + "
+                      f"numpy vector updates, 1 thread ({r['seconds']:.1f} s; host has "
+                      f"{r['cores']} cores available)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rand2d_256_N6")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the pressure path is measured on one "
+              "GPU's share); --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1602_05806_amd as pd
+    import synthetic
+
+    cfg = dict(synthetic.CONFIGS[args.workload])
+    cfg.setdefault("steps", 1)
+    dim = len(cfg["cells"])
+    ctx = pd.pd_setup(dim, cfg["cells"], cfg["lengths"], cfg["N"], cfg["dt"], cfg["theta"],
+                      cfg["nu"])
+    pd.pd_configure(ctx, pd.PD_CFG_P_RTOL, cfg["rtol"])
+    if args.workload.startswith("rand3d"):
+        pd.pd_configure(ctx, pd.PD_CFG_CONVECTION, 0)    # one pressure + viscous solve per step
+    u = initial_state(pd, ctx, cfg, torch)
+    p = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
+
+    results = {}
+    for prec_name, prec in (("fp64", pd.PD_FP64), ("fp32_refine64", pd.PD_FP32_REFINE64)):
+        pd.pd_configure(ctx, pd.PD_CFG_STEP_PREC, prec)
+        u_run = [x.clone() for x in u]
+        p_run = p.clone()
+        pd.pd_configure(ctx, pd.PD_CFG_TIMING, 0)
+        run_steps(pd, ctx, u_run, p_run, args.warmup, torch)
+        pd.pd_configure(ctx, pd.PD_CFG_TIMING, 1)
+        pd.pd_timing(ctx, pd.PD_FP64, reset=True)
+        pd.pd_timing(ctx, pd.PD_FP32, reset=True)
+        secs, iters, solves = run_steps(pd, ctx, u_run, p_run, args.steps, torch)
+        pd.pd_configure(ctx, pd.PD_CFG_TIMING, 0)
+        kt = pd.pd_timing(ctx, pd.PD_FP64 if prec == pd.PD_FP64 else pd.PD_FP32, reset=True)
+        psolve_ms = sum(s[3]["ms"] for s in solves)
+        results[prec_name] = dict(
+            seconds=secs, iters=iters, psolve_ms=psolve_ms,
+            outer=[s[3]["outer_iters"] for s in solves],
+            rel_res_true=max(s[3]["rel_res_true"] for s in solves),
+            visc_iters=[[s[d]["iters"] for d in range(dim)] for s in solves],
+            kernel=kt)
+        del u_run, p_run
+
+    r64, r32 = results["fp64"], results["fp32_refine64"]
+    ndof = ctx.ndof
+    value = ndof * r64["iters"] / r64["seconds"]
+    kt = r64["kernel"]
+    avg_ms = kt["total_ms"] / max(kt["launches"], 1)
+    achieved = kt["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if kt["launches"] else None
+    kt32 = r32["kernel"]
+    avg32 = kt32["total_ms"] / max(kt32["launches"], 1)
+    ach32 = kt32["bytes_per_launch"] / (avg32 * 1e-3) / 1e9 if kt32["launches"] else None
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DoF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r64["seconds"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": list(cfg["cells"]), "N": cfg["N"],
+                   "pressure_dofs": ndof, "dt": cfg["dt"], "nu": cfg["nu"],
+                   "theta": cfg["theta"], "rtol": cfg["rtol"],
+                   "step": "full fractional step" if not args.workload.startswith("rand3d")
+                   else "fractional step without convection"},
+        "pressure_iters_per_step": r64["iters"] / args.steps,
+        "pressure_solve_ms_per_step": r64["psolve_ms"] / args.steps,
+        "pressure_dof_it_per_s_solve_only": ndof * r64["iters"] / (r64["psolve_ms"] * 1e-3),
+        "algorithmic_gbs_cg": ndof * r64["iters"] * 80.0 / (r64["psolve_ms"] * 1e-3) / 1e9,
+        "rel_res_true_max": r64["rel_res_true"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": "k_apply (fused CG form, FP64)",
+                     "avg_launch_us": 1e3 * avg_ms, "launches": kt["launches"],
+                     "bytes_per_launch": kt["bytes_per_launch"]},
+        "fp32_refine64": {
+            "value": ndof * r32["iters"] / r32["seconds"], "unit": "DoF-iterations/s",
+            "ms_per_step": 1e3 * r32["seconds"] / args.steps,
+            "pressure_iters_per_step": r32["iters"] / args.steps,
+            "outer_iters": r32["outer"],
+            "pressure_solve_ms_per_step": r32["psolve_ms"] / args.steps,
+            "speedup_pressure_solve_vs_fp64": r64["psolve_ms"] / r32["psolve_ms"],
+            "rel_res_true_max": r32["rel_res_true"],
+            "apply_kernel": {"avg_launch_us": 1e3 * avg32, "achieved_gbs": ach32,
+                             "frac": (ach32 / HBM_PEAK_GBS) if ach32 else None,
+                             "bytes_per_launch": kt32["bytes_per_launch"]}},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    ctx.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

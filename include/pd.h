@@ -1,0 +1,164 @@
+/*
+ * pd.h -- C ABI of libpd, the MI355X (gfx950) pressure solver for the staggered spectral
+ * semi-implicit discontinuous Galerkin scheme of Fambri & Dumbser, "Spectral semi-implicit and
+ * space-time discontinuous Galerkin methods for the incompressible Navier-Stokes equations on
+ * staggered Cartesian grids", arXiv:1602.05806 (Section 2, "Spectral semi-implicit DG schemes on
+ * staggered Cartesian grids").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Grid. Uniform Cartesian grid with nx*ny(*nz) main cells of size h_d = len[d]/ncell[d],
+ *    periodic in every direction (periodic_mask must have one bit per dimension set). Main cell
+ *    i covers [i h, (i+1) h]; the dual cell i of a velocity component staggered along d covers
+ *    [(i+1/2) h, (i+3/2) h], i.e. it overlaps the right half of main cell i and the left half of
+ *    main cell i+1 (the edge-based staggering of Section 2.1 with the periodic wrap of eq. pSyst1d).
+ *  * DoF layout (element-blocked). A field is (N+1)^d nodal values per cell at the Gauss-Legendre
+ *    nodes of that cell. Flat index = cell * (N+1)^d + node, with cell = (k*ny + j)*nx + i and
+ *    node = (l3*(N+1) + l2)*(N+1) + l1 (x fastest in both). Pressure-like fields live on the main
+ *    grid; velocity component d lives on its own dual grid with the same index formula.
+ *  * Pointers. Every array argument is a DEVICE pointer owned by the caller, of PD_FP64 (double)
+ *    or PD_FP32 (float) elements as the call states; the library never frees caller memory.
+ *    Arrays may not alias unless a call says so.
+ *  * Streams. All work is enqueued on `hip_stream` (a hipStream_t; NULL = the null stream) and
+ *    returns without waiting, except where a call says it synchronises (solves read their
+ *    convergence information back).
+ *  * Errors. Negative PD_E* codes are returned, never thrown; pd_last_error() gives the message.
+ *    A context is not thread safe; use one context per stream.
+ */
+#ifndef PD_H
+#define PD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pd_ctx pd_ctx;
+
+/* Status codes. */
+enum {
+  PD_OK = 0,
+  PD_EINVAL = -1,      /* invalid argument or unsupported configuration                    */
+  PD_ENOMEM = -2,      /* device allocation failed                                           */
+  PD_EDEVICE = -3,     /* a HIP call failed (message holds the HIP error string)             */
+  PD_ENOCONV = -4,     /* maxit reached before the tolerance                                 */
+  PD_EBREAKDOWN = -5   /* CG breakdown: <p, A p> <= 0 or not finite (e.g. NaN in the RHS)   */
+};
+
+/* Precision of a call. PD_FP64: FP64 arrays and arithmetic. PD_FP32: FP32 arrays and arithmetic
+ * with FP64 dot-product accumulation (pd_apply only). PD_FP32_REFINE64: FP64 arrays at the
+ * boundary; the solve runs FP32 conjugate-gradient inner solves on the FP64 residual and
+ * accumulates the corrections in FP64 (iterative refinement), stopping on the FP64 residual. */
+enum { PD_FP64 = 0, PD_FP32 = 1, PD_FP32_REFINE64 = 2 };
+
+/* Operators. PD_OP_PRESSURE: A_p = dt * K with K = sum_d h_d^-2 (M on the other directions)
+ * (x) H_d and H_d = D_d^T M^-1 D_d the block-tridiagonal 1D operator with blocks L, C, R of
+ * eq. (pSyst) / (PerPrSyst); it acts on q = P^{n+theta} (eq. LOpressure). PD_OP_VISCOUS:
+ * A_v = M^{xyz} + nu dt K, the implicit-viscosity operator of eq. (implicitviscosity) with the
+ * dt and h factors of eqs. (uSDG12), (Ux) made explicit. Both are symmetric; A_v is positive
+ * definite, A_p positive semi-definite with null space Z = null of the weak gradient. */
+enum { PD_OP_PRESSURE = 0, PD_OP_VISCOUS = 1 };
+
+/* Per-solve report. iters: total CG iterations (inner iterations summed for refinement);
+ * outer_iters: refinement outer iterations (1 for PD_FP64); status: PD_OK / PD_ENOCONV /
+ * PD_EBREAKDOWN; rel_res_recur: final recurrence residual ||r||/||b||; rel_res_true: true FP64
+ * residual ||b - A x||/||b|| recomputed at exit; ms: wall time of the solve on the stream. */
+typedef struct {
+  int iters, outer_iters, status;
+  double rel_res_recur, rel_res_true, ms;
+} pd_solve_info;
+
+/* Create a context: computes the 1D tables of eq. (matrices), eq. (pSyst) and eq. (l2forward) in
+ * FP64 on the host for degree N (0 <= N <= 8), uploads FP64 and FP32 copies, and allocates the
+ * solver workspace. dim is 2 or 3; ncell[d] >= 1 and len[d] > 0 for d < dim; dt > 0;
+ * 0.5 <= theta <= 1 (theta of eq. uSDG1); nu >= 0. periodic_mask: bit d set = periodic along d;
+ * only fully periodic grids are supported (PD_EINVAL otherwise). On error *out is NULL and the
+ * message is available from pd_last_error(NULL). */
+int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int N,
+             double dt, double theta, double nu, unsigned periodic_mask, void* hip_stream);
+
+/* Release the context's device memory (waits for its stream). NULL is ignored. */
+void pd_destroy(pd_ctx* ctx);
+
+/* Last error message of ctx (or of the last failed pd_setup if ctx is NULL). Never NULL. */
+const char* pd_last_error(const pd_ctx* ctx);
+
+/* Sizes: number of main cells, DoFs per field (cells * (N+1)^dim) and dim. Host call. */
+int pd_sizes(const pd_ctx* ctx, long long* ncells, long long* ndof, int* dim);
+
+/* Copy the N+1 Gauss-Legendre nodes and weights on [0,1] used by ctx to host arrays. */
+int pd_nodes(const pd_ctx* ctx, double* xi, double* w);
+
+/* y = A x for op PD_OP_PRESSURE or PD_OP_VISCOUS; x, y: ndof elements of precision prec
+ * (PD_FP64 or PD_FP32). Matrix-free: tensor-product application of the 1D blocks along each
+ * direction (eq. tensorP1) with the diagonal Gauss-Legendre masses. */
+int pd_apply(pd_ctx* ctx, int op, int prec, const void* x, void* y, void* hip_stream);
+
+/* Solve A x = b with unpreconditioned conjugate gradients (the paper's matrix-free CG,
+ * Section 2.1). b, x: ndof FP64 arrays. x holds the initial guess on entry (set it to zero for
+ * the paper's choice) and the solution on exit. For PD_OP_PRESSURE, b is first projected onto
+ * range(A_p) (orthogonal complement of the null space of the weak gradient) and x is projected
+ * at exit, so the result is the minimum-norm solution. Stops when ||r||_2 <= rtol ||b||_2.
+ * prec: PD_FP64 or PD_FP32_REFINE64. Synchronises with the stream at exit; info may be NULL.
+ * Returns PD_OK, PD_ENOCONV (maxit reached) or PD_EBREAKDOWN. */
+int pd_cg_solve(pd_ctx* ctx, int op, int prec, const void* b, void* x, double rtol, int maxit,
+                pd_solve_info* info, void* hip_stream);
+
+/* b = sum_d B_d u_d with B_d = h_d^-1 (M on the other directions) (x) D_d^T: the right-hand
+ * side of eq. (LOpressure) from the dual velocity components u[0..dim-1] (FP64, dual layout).
+ * The discrete divergence of eq. (pSDG1) is -b. */
+int pd_rhs_div(pd_ctx* ctx, void* const u[3], void* b, void* hip_stream);
+
+/* Velocity update of eqs. (LOvelocityU)-(LOvelocityW): u_d -= dt h_d^-1 M_d^-1 D_d q for every
+ * direction d, with q = P^{n+theta} (FP64, main grid) and u[d] the FP64 dual components,
+ * updated in place. */
+int pd_project_velocity(pd_ctx* ctx, const void* q, void* const u[3], void* hip_stream);
+
+/* Null-space projection v <- v - Z Z^T v of an FP64 (prec = PD_FP64) or FP32 main-grid field,
+ * Z = orthonormal basis of null(A_p) (tensor products of the cell-periodic null vectors of the
+ * 1D weak gradient: 1 per direction for even N, 2 for odd N). In place. */
+int pd_project_null(pd_ctx* ctx, int prec, void* v, void* hip_stream);
+
+/* L2 projections between a dual grid and the main grid along direction d (eq. l2forward and
+ * eq. l2backward): dir = 0: main = pi_{*->#}(dual); dir = 1: dual = pi_{#->*}(main). FP64. */
+int pd_l2_project(pd_ctx* ctx, int d, int dir, const void* in, void* out, void* hip_stream);
+
+/* One explicit convection step of eqs. (Fu)-(Fw) on the main grid with the third-order TVD
+ * Runge-Kutta scheme: um[d] (FP64 main-grid velocity components) are replaced by the
+ * predicted Fu, Fv, Fw. Rusanov flux with s = 2 max(|v_e^-|, |v_e^+|) on faces normal to e. */
+int pd_convect(pd_ctx* ctx, void* const um[3], void* hip_stream);
+
+/* One semi-implicit fractional step (eqs. LOdiffusionU-LOvelocityW): u[d] = dual velocity
+ * components U^n (in) / U^{n+1} (out), p = P^n (in) / P^{n+1} (out), all FP64. info[0..dim-1]
+ * report the viscous solves, info[3] the pressure solve (info may be NULL). Synchronises.
+ * Solver settings come from pd_configure. */
+int pd_step(pd_ctx* ctx, void* const u[3], void* p, pd_solve_info info[4], void* hip_stream);
+
+/* Settings used by pd_step and the timing hooks (key, value):
+ *   PD_CFG_STEP_PREC     PD_FP64 (default) or PD_FP32_REFINE64 for the step's solves
+ *   PD_CFG_P_RTOL        pressure tolerance in pd_step (default 1e-10)
+ *   PD_CFG_V_RTOL        viscous tolerance in pd_step (default 1e-12)
+ *   PD_CFG_MAXIT         iteration cap for the step's solves (default 100000)
+ *   PD_CFG_CONVECTION    1 (default) = explicit convection on, 0 = off (unsteady Stokes step)
+ *   PD_CFG_INNER_RTOL    inner FP32 tolerance of the refinement (default 1e-4)
+ *   PD_CFG_TIMING        1 = record HIP events around every launch of the operator kernel
+ *                        inside solves (see pd_timing), 0 (default) = off
+ *   PD_CFG_CHECK_EVERY   convergence poll interval of the solve loop in iterations (default 32) */
+enum {
+  PD_CFG_STEP_PREC = 0, PD_CFG_P_RTOL = 1, PD_CFG_V_RTOL = 2, PD_CFG_MAXIT = 3,
+  PD_CFG_CONVECTION = 4, PD_CFG_INNER_RTOL = 5, PD_CFG_TIMING = 6, PD_CFG_CHECK_EVERY = 7
+};
+int pd_configure(pd_ctx* ctx, int key, double value);
+
+/* Timing hook: total milliseconds and launch count of the fused CG operator-apply kernel of
+ * precision prec (PD_FP64: FP64 solves; PD_FP32: inner solves of PD_FP32_REFINE64) launched inside
+ * pressure solves since the last reset (reset != 0 clears after reading). Each launch is
+ * bracketed by HIP events on the solve's stream; launches after convergence (early exits) are
+ * not counted. Requires PD_CFG_TIMING = 1. bytes_per_launch: algorithmic bytes of one launch
+ * (reads r and p_old, writes p and A p: 4 words per DoF). Synchronises with the last stream. */
+int pd_timing(pd_ctx* ctx, int prec, double* total_ms, long long* launches,
+              double* bytes_per_launch, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PD_H */

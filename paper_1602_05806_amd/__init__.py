@@ -1,0 +1,239 @@
+"""Python binding of libpd, the gfx950 pressure solver for the staggered spectral semi-implicit DG
+scheme of arXiv:1602.05806 (Section 2).
+
+Argument marshalling only: every function forwards device pointers of torch tensors and the
+current HIP stream to the C ABI declared in ``include/pd.h``; all arithmetic runs in the HIP
+kernels of ``libpd.so``. There is no CPU fallback: importing this package fails if the library
+has not been built (``python -c "import __graft_entry__ as g; g.build()"``).
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libpd.so not found at {LIB_PATH}: build the HIP library first "
+        "(make -C paper_1602_05806_amd/csrc, or __graft_entry__.build())")
+
+# torch is loaded first so that libpd binds to the HIP runtime torch already uses (both carry the
+# soname libamdhip64.so.7; loading libpd first would bring a second runtime into the process).
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes, precisions, operators, configuration keys (mirrors include/pd.h)
+PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ENOCONV, PD_EBREAKDOWN = 0, -1, -2, -3, -4, -5
+PD_FP64, PD_FP32, PD_FP32_REFINE64 = 0, 1, 2
+PD_OP_PRESSURE, PD_OP_VISCOUS = 0, 1
+(PD_CFG_STEP_PREC, PD_CFG_P_RTOL, PD_CFG_V_RTOL, PD_CFG_MAXIT, PD_CFG_CONVECTION,
+ PD_CFG_INNER_RTOL, PD_CFG_TIMING, PD_CFG_CHECK_EVERY) = range(8)
+
+EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "pd_apply",
+            "pd_cg_solve", "pd_rhs_div", "pd_project_velocity", "pd_project_null",
+            "pd_l2_project", "pd_convect", "pd_step", "pd_configure", "pd_timing"]
+
+
+class pd_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
+                ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_lib.pd_setup.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                          ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_double,
+                          ctypes.c_double, ctypes.c_double, ctypes.c_uint, _vp]
+_lib.pd_destroy.argtypes = [_vp]
+_lib.pd_destroy.restype = None
+_lib.pd_last_error.argtypes = [_vp]
+_lib.pd_last_error.restype = ctypes.c_char_p
+_lib.pd_sizes.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong),
+                          ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)]
+_lib.pd_nodes.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.pd_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+_lib.pd_cg_solve.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double,
+                             ctypes.c_int, ctypes.POINTER(pd_solve_info), _vp]
+_lib.pd_rhs_div.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _vp]
+_lib.pd_project_velocity.argtypes = [_vp, _vp, ctypes.POINTER(_vp), _vp]
+_lib.pd_project_null.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+_lib.pd_l2_project.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+_lib.pd_convect.argtypes = [_vp, ctypes.POINTER(_vp), _vp]
+_lib.pd_step.argtypes = [_vp, ctypes.POINTER(_vp), _vp, ctypes.POINTER(pd_solve_info), _vp]
+_lib.pd_configure.argtypes = [_vp, ctypes.c_int, ctypes.c_double]
+_lib.pd_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double),
+                           ctypes.c_int]
+
+
+class PdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libpd error {code}: {msg}")
+        self.code = code
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t, ndof=None, dtype=None):
+    """Device pointer of a contiguous CUDA tensor (validated against the expected size/dtype)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if ndof is not None and t.numel() != ndof:
+        raise ValueError(f"expected {ndof} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns one pd_ctx. Sizes: .ncells, .ndof, .dim; .N; nodes via pd_nodes()."""
+
+    def __init__(self, handle, dim, N):
+        self._h = handle
+        self.dim = dim
+        self.N = N
+        nc, nd, d = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+        _check(self, _lib.pd_sizes(self._h, ctypes.byref(nc), ctypes.byref(nd), ctypes.byref(d)))
+        self.ncells, self.ndof = nc.value, nd.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("context destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            _lib.pd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check(ctx, rc, allow=()):
+    if rc == PD_OK or rc in allow:
+        return rc
+    h = None if ctx is None else ctx._h
+    msg = _lib.pd_last_error(h)
+    raise PdError(rc, msg.decode() if msg else "")
+
+
+def pd_setup(dim, ncell, length, N, dt, theta, nu, periodic_mask=None, stream=None):
+    nc = (ctypes.c_int * 3)(*(list(ncell) + [1] * (3 - len(ncell))))
+    ln = (ctypes.c_double * 3)(*(list(length) + [1.0] * (3 - len(length))))
+    mask = (1 << dim) - 1 if periodic_mask is None else periodic_mask
+    h = ctypes.c_void_p()
+    rc = _lib.pd_setup(ctypes.byref(h), dim, nc, ln, int(N), float(dt), float(theta), float(nu),
+                       mask, ctypes.c_void_p(_stream(stream)))
+    if rc != PD_OK:
+        raise PdError(rc, _lib.pd_last_error(None).decode())
+    return Context(h, dim, int(N))
+
+
+def pd_destroy(ctx):
+    ctx.close()
+
+
+def pd_nodes(ctx):
+    n = ctx.N + 1
+    xi = (ctypes.c_double * n)()
+    w = (ctypes.c_double * n)()
+    _check(ctx, _lib.pd_nodes(ctx.handle, xi, w))
+    return list(xi), list(w)
+
+
+def _dtype(prec):
+    import torch
+    return torch.float32 if prec == PD_FP32 else torch.float64
+
+
+def pd_apply(ctx, op, prec, x, y, stream=None):
+    dt = _dtype(prec)
+    _check(ctx, _lib.pd_apply(ctx.handle, op, prec, _ptr(x, ctx.ndof, dt), _ptr(y, ctx.ndof, dt),
+                              ctypes.c_void_p(_stream(stream))))
+
+
+def pd_cg_solve(ctx, op, prec, b, x, rtol, maxit, stream=None):
+    """Returns the pd_solve_info as a dict; raises on invalid use or device errors.
+    Non-convergence / breakdown are reported through info['status']."""
+    import torch
+    info = pd_solve_info()
+    rc = _lib.pd_cg_solve(ctx.handle, op, prec, _ptr(b, ctx.ndof, torch.float64),
+                          _ptr(x, ctx.ndof, torch.float64), float(rtol), int(maxit),
+                          ctypes.byref(info), ctypes.c_void_p(_stream(stream)))
+    _check(ctx, rc, allow=(PD_ENOCONV, PD_EBREAKDOWN))
+    return info.as_dict()
+
+
+def _vec3(ctx, u):
+    import torch
+    arr = (ctypes.c_void_p * 3)()
+    for d in range(ctx.dim):
+        arr[d] = _ptr(u[d], ctx.ndof, torch.float64).value
+    return arr
+
+
+def pd_rhs_div(ctx, u, b, stream=None):
+    import torch
+    _check(ctx, _lib.pd_rhs_div(ctx.handle, _vec3(ctx, u), _ptr(b, ctx.ndof, torch.float64),
+                                ctypes.c_void_p(_stream(stream))))
+
+
+def pd_project_velocity(ctx, q, u, stream=None):
+    import torch
+    _check(ctx, _lib.pd_project_velocity(ctx.handle, _ptr(q, ctx.ndof, torch.float64),
+                                         _vec3(ctx, u), ctypes.c_void_p(_stream(stream))))
+
+
+def pd_project_null(ctx, prec, v, stream=None):
+    _check(ctx, _lib.pd_project_null(ctx.handle, prec, _ptr(v, ctx.ndof, _dtype(prec)),
+                                     ctypes.c_void_p(_stream(stream))))
+
+
+def pd_l2_project(ctx, d, direction, src, dst, stream=None):
+    import torch
+    _check(ctx, _lib.pd_l2_project(ctx.handle, d, direction, _ptr(src, ctx.ndof, torch.float64),
+                                   _ptr(dst, ctx.ndof, torch.float64),
+                                   ctypes.c_void_p(_stream(stream))))
+
+
+def pd_convect(ctx, um, stream=None):
+    _check(ctx, _lib.pd_convect(ctx.handle, _vec3(ctx, um), ctypes.c_void_p(_stream(stream))))
+
+
+def pd_step(ctx, u, p, stream=None):
+    """One fractional step in place on u (dual components) and p. Returns 4 solve-info dicts
+    (viscous x, y, z; pressure)."""
+    import torch
+    info = (pd_solve_info * 4)()
+    rc = _lib.pd_step(ctx.handle, _vec3(ctx, u), _ptr(p, ctx.ndof, torch.float64), info,
+                      ctypes.c_void_p(_stream(stream)))
+    _check(ctx, rc, allow=(PD_ENOCONV, PD_EBREAKDOWN))
+    return [i.as_dict() for i in info]
+
+
+def pd_configure(ctx, key, value):
+    _check(ctx, _lib.pd_configure(ctx.handle, int(key), float(value)))
+
+
+def pd_timing(ctx, prec, reset=True):
+    ms, cnt, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+    _check(ctx, _lib.pd_timing(ctx.handle, prec, ctypes.byref(ms), ctypes.byref(cnt),
+                               ctypes.byref(by), 1 if reset else 0))
+    return dict(total_ms=ms.value, launches=cnt.value, bytes_per_launch=by.value)

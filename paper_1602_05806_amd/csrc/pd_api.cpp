@@ -1,0 +1,781 @@
+// C-ABI of libpd: context set-up, matrix-free operator application, conjugate-gradient solves
+// (FP64 and FP32 inner solves with FP64 iterative refinement) and the semi-implicit fractional
+// step of arXiv:1602.05806 Section 2.1-2.3 (eqs. LOdiffusionU-LOvelocityW).
+#include "pd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pd_launch.h"
+#include "pd_tables.h"
+
+using pdk::CgState;
+
+struct pd_ctx {
+  int dim = 2, N = 0, n = 1, NC = 1;
+  int nc[3] = {1, 1, 1};
+  double len[3] = {1, 1, 1}, h[3] = {1, 1, 1};
+  double dt = 0, theta = 1, nu = 0;
+  long long ncells = 0, ndof = 0;
+  pdh::Table1D tab;
+  pdk::OpTables optab;
+  std::string err;
+  // settings
+  int step_prec = PD_FP64;
+  double p_rtol = 1e-10, v_rtol = 1e-12, inner_rtol = 1e-4;
+  int maxit = 100000, convection = 1, timing = 0, check_every = 32;
+  // device workspace
+  CgState* st = nullptr;       // CG state of the (inner) solve
+  CgState* st2 = nullptr;      // outer refinement / residual norms
+  double* rhopart = nullptr;   // 2 x stream-grid partials of <r, r> (iteration parity)
+  double* sigpart = nullptr;   // apply-grid partials of <p, A p>
+  double* tmppart = nullptr;   // partials of stand-alone reductions
+  double* null_part = nullptr;
+  double* null_corr = nullptr;
+  double *r64 = nullptr, *pa64 = nullptr, *pb64 = nullptr, *q64 = nullptr, *bw64 = nullptr;
+  float *r32 = nullptr, *pa32 = nullptr, *pb32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+  double* um[3] = {nullptr, nullptr, nullptr};
+  double* s1[3] = {nullptr, nullptr, nullptr};
+  double* s2[3] = {nullptr, nullptr, nullptr};
+  double* qbuf = nullptr;
+  CgState* hst = nullptr;      // pinned host mirror, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  std::vector<hipEvent_t> tev;
+  double t_ms[2] = {0, 0};
+  long long t_cnt[2] = {0, 0};
+  hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_setup_err;
+
+int fail(pd_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  else g_setup_err = m;
+  return code;
+}
+
+#define PD_HIP(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, PD_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+template <typename T>
+int dev_alloc(pd_ctx* c, T** p, size_t count) {
+  if (*p) return PD_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T) + 256);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(c, PD_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return PD_OK;
+}
+
+void op_coefs(const pd_ctx* c, int op, double* alpha, double coef[3]) {
+  const double beta = (op == PD_OP_PRESSURE) ? c->dt : c->nu * c->dt;
+  *alpha = (op == PD_OP_PRESSURE) ? 0.0 : 1.0;
+  for (int d = 0; d < 3; ++d) coef[d] = d < c->dim ? beta / (c->h[d] * c->h[d]) : 0.0;
+}
+
+pdk::ApplyLaunch base_launch(const pd_ctx* c, int op, bool fp32) {
+  pdk::ApplyLaunch L;
+  L.dim = c->dim;
+  L.N = c->N;
+  for (int d = 0; d < 3; ++d) L.nc[d] = c->nc[d];
+  L.fp32 = fp32;
+  op_coefs(c, op, &L.alpha, L.coef);
+  L.tab = &c->optab;
+  return L;
+}
+
+int plain_apply(pd_ctx* c, int op, bool fp32, const void* x, void* y, hipStream_t s) {
+  pdk::ApplyLaunch L = base_launch(c, op, fp32);
+  L.x = x;
+  L.y = y;
+  PD_HIP(c, pdk::launch_apply(L, s));
+  return PD_OK;
+}
+
+int project_null(pd_ctx* c, bool fp32, void* v, hipStream_t s) {
+  PD_HIP(c, pdk::launch_project_null(fp32, v, c->ncells, c->dim, c->n, c->tab.Pnull,
+                                     c->null_part, c->null_corr, s));
+  return PD_OK;
+}
+
+// <a, b> -> st->aux (FIN_AUX) or bnorm2/tol2 (FIN_BNORM), on the stream.
+int dot_into(pd_ctx* c, bool fp32, const void* a, const void* b, CgState* st, int fin,
+             hipStream_t s) {
+  PD_HIP(c, pdk::launch_dot(fp32, a, b, c->ndof, c->tmppart, s));
+  PD_HIP(c, pdk::launch_finalize(c->tmppart, (int)pdk::stream_grid(c->ndof), st, fin, s));
+  return PD_OK;
+}
+
+int read_state(pd_ctx* c, const CgState* dev, CgState* host, hipStream_t s) {
+  PD_HIP(c, hipMemcpyAsync(host, dev, sizeof(CgState), hipMemcpyDeviceToHost, s));
+  PD_HIP(c, hipStreamSynchronize(s));
+  return PD_OK;
+}
+
+// Conjugate gradients on A x = b in precision T (FP64 or FP32 vectors, FP64 scalars).
+//   r, pa, pb, q : workspace vectors; b may equal r when x_zero (then b is consumed).
+//   Returns PD_OK and fills iters/rel_recur/status from the device state.
+struct CgBuffers {
+  void *r, *pa, *pb, *q;
+};
+
+int run_cg(pd_ctx* c, int op, bool fp32, void* x, const void* b, bool x_zero, double rtol,
+           int maxit, CgState* st, CgBuffers B, hipStream_t s, bool timed, int* iters,
+           double* rel_recur, int* status) {
+  const long long n = c->ndof;
+  const int nrho = (int)pdk::stream_grid(n);
+  double* rho[2] = {c->rhopart, c->rhopart + pdk::kMaxStreamPartials};
+  PD_HIP(c, pdk::launch_state_init(st, maxit, rtol, s));
+  int rc = dot_into(c, fp32, b, b, st, pdk::FIN_BNORM, s);
+  if (rc) return rc;
+  // r_0 and the partials of <r_0, r_0> (iteration 0 reads them)
+  if (x_zero) {
+    if (b != B.r) {
+      if (fp32) return fail(c, PD_EINVAL, "internal: FP32 CG expects b == r");
+      PD_HIP(c, pdk::launch_residual((const double*)b, nullptr, (double*)B.r, n, rho[0], s));
+    } else {
+      PD_HIP(c, pdk::launch_dot(fp32, B.r, B.r, n, rho[0], s));
+    }
+  } else {
+    if (fp32) return fail(c, PD_EINVAL, "internal: FP32 CG needs a zero start");
+    rc = plain_apply(c, op, false, x, B.q, s);
+    if (rc) return rc;
+    PD_HIP(c, pdk::launch_residual((const double*)b, (const double*)B.q, (double*)B.r, n, rho[0], s));
+  }
+  PD_HIP(c, pdk::launch_zero(fp32, B.pa, n, s));
+
+  pdk::ApplyLaunch L = base_launch(c, op, fp32);
+  L.fuse = 1;
+  L.st = st;
+  L.nrho = nrho;
+  L.sigpart = c->sigpart;
+  const int nsig = (int)pdk::apply_blocks(L);
+  void* pold = B.pa;
+  void* pnew = B.pb;
+  const int chunk = c->check_every > 0 ? c->check_every : 32;
+  int slot = 0;
+  bool pending[2] = {false, false};
+  bool finished = false;
+  const int tslot = fp32 ? 1 : 0;
+  size_t nt = 0;
+  int k = 0;
+  while (!finished) {
+    for (int i = 0; i < chunk; ++i, ++k) {
+      L.k = k;
+      L.rho_cur = rho[k & 1];
+      L.x = B.r;
+      L.pold = pold;
+      L.pnew = pnew;
+      L.y = B.q;
+      if (timed) {
+        if (c->tev.size() < 2 * (nt + 1)) {
+          hipEvent_t e0, e1;
+          PD_HIP(c, hipEventCreate(&e0));
+          PD_HIP(c, hipEventCreate(&e1));
+          c->tev.push_back(e0);
+          c->tev.push_back(e1);
+        }
+        PD_HIP(c, hipEventRecord(c->tev[2 * nt], s));
+      }
+      PD_HIP(c, pdk::launch_apply(L, s));
+      if (timed) {
+        PD_HIP(c, hipEventRecord(c->tev[2 * nt + 1], s));
+        ++nt;
+      }
+      PD_HIP(c, pdk::launch_cg_update(fp32, x, pnew, B.q, B.r, n, st, k, c->sigpart, nsig,
+                                      rho[(k + 1) & 1], s));
+      void* t = pold;
+      pold = pnew;
+      pnew = t;
+    }
+    PD_HIP(c, hipMemcpyAsync(&c->hst[slot], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    PD_HIP(c, hipEventRecord(c->ev[slot], s));
+    pending[slot] = true;
+    const int prev = slot ^ 1;
+    if (pending[prev]) {
+      PD_HIP(c, hipEventSynchronize(c->ev[prev]));
+      pending[prev] = false;
+      if (c->hst[prev].done) finished = true;
+    }
+    slot ^= 1;
+    if (k > maxit + 2 * chunk) finished = true;
+  }
+  CgState fin;
+  rc = read_state(c, st, &fin, s);
+  if (rc) return rc;
+  *iters = fin.iter;
+  *rel_recur = fin.bnorm2 > 0 ? std::sqrt(fin.rho / fin.bnorm2) : 0.0;
+  *status = fin.done ? fin.status : PD_ENOCONV;
+  if (timed) {
+    const size_t use = (size_t)fin.iter < nt ? (size_t)fin.iter : nt;
+    for (size_t i = 0; i < use; ++i) {
+      float ms = 0.f;
+      PD_HIP(c, hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]));
+      c->t_ms[tslot] += ms;
+      c->t_cnt[tslot] += 1;
+    }
+  }
+  return PD_OK;
+}
+
+// ||b - A x|| / ||b|| in FP64 (uses q64, r64 and st2).
+int true_residual(pd_ctx* c, int op, const double* b, const double* x, double bnorm,
+                  hipStream_t s, double* rel) {
+  int rc = plain_apply(c, op, false, x, c->q64, s);
+  if (rc) return rc;
+  PD_HIP(c, pdk::launch_residual(b, c->q64, c->r64, c->ndof, c->tmppart, s));
+  PD_HIP(c, pdk::launch_finalize(c->tmppart, (int)pdk::stream_grid(c->ndof), c->st2, pdk::FIN_AUX, s));
+  CgState h;
+  rc = read_state(c, c->st2, &h, s);
+  if (rc) return rc;
+  *rel = bnorm > 0 ? std::sqrt(h.aux) / bnorm : std::sqrt(h.aux);
+  return PD_OK;
+}
+
+int solve(pd_ctx* c, int op, int prec, const double* b_in, double* x, double rtol, int maxit,
+          pd_solve_info* info, hipStream_t s) {
+  if (op != PD_OP_PRESSURE && op != PD_OP_VISCOUS) return fail(c, PD_EINVAL, "unknown operator");
+  if (prec != PD_FP64 && prec != PD_FP32_REFINE64)
+    return fail(c, PD_EINVAL, "pd_cg_solve precision must be PD_FP64 or PD_FP32_REFINE64");
+  if (!b_in || !x) return fail(c, PD_EINVAL, "null array");
+  if (!(rtol > 0.0)) return fail(c, PD_EINVAL, "rtol must be > 0");
+  if (maxit < 0) return fail(c, PD_EINVAL, "maxit must be >= 0");
+  c->last_stream = s;
+  const long long n = c->ndof;
+  PD_HIP(c, hipEventRecord(c->t0, s));
+  const double* b = b_in;
+  if (op == PD_OP_PRESSURE) {
+    PD_HIP(c, pdk::launch_axpby(1.0, b_in, 0.0, c->bw64, n, s));
+    int rc = project_null(c, false, c->bw64, s);
+    if (rc) return rc;
+    rc = project_null(c, false, x, s);
+    if (rc) return rc;
+    b = c->bw64;
+  }
+  const bool timed = c->timing && op == PD_OP_PRESSURE;
+  // ||b||
+  int rc = dot_into(c, false, b, b, c->st2, pdk::FIN_AUX, s);
+  if (rc) return rc;
+  CgState h;
+  rc = read_state(c, c->st2, &h, s);
+  if (rc) return rc;
+  const double bnorm = std::sqrt(h.aux);
+  pd_solve_info inf{};
+  inf.status = PD_OK;
+  if (bnorm == 0.0) {
+    PD_HIP(c, pdk::launch_zero(false, x, n, s));
+  } else if (prec == PD_FP64) {
+    CgBuffers B{c->r64, c->pa64, c->pb64, c->q64};
+    rc = run_cg(c, op, false, x, b, false, rtol, maxit, c->st, B, s, timed, &inf.iters,
+                &inf.rel_res_recur, &inf.status);
+    if (rc) return rc;
+    inf.outer_iters = 1;
+  } else {
+    CgBuffers B{c->r32, c->pa32, c->pb32, c->q32};
+    int total = 0, outer = 0;
+    double res = 0.0;
+    inf.status = PD_ENOCONV;
+    for (outer = 0; outer < 60; ++outer) {
+      rc = plain_apply(c, op, false, x, c->q64, s);
+      if (rc) return rc;
+      PD_HIP(c, pdk::launch_axpby(-1.0, c->q64, 0.0, c->r64, n, s));
+      PD_HIP(c, pdk::launch_axpby(1.0, b, 1.0, c->r64, n, s));
+      if (op == PD_OP_PRESSURE) {
+        rc = project_null(c, false, c->r64, s);
+        if (rc) return rc;
+      }
+      rc = dot_into(c, false, c->r64, c->r64, c->st2, pdk::FIN_AUX, s);
+      if (rc) return rc;
+      rc = read_state(c, c->st2, &h, s);
+      if (rc) return rc;
+      res = std::sqrt(h.aux) / bnorm;
+      if (!std::isfinite(res)) {
+        inf.status = PD_EBREAKDOWN;
+        break;
+      }
+      if (res <= rtol) {
+        inf.status = PD_OK;
+        break;
+      }
+      if (total >= maxit) {
+        inf.status = PD_ENOCONV;
+        break;
+      }
+      double tin = c->inner_rtol;
+      const double need = 0.3 * rtol / res;
+      if (need > tin) tin = need;
+      if (tin > 0.5) tin = 0.5;
+      PD_HIP(c, pdk::launch_to_f32_scaled(c->r64, c->r32, n, c->st2, s));
+      PD_HIP(c, pdk::launch_zero(true, c->d32, n, s));
+      int it = 0, st_in = 0;
+      double rr = 0;
+      rc = run_cg(c, op, true, c->d32, c->r32, true, tin, maxit - total, c->st, B, s, timed,
+                  &it, &rr, &st_in);
+      if (rc) return rc;
+      total += it;
+      PD_HIP(c, pdk::launch_add_f32_scaled(x, c->d32, n, c->st2, s));
+      if (st_in == PD_EBREAKDOWN) {
+        inf.status = PD_EBREAKDOWN;
+        break;
+      }
+    }
+    inf.iters = total;
+    inf.outer_iters = outer + 1;
+    inf.rel_res_recur = res;
+  }
+  if (op == PD_OP_PRESSURE) {
+    rc = project_null(c, false, x, s);
+    if (rc) return rc;
+  }
+  if (bnorm > 0.0) {
+    rc = true_residual(c, op, b, x, bnorm, s, &inf.rel_res_true);
+    if (rc) return rc;
+  }
+  PD_HIP(c, hipEventRecord(c->t1, s));
+  PD_HIP(c, hipEventSynchronize(c->t1));
+  float ms = 0.f;
+  PD_HIP(c, hipEventElapsedTime(&ms, c->t0, c->t1));
+  inf.ms = ms;
+  if (info) *info = inf;
+  return inf.status;
+}
+
+void fill_line_common(const pd_ctx* c, pdk::LineLaunch* L) {
+  L->dim = c->dim;
+  L->N = c->N;
+  for (int d = 0; d < 3; ++d) L->nc[d] = c->nc[d];
+  for (int i = 0; i < 9; ++i) L->w[i] = i < c->n ? c->tab.w[i] : 0.0;
+}
+
+// pi_{*->#} (dir 0) or pi_{#->*} (dir 1) along d.
+int l2_project(pd_ctx* c, int d, int dir, const double* in, double* out, hipStream_t s) {
+  pdk::LineLaunch L;
+  fill_line_common(c, &L);
+  const int n = c->n;
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      L.A0[p * n + q] = c->tab.ML[p * n + q] / c->tab.w[p];
+      L.A1[p * n + q] = c->tab.MR[p * n + q] / c->tab.w[p];
+    }
+  L.d = d;
+  if (dir == 0) {      // eq. (l2forward): U#_i = M^-1 (M^L U*_{i-1} + M^R U*_i)
+    L.o0 = -1;
+    L.o1 = 0;
+  } else {             // eq. (l2backward): U*_i = M^-1 (M^L U#_i + M^R U#_{i+1})
+    L.o0 = 0;
+    L.o1 = 1;
+  }
+  L.coef = 1.0;
+  L.in = in;
+  L.out = out;
+  PD_HIP(c, pdk::launch_line(L, s));
+  return PD_OK;
+}
+
+// b = sum_d h_d^-1 W_perp (R~^T u_d[i-1] - L~^T u_d[i])
+int rhs_div(pd_ctx* c, void* const u[3], double* b, hipStream_t s) {
+  const int n = c->n;
+  for (int d = 0; d < c->dim; ++d) {
+    if (!u[d]) return fail(c, PD_EINVAL, "null velocity component");
+    pdk::LineLaunch L;
+    fill_line_common(c, &L);
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) {
+        L.A0[p * n + q] = c->tab.Rt[q * n + p];
+        L.A1[p * n + q] = -c->tab.Lt[q * n + p];
+      }
+    L.d = d;
+    L.o0 = -1;
+    L.o1 = 0;
+    L.coef = 1.0 / c->h[d];
+    L.wperp = 1;
+    L.accum = d == 0 ? 0.0 : 1.0;
+    L.in = (const double*)u[d];
+    L.out = b;
+    PD_HIP(c, pdk::launch_line(L, s));
+  }
+  return PD_OK;
+}
+
+// u_d -= dt/h_d M^-1 (R~ q[i+1] - L~ q[i])
+int project_velocity(pd_ctx* c, const double* q, void* const u[3], hipStream_t s) {
+  const int n = c->n;
+  for (int d = 0; d < c->dim; ++d) {
+    if (!u[d]) return fail(c, PD_EINVAL, "null velocity component");
+    pdk::LineLaunch L;
+    fill_line_common(c, &L);
+    for (int p = 0; p < n; ++p)
+      for (int r = 0; r < n; ++r) {
+        L.A0[p * n + r] = c->tab.Rt[p * n + r] / c->tab.w[p];
+        L.A1[p * n + r] = -c->tab.Lt[p * n + r] / c->tab.w[p];
+      }
+    L.d = d;
+    L.o0 = 1;
+    L.o1 = 0;
+    L.coef = -c->dt / c->h[d];
+    L.accum = 1.0;
+    L.in = q;
+    L.out = (double*)u[d];
+    PD_HIP(c, pdk::launch_line(L, s));
+  }
+  return PD_OK;
+}
+
+int ensure_step_buffers(pd_ctx* c) {
+  const size_t n = (size_t)c->ndof;
+  for (int d = 0; d < c->dim; ++d) {
+    int rc;
+    if ((rc = dev_alloc(c, &c->um[d], n))) return rc;
+    if ((rc = dev_alloc(c, &c->s1[d], n))) return rc;
+    if ((rc = dev_alloc(c, &c->s2[d], n))) return rc;
+  }
+  return dev_alloc(c, &c->qbuf, n);
+}
+
+int convect(pd_ctx* c, double* const um[3], hipStream_t s) {
+  pdk::ConvLaunch L;
+  L.dim = c->dim;
+  L.N = c->N;
+  for (int d = 0; d < 3; ++d) {
+    L.nc[d] = c->nc[d];
+    L.h[d] = c->h[d];
+  }
+  const int n = c->n;
+  for (int i = 0; i < 9; ++i) {
+    L.w[i] = i < n ? c->tab.w[i] : 0;
+    L.phi0[i] = i < n ? c->tab.phi0[i] : 0;
+    L.phi1[i] = i < n ? c->tab.phi1[i] : 0;
+  }
+  for (int i = 0; i < 81; ++i) L.Kv[i] = i < n * n ? c->tab.Kv[i] : 0;
+  L.dt = c->dt;
+  // Shu-Osher TVD RK3: U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
+  //                    U  = 1/3 U + 2/3 (U2 + dt L(U2))
+  for (int d = 0; d < c->dim; ++d) {
+    L.ucur[d] = um[d];
+    L.u0[d] = um[d];
+    L.out[d] = c->s1[d];
+  }
+  L.a = 0.0;
+  L.b = 1.0;
+  PD_HIP(c, pdk::launch_convect_stage(L, s));
+  for (int d = 0; d < c->dim; ++d) {
+    L.ucur[d] = c->s1[d];
+    L.out[d] = c->s2[d];
+  }
+  L.a = 0.75;
+  L.b = 0.25;
+  PD_HIP(c, pdk::launch_convect_stage(L, s));
+  for (int d = 0; d < c->dim; ++d) {
+    L.ucur[d] = c->s2[d];
+    L.out[d] = um[d];
+  }
+  L.a = 1.0 / 3.0;
+  L.b = 2.0 / 3.0;
+  PD_HIP(c, pdk::launch_convect_stage(L, s));
+  return PD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int N, double dt,
+             double theta, double nu, unsigned periodic_mask, void* hip_stream) {
+  if (!out) return fail(nullptr, PD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return fail(nullptr, PD_EINVAL, "dim must be 2 or 3");
+  if (!ncell || !len) return fail(nullptr, PD_EINVAL, "ncell/len is NULL");
+  for (int d = 0; d < dim; ++d) {
+    if (ncell[d] < 1) return fail(nullptr, PD_EINVAL, "ncell[d] must be >= 1");
+    if (!(len[d] > 0.0)) return fail(nullptr, PD_EINVAL, "len[d] must be > 0");
+  }
+  if (!(dt > 0.0)) return fail(nullptr, PD_EINVAL, "dt must be > 0");
+  if (!(theta >= 0.5 && theta <= 1.0)) return fail(nullptr, PD_EINVAL, "theta must be in [0.5, 1]");
+  if (!(nu >= 0.0)) return fail(nullptr, PD_EINVAL, "nu must be >= 0");
+  const unsigned need = (1u << dim) - 1u;
+  if ((periodic_mask & need) != need)
+    return fail(nullptr, PD_EINVAL, "only fully periodic grids are supported");
+  pd_ctx* c = new pd_ctx();
+  std::string e;
+  if (!pdh::build_table(N, &c->tab, &e)) {
+    delete c;
+    return fail(nullptr, PD_EINVAL, e);
+  }
+  c->dim = dim;
+  c->N = N;
+  c->n = N + 1;
+  c->NC = dim == 3 ? c->n * c->n * c->n : c->n * c->n;
+  c->ncells = 1;
+  for (int d = 0; d < dim; ++d) {
+    c->nc[d] = ncell[d];
+    c->len[d] = len[d];
+    c->h[d] = len[d] / ncell[d];
+    c->ncells *= ncell[d];
+  }
+  c->ndof = c->ncells * c->NC;
+  if (c->ncells > (1LL << 31) / 2) {
+    delete c;
+    return fail(nullptr, PD_EINVAL, "grid too large");
+  }
+  c->dt = dt;
+  c->theta = theta;
+  c->nu = nu;
+  for (int i = 0; i < c->n * c->n; ++i) {
+    c->optab.L[i] = c->tab.Lb[i];
+    c->optab.C[i] = c->tab.Cb[i];
+    c->optab.R[i] = c->tab.Rb[i];
+  }
+  for (int i = 0; i < c->n; ++i) c->optab.w[i] = c->tab.w[i];
+  const size_t n = (size_t)c->ndof;
+  int rc = PD_OK;
+  if ((rc = dev_alloc(c, &c->st, 1)) || (rc = dev_alloc(c, &c->st2, 1)) ||
+      (rc = dev_alloc(c, &c->rhopart, 2 * (size_t)pdk::kMaxStreamPartials)) ||
+      (rc = dev_alloc(c, &c->sigpart, pdk::kMaxPartials)) ||
+      (rc = dev_alloc(c, &c->tmppart, pdk::kMaxStreamPartials)) ||
+      (rc = dev_alloc(c, &c->null_part, (size_t)256 * c->NC)) ||
+      (rc = dev_alloc(c, &c->null_corr, (size_t)c->NC)) || (rc = dev_alloc(c, &c->r64, n)) ||
+      (rc = dev_alloc(c, &c->pa64, n)) || (rc = dev_alloc(c, &c->pb64, n)) ||
+      (rc = dev_alloc(c, &c->q64, n)) || (rc = dev_alloc(c, &c->bw64, n)) ||
+      (rc = dev_alloc(c, &c->r32, n)) || (rc = dev_alloc(c, &c->pa32, n)) ||
+      (rc = dev_alloc(c, &c->pb32, n)) || (rc = dev_alloc(c, &c->q32, n)) ||
+      (rc = dev_alloc(c, &c->d32, n))) {
+    g_setup_err = c->err;
+    pd_destroy(c);
+    return rc;
+  }
+  hipStream_t s = S(hip_stream);
+  hipError_t he = hipHostMalloc((void**)&c->hst, 2 * sizeof(CgState), hipHostMallocDefault);
+  if (he == hipSuccess) he = hipEventCreate(&c->ev[0]);
+  if (he == hipSuccess) he = hipEventCreate(&c->ev[1]);
+  if (he == hipSuccess) he = hipEventCreate(&c->t0);
+  if (he == hipSuccess) he = hipEventCreate(&c->t1);
+  if (he == hipSuccess) he = hipMemsetAsync(c->st, 0, sizeof(CgState), s);
+  if (he == hipSuccess) he = hipMemsetAsync(c->st2, 0, sizeof(CgState), s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) {
+    g_setup_err = std::string("setup: ") + hipGetErrorString(he);
+    pd_destroy(c);
+    return PD_EDEVICE;
+  }
+  c->last_stream = s;
+  *out = c;
+  return PD_OK;
+}
+
+void pd_destroy(pd_ctx* c) {
+  if (!c) return;
+  if (c->last_stream) (void)hipStreamSynchronize(c->last_stream);
+  (void)hipDeviceSynchronize();
+  void* bufs[] = {c->st, c->st2, c->rhopart, c->sigpart, c->tmppart, c->null_part, c->null_corr,
+                  c->r64, c->pa64, c->pb64, c->q64, c->bw64, c->r32, c->pa32, c->pb32, c->q32,
+                  c->d32, c->qbuf};
+  for (void* p : bufs)
+    if (p) (void)hipFree(p);
+  for (int d = 0; d < 3; ++d) {
+    if (c->um[d]) (void)hipFree(c->um[d]);
+    if (c->s1[d]) (void)hipFree(c->s1[d]);
+    if (c->s2[d]) (void)hipFree(c->s2[d]);
+  }
+  if (c->hst) (void)hipHostFree(c->hst);
+  for (int i = 0; i < 2; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->t0) (void)hipEventDestroy(c->t0);
+  if (c->t1) (void)hipEventDestroy(c->t1);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* pd_last_error(const pd_ctx* c) { return c ? c->err.c_str() : g_setup_err.c_str(); }
+
+int pd_sizes(const pd_ctx* c, long long* ncells, long long* ndof, int* dim) {
+  if (!c) return PD_EINVAL;
+  if (ncells) *ncells = c->ncells;
+  if (ndof) *ndof = c->ndof;
+  if (dim) *dim = c->dim;
+  return PD_OK;
+}
+
+int pd_nodes(const pd_ctx* c, double* xi, double* w) {
+  if (!c) return PD_EINVAL;
+  for (int i = 0; i < c->n; ++i) {
+    if (xi) xi[i] = c->tab.xi[i];
+    if (w) w[i] = c->tab.w[i];
+  }
+  return PD_OK;
+}
+
+int pd_apply(pd_ctx* c, int op, int prec, const void* x, void* y, void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (op != PD_OP_PRESSURE && op != PD_OP_VISCOUS) return fail(c, PD_EINVAL, "unknown operator");
+  if (prec != PD_FP64 && prec != PD_FP32) return fail(c, PD_EINVAL, "pd_apply: prec must be PD_FP64 or PD_FP32");
+  if (!x || !y) return fail(c, PD_EINVAL, "null array");
+  if (x == y) return fail(c, PD_EINVAL, "x and y must not alias");
+  c->last_stream = S(hip_stream);
+  return plain_apply(c, op, prec == PD_FP32, x, y, S(hip_stream));
+}
+
+int pd_cg_solve(pd_ctx* c, int op, int prec, const void* b, void* x, double rtol, int maxit,
+                pd_solve_info* info, void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  return solve(c, op, prec, (const double*)b, (double*)x, rtol, maxit, info, S(hip_stream));
+}
+
+int pd_rhs_div(pd_ctx* c, void* const u[3], void* b, void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!u || !b) return fail(c, PD_EINVAL, "null array");
+  c->last_stream = S(hip_stream);
+  return rhs_div(c, u, (double*)b, S(hip_stream));
+}
+
+int pd_project_velocity(pd_ctx* c, const void* q, void* const u[3], void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!q || !u) return fail(c, PD_EINVAL, "null array");
+  c->last_stream = S(hip_stream);
+  return project_velocity(c, (const double*)q, u, S(hip_stream));
+}
+
+int pd_project_null(pd_ctx* c, int prec, void* v, void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!v) return fail(c, PD_EINVAL, "null array");
+  if (prec != PD_FP64 && prec != PD_FP32) return fail(c, PD_EINVAL, "prec must be PD_FP64 or PD_FP32");
+  c->last_stream = S(hip_stream);
+  return project_null(c, prec == PD_FP32, v, S(hip_stream));
+}
+
+int pd_l2_project(pd_ctx* c, int d, int dir, const void* in, void* out, void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (d < 0 || d >= c->dim || (dir != 0 && dir != 1)) return fail(c, PD_EINVAL, "bad direction");
+  if (!in || !out || in == out) return fail(c, PD_EINVAL, "null or aliased array");
+  c->last_stream = S(hip_stream);
+  return l2_project(c, d, dir, (const double*)in, (double*)out, S(hip_stream));
+}
+
+int pd_convect(pd_ctx* c, void* const um[3], void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!um) return fail(c, PD_EINVAL, "null array");
+  for (int d = 0; d < c->dim; ++d)
+    if (!um[d]) return fail(c, PD_EINVAL, "null velocity component");
+  int rc = ensure_step_buffers(c);
+  if (rc) return rc;
+  c->last_stream = S(hip_stream);
+  double* m[3] = {(double*)um[0], (double*)um[1], c->dim == 3 ? (double*)um[2] : nullptr};
+  return convect(c, m, S(hip_stream));
+}
+
+int pd_step(pd_ctx* c, void* const u[3], void* p, pd_solve_info info[4], void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!u || !p) return fail(c, PD_EINVAL, "null array");
+  for (int d = 0; d < c->dim; ++d)
+    if (!u[d]) return fail(c, PD_EINVAL, "null velocity component");
+  int rc = ensure_step_buffers(c);
+  if (rc) return rc;
+  hipStream_t s = S(hip_stream);
+  c->last_stream = s;
+  const long long n = c->ndof;
+  pd_solve_info loc[4];
+  std::memset(loc, 0, sizeof(loc));
+  // 1. pi_{*->#}
+  for (int d = 0; d < c->dim; ++d)
+    if ((rc = l2_project(c, d, 0, (const double*)u[d], c->um[d], s))) return rc;
+  // 2. explicit convection (TVD RK3)
+  if (c->convection)
+    if ((rc = convect(c, c->um, s))) return rc;
+  // 3. implicit viscosity on the main grid: (M + nu dt K) U = M F, initial guess F
+  if (c->nu > 0.0) {
+    for (int d = 0; d < c->dim; ++d) {
+      PD_HIP(c, pdk::launch_mass(c->dim, c->N, c->tab.w, c->um[d], c->s1[d], c->ncells, s));
+      rc = solve(c, PD_OP_VISCOUS, c->step_prec, c->s1[d], c->um[d], c->v_rtol, c->maxit, &loc[d], s);
+      if (rc != PD_OK) {
+        if (info) std::memcpy(info, loc, sizeof(loc));
+        return rc;
+      }
+    }
+  }
+  // 4. pi_{#->*}
+  for (int d = 0; d < c->dim; ++d)
+    if ((rc = l2_project(c, d, 1, c->um[d], (double*)u[d], s))) return rc;
+  // 5. b = sum_d B_d U*_d, pressure solve for q = P^{n+theta} from q = 0
+  if ((rc = rhs_div(c, u, c->s2[0], s))) return rc;
+  PD_HIP(c, pdk::launch_zero(false, c->qbuf, n, s));
+  rc = solve(c, PD_OP_PRESSURE, c->step_prec, c->s2[0], c->qbuf, c->p_rtol, c->maxit, &loc[3], s);
+  if (info) std::memcpy(info, loc, sizeof(loc));
+  if (rc != PD_OK) return rc;
+  // 6. velocity update, 7. P^{n+1} = (q - (1-theta) P^n) / theta
+  if ((rc = project_velocity(c, c->qbuf, u, s))) return rc;
+  PD_HIP(c, pdk::launch_axpby(1.0 / c->theta, c->qbuf, -(1.0 - c->theta) / c->theta, (double*)p, n, s));
+  PD_HIP(c, hipStreamSynchronize(s));
+  return PD_OK;
+}
+
+int pd_configure(pd_ctx* c, int key, double v) {
+  if (!c) return PD_EINVAL;
+  switch (key) {
+    case PD_CFG_STEP_PREC:
+      if (v != PD_FP64 && v != PD_FP32_REFINE64) return fail(c, PD_EINVAL, "bad step precision");
+      c->step_prec = (int)v;
+      break;
+    case PD_CFG_P_RTOL:
+      if (!(v > 0)) return fail(c, PD_EINVAL, "rtol must be > 0");
+      c->p_rtol = v;
+      break;
+    case PD_CFG_V_RTOL:
+      if (!(v > 0)) return fail(c, PD_EINVAL, "rtol must be > 0");
+      c->v_rtol = v;
+      break;
+    case PD_CFG_MAXIT:
+      if (!(v >= 0)) return fail(c, PD_EINVAL, "maxit must be >= 0");
+      c->maxit = (int)v;
+      break;
+    case PD_CFG_CONVECTION:
+      c->convection = v != 0.0;
+      break;
+    case PD_CFG_INNER_RTOL:
+      if (!(v > 0 && v < 1)) return fail(c, PD_EINVAL, "inner rtol must be in (0, 1)");
+      c->inner_rtol = v;
+      break;
+    case PD_CFG_TIMING:
+      c->timing = v != 0.0;
+      break;
+    case PD_CFG_CHECK_EVERY:
+      if (!(v >= 1)) return fail(c, PD_EINVAL, "check interval must be >= 1");
+      c->check_every = (int)v;
+      break;
+    default:
+      return fail(c, PD_EINVAL, "unknown configuration key");
+  }
+  return PD_OK;
+}
+
+int pd_timing(pd_ctx* c, int prec, double* total_ms, long long* launches,
+              double* bytes_per_launch, int reset) {
+  if (!c) return PD_EINVAL;
+  if (prec != PD_FP64 && prec != PD_FP32) return fail(c, PD_EINVAL, "prec must be PD_FP64 or PD_FP32");
+  if (c->last_stream) PD_HIP(c, hipStreamSynchronize(c->last_stream));
+  const int k = prec == PD_FP32 ? 1 : 0;
+  if (total_ms) *total_ms = c->t_ms[k];
+  if (launches) *launches = c->t_cnt[k];
+  // fused CG apply: reads r and p_old, writes p and A p (4 words per DoF)
+  if (bytes_per_launch) *bytes_per_launch = 4.0 * (double)c->ndof * (k ? 4.0 : 8.0);
+  if (reset) {
+    c->t_ms[k] = 0;
+    c->t_cnt[k] = 0;
+  }
+  return PD_OK;
+}
+
+}  // extern "C"

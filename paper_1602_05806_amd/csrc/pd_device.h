@@ -1,0 +1,127 @@
+// Device-side shared definitions of libpd (gfx950): parameter blocks passed by value to the
+// kernels, the device-resident CG scalar state and the deterministic block / grid reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdk {
+
+constexpr int kBlock = 256;          // threads of the streaming kernels
+constexpr int kMaxPartials = 1 << 16;        // blocks of one operator-apply launch
+constexpr int kMaxStreamPartials = 1024;     // blocks of one streaming-kernel launch
+constexpr int kMaxNC = 729;          // (N+1)^3 for N = 8
+
+// 1D blocks of the operator of eq. (pSyst) for degree N in precision T, passed as a kernel
+// argument so that every (uniform) table access is a scalar load from the kernarg segment.
+template <typename T, int N>
+struct Blk {
+  T L[(N + 1) * (N + 1)];   // couples cell i to cell i-1
+  T C[(N + 1) * (N + 1)];   // diagonal block
+  T R[(N + 1) * (N + 1)];   // couples cell i to cell i+1
+  T w[N + 1];               // GL weights (1D mass diagonal)
+};
+
+// Device-resident scalars of one CG solve. Kernels never synchronise across blocks inside a
+// launch: a kernel writes one partial sum per block (plain stores), and every block of the NEXT
+// kernel re-sums those partials in block order (kernel boundaries make them visible; the fixed
+// order keeps every block's scalar bit-identical and the whole solve deterministic). Block 0
+// mirrors the scalars here for the host (convergence polling) and for later kernels.
+struct CgState {
+  double rho_hist[2];  // rho_k kept in slot k % 2 by block 0 of apply k (rho_{k-1} for apply k)
+  double rho;        // <r_k, r_k> of the current iterate (written by block 0 of the apply)
+  double sigma;      // <p_k, A p_k>
+  double alpha;      // rho / sigma
+  double beta;       // rho_k / rho_{k-1}
+  double bnorm2;     // <b, b>
+  double tol2;       // (rtol ||b||)^2
+  double aux;        // scalar result of a stand-alone reduction (FIN_AUX), rtol input of FIN_BNORM
+  int iter;          // iterations completed when done
+  int maxit;
+  int done;          // 1 once converged, out of iterations or broken down
+  int status;        // 0 ok, -4 no convergence, -5 breakdown
+  int pad[2];
+};
+
+// Finalizers of the stand-alone reductions (dot kernel + single-block finalize kernel).
+enum Finalize : int {
+  FIN_BNORM = 3,     // sum = <b, b>: bnorm2 = sum, tol2 = aux^2 * sum (aux holds rtol)
+  FIN_AUX = 4        // sum stored in aux
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block in a fixed order; the result is returned to EVERY thread.
+template <int NT>
+__device__ __forceinline__ double block_sum_all(double v) {
+  __shared__ double red[(NT + 63) / 64];
+  __shared__ double tot;
+  __syncthreads();
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < (NT + 63) / 64; ++i) s += red[i];
+    tot = s;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// Fixed-order sum of `n` partials written by a previous kernel; result in every thread.
+template <int NT>
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) s += part[i];
+  return block_sum_all<NT>(s);
+}
+
+// Scalars of CG iteration k shared by the apply kernel of that iteration: rho_k from the
+// partials of <r_k, r_k>, the stop decision, and beta_k = rho_k / rho_{k-1}.
+struct IterScalars {
+  double rho, beta;
+  bool stop;
+};
+
+template <int NT>
+__device__ __forceinline__ IterScalars iteration_scalars(CgState* st, int k,
+                                                         const double* rho_cur, int nrho) {
+  IterScalars r;
+  r.rho = sum_partials<NT>(rho_cur, nrho);
+  const double rho_old = k > 0 ? st->rho_hist[(k + 1) & 1] : 0.0;
+  r.beta = k > 0 ? r.rho / rho_old : 0.0;
+  int status = 1;                               // 1 = keep iterating
+  if (!isfinite(r.rho)) status = -5;
+  else if (r.rho <= st->tol2) status = 0;
+  else if (k >= st->maxit) status = -4;
+  r.stop = status != 1;
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->rho_hist[k & 1] = r.rho;
+    st->rho = r.rho;
+    st->beta = r.beta;
+    st->iter = k;
+    if (r.stop) {
+      st->status = status;
+      st->done = 1;
+    }
+  }
+  return r;
+}
+
+// Map the hardware block index to a logical tile so that each XCD (blocks are dispatched to
+// the 8 XCDs round-robin) processes one contiguous range of tiles, keeping neighbouring tiles
+// (whose halos overlap) in the same L2.
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned G) {
+  const unsigned q = G / 8u, r = G % 8u;
+  const unsigned x = b % 8u, idx = b / 8u;
+  const unsigned start = (x < r) ? x * (q + 1u) : r * (q + 1u) + (x - r) * q;
+  return start + idx;
+}
+
+}  // namespace pdk

@@ -1,0 +1,105 @@
+// Host-side launch descriptors shared by the kernel translation units and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pd_device.h"
+
+namespace pdk {
+
+// FP64 copies of the 1D tables a launch needs (converted to the kernel precision at launch).
+struct OpTables {
+  double L[81], C[81], R[81], w[9];
+};
+
+struct ApplyLaunch {
+  int dim = 2, N = 0;
+  int nc[3] = {1, 1, 1};
+  bool fp32 = false;
+  int fuse = 0;              // 1: CG iteration form (p = r + beta p_old; sigma partials)
+  const void* x = nullptr;   // operand (fuse = 0) or r (fuse = 1)
+  const void* pold = nullptr;
+  void* pnew = nullptr;
+  void* y = nullptr;
+  double alpha = 0.0;
+  double coef[3] = {0, 0, 0};
+  // fuse = 1 only: CG state, iteration index, partials of rho_k, sigma partials out
+  CgState* st = nullptr;
+  int k = 0;
+  const double* rho_cur = nullptr;
+  int nrho = 0;
+  double* sigpart = nullptr;
+  int kz_override = 0;
+  const OpTables* tab = nullptr;
+};
+
+hipError_t launch_apply(const ApplyLaunch& L, hipStream_t s);
+// number of blocks (= partials) the apply kernel launches for this shape
+unsigned apply_blocks(const ApplyLaunch& L);
+
+// ---- streaming vector kernels (pd_vec.hip). Reductions write one partial per block; the
+// consumer (next kernel or the single-block finalize) re-sums them in block order.
+unsigned stream_grid(long long n);   // blocks (= partials) of every streaming kernel of length n
+hipError_t launch_dot(bool fp32, const void* a, const void* b, long long n, double* partials,
+                      hipStream_t s);
+hipError_t launch_finalize(const double* partials, int nparts, CgState* st, int fin,
+                           hipStream_t s);
+// CG iteration k, second half (see k_cg_update)
+hipError_t launch_cg_update(bool fp32, void* x, const void* p, const void* q, void* r,
+                            long long n, CgState* st, int k, const double* sigpart, int nsig,
+                            double* rho_next, hipStream_t s);
+// r = b - q (q == nullptr: r = b) with partials of <r, r>
+hipError_t launch_residual(const double* b, const double* q, double* r, long long n,
+                           double* partials, hipStream_t s);
+// r32 = (float)(r64 / sqrt(st->aux))
+hipError_t launch_to_f32_scaled(const double* r64, float* r32, long long n, const CgState* st,
+                                hipStream_t s);
+// x64 += sqrt(st->aux) * (double)d32
+hipError_t launch_add_f32_scaled(double* x64, const float* d32, long long n, const CgState* st,
+                                 hipStream_t s);
+// y = a*x + b*y (FP64); with b == 0 the old y is not read (it may hold NaN)
+hipError_t launch_axpby(double a, const double* x, double b, double* y, long long n,
+                        hipStream_t s);
+// fill with zero (a kernel, not a memset, so that captured graphs hold no memset nodes)
+hipError_t launch_zero(bool fp32, void* x, long long n, hipStream_t s);
+// reset CG state for a new solve: maxit, rtol (kept in aux for FIN_BNORM), done = 0
+hipError_t launch_state_init(CgState* st, int maxit, double rtol, hipStream_t s);
+// y = W^{(x)d} x (nodal mass weights), FP64
+hipError_t launch_mass(int dim, int N, const double* w, const double* x, double* y,
+                       long long ncells, hipStream_t s);
+
+// ---- null-space projection (pd_vec.hip)
+// corr = (P (x) P (x) P) (sum over cells of v) / ncells, then v -= corr per cell.
+// part: 256 * (N+1)^dim doubles; corr: (N+1)^dim doubles.
+hipError_t launch_project_null(bool fp32, void* v, long long ncells, int dim, int n,
+                               const double* Pnull_host, double* part, double* corr,
+                               hipStream_t s);
+
+// ---- line operators and convection (pd_ops.hip)
+struct LineLaunch {
+  int dim = 2, N = 0;
+  int nc[3] = {1, 1, 1};
+  int d = 0;                 // direction of the 1D operator
+  int o0 = 0, o1 = 0;        // cell offsets of the two inputs along d
+  double A0[81], A1[81];     // out_line = A0 in(i+o0) + A1 in(i+o1)
+  double coef = 1.0;         // scale
+  int wperp = 0;             // multiply by the GL weights of the other directions
+  double w[9];
+  double accum = 0.0;        // out = accum*out + coef*(...)
+  const double* in = nullptr;
+  double* out = nullptr;
+};
+hipError_t launch_line(const LineLaunch& L, hipStream_t s);
+
+struct ConvLaunch {
+  int dim = 2, N = 0;
+  int nc[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  double w[9], phi0[9], phi1[9], Kv[81];
+  const double* ucur[3] = {nullptr, nullptr, nullptr};   // stage input (main grid)
+  const double* u0[3] = {nullptr, nullptr, nullptr};     // step start
+  double* out[3] = {nullptr, nullptr, nullptr};
+  double a = 0.0, b = 1.0, dt = 0.0;                     // out = a u0 + b (ucur + dt L(ucur))
+};
+hipError_t launch_convect_stage(const ConvLaunch& L, hipStream_t s);
+
+}  // namespace pdk

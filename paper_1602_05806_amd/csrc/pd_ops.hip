@@ -1,0 +1,243 @@
+// Once-per-step operators of the fractional step (arXiv:1602.05806 Section 2.1-2.3):
+//   * 1D two-cell line operators along one direction: the weak gradient D (eq. weakgradient,
+//     velocity update eq. LOvelocityU), its transpose D^T (RHS of eq. LOpressure) and the L2
+//     projections between main and dual grids (eqs. l2forward, l2backward);
+//   * the explicit DG convection term with the Rusanov flux (eqs. Fu-Fw) combined with one stage
+//     of the third-order TVD Runge-Kutta scheme.
+// These run a few times per time step, not per CG iteration; they read their operands directly
+// from global memory (one thread per output DoF, neighbour lines served from L1/L2).
+#include "pd_device.h"
+#include "pd_launch.h"
+
+namespace pdk {
+
+namespace {
+
+template <int N>
+struct LineMats {
+  double A0[(N + 1) * (N + 1)], A1[(N + 1) * (N + 1)], w[N + 1];
+};
+
+__device__ __forceinline__ long long wrapl(long long i, long long m) {
+  i %= m;
+  return i < 0 ? i + m : i;
+}
+
+// out[cell, l] = accum*out + coef * wperp(l) * sum_m (A0[l_d][m] in[cell+o0 e_d, l(l_d=m)]
+//                                                     + A1[l_d][m] in[cell+o1 e_d, l(l_d=m)])
+template <int N, int DIM>
+__global__ __launch_bounds__(kBlock) void k_line(LineMats<N> M, const double* __restrict__ in,
+                                                 double* __restrict__ out, int nx, int ny, int nz,
+                                                 int d, int o0, int o1, double coef, int wperp,
+                                                 double accum) {
+  constexpr int n = N + 1, NC = DIM == 3 ? n * n * n : n * n;
+  const long long ncells = (long long)nx * ny * nz;
+  const long long tot = ncells * NC;
+  const int sd = d == 0 ? 1 : d == 1 ? n : n * n;   // node stride along d
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * kBlock) {
+    const long long cell = i / NC;
+    const int l = (int)(i - cell * NC);
+    const int l1 = l % n, l2 = (l / n) % n, l3 = DIM == 3 ? l / (n * n) : 0;
+    const int ld = d == 0 ? l1 : d == 1 ? l2 : l3;
+    const int lbase = l - ld * sd;
+    long long ci = cell % nx, cj = (cell / nx) % ny, ck = cell / ((long long)nx * ny);
+    long long c0, c1;
+    if (d == 0) {
+      c0 = (ck * ny + cj) * nx + wrapl(ci + o0, nx);
+      c1 = (ck * ny + cj) * nx + wrapl(ci + o1, nx);
+    } else if (d == 1) {
+      c0 = (ck * ny + wrapl(cj + o0, ny)) * nx + ci;
+      c1 = (ck * ny + wrapl(cj + o1, ny)) * nx + ci;
+    } else {
+      c0 = (wrapl(ck + o0, nz) * ny + cj) * nx + ci;
+      c1 = (wrapl(ck + o1, nz) * ny + cj) * nx + ci;
+    }
+    const double* p0 = in + c0 * NC + lbase;
+    const double* p1 = in + c1 * NC + lbase;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < n; ++m) s += M.A0[ld * n + m] * p0[m * sd] + M.A1[ld * n + m] * p1[m * sd];
+    double wt = 1.0;
+    if (wperp) {
+      if (d != 0) wt *= M.w[l1];
+      if (d != 1) wt *= M.w[l2];
+      if (DIM == 3 && d != 2) wt *= M.w[l3];
+    }
+    const double v = coef * wt * s;
+    out[i] = accum == 0.0 ? v : accum * out[i] + v;
+  }
+}
+
+template <int N>
+struct ConvMats {
+  double w[N + 1], phi0[N + 1], phi1[N + 1], Kv[(N + 1) * (N + 1)];
+};
+
+struct ConvPtrs {
+  const double* ucur[3];
+  const double* u0[3];
+  double* out[3];
+};
+
+// One RK stage for component `comp` at every DoF: out = a u0 + b (ucur + dt L(ucur)) with
+// L(U)_q = -sum_e h_e^-1 [ (phi_k(1) F_{e,right} - phi_k(0) F_{e,left}) / w_k
+//                          - sum_m Kv[k][m] (q v_e)(m) ]   (collocated at the GL nodes)
+// and the Rusanov flux F = (q^- v^- + q^+ v^+)/2 - s (q^+ - q^-)/2, s = 2 max(|v_e^-|, |v_e^+|).
+template <int N, int DIM>
+__global__ __launch_bounds__(kBlock) void k_convect(ConvMats<N> M, ConvPtrs P, int nx, int ny,
+                                                    int nz, double h0, double h1, double h2,
+                                                    double a, double b, double dt) {
+  constexpr int n = N + 1, NC = DIM == 3 ? n * n * n : n * n;
+  const long long ncells = (long long)nx * ny * nz;
+  const long long tot = ncells * NC;
+  const double hh[3] = {h0, h1, h2};
+  for (long long gi = (long long)blockIdx.x * kBlock + threadIdx.x; gi < tot * DIM;
+       gi += (long long)gridDim.x * kBlock) {
+    const int comp = (int)(gi / tot);
+    const long long i = gi - comp * tot;
+    const long long cell = i / NC;
+    const int l = (int)(i - cell * NC);
+    const int lidx[3] = {l % n, (l / n) % n, DIM == 3 ? l / (n * n) : 0};
+    const long long ci = cell % nx, cj = (cell / nx) % ny, ck = cell / ((long long)nx * ny);
+    const double* q = P.ucur[comp];
+    double rate = 0.0;
+#pragma unroll
+    for (int e = 0; e < DIM; ++e) {
+      const int sd = e == 0 ? 1 : e == 1 ? n : n * n;
+      const int le = lidx[e];
+      const int lbase = l - le * sd;
+      long long cl, cr;
+      if (e == 0) {
+        cl = (ck * ny + cj) * nx + wrapl(ci - 1, nx);
+        cr = (ck * ny + cj) * nx + wrapl(ci + 1, nx);
+      } else if (e == 1) {
+        cl = (ck * ny + wrapl(cj - 1, ny)) * nx + ci;
+        cr = (ck * ny + wrapl(cj + 1, ny)) * nx + ci;
+      } else {
+        cl = (wrapl(ck - 1, nz) * ny + cj) * nx + ci;
+        cr = (wrapl(ck + 1, nz) * ny + cj) * nx + ci;
+      }
+      const double* ve = P.ucur[e];
+      const double* qo = q + cell * NC + lbase;
+      const double* vo = ve + cell * NC + lbase;
+      const double* ql = q + cl * NC + lbase;
+      const double* vl = ve + cl * NC + lbase;
+      const double* qr = q + cr * NC + lbase;
+      const double* vr = ve + cr * NC + lbase;
+      double vol = 0.0, q0 = 0.0, q1 = 0.0, v0 = 0.0, v1 = 0.0;
+      double qlf = 0.0, vlf = 0.0, qrf = 0.0, vrf = 0.0;
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        const double qm = qo[m * sd], vm = vo[m * sd];
+        vol += M.Kv[le * n + m] * qm * vm;
+        q0 += M.phi0[m] * qm;
+        q1 += M.phi1[m] * qm;
+        v0 += M.phi0[m] * vm;
+        v1 += M.phi1[m] * vm;
+        qlf += M.phi1[m] * ql[m * sd];    // left neighbour at its right face
+        vlf += M.phi1[m] * vl[m * sd];
+        qrf += M.phi0[m] * qr[m * sd];    // right neighbour at its left face
+        vrf += M.phi0[m] * vr[m * sd];
+      }
+      const double sR = 2.0 * fmax(fabs(v1), fabs(vrf));
+      const double FR = 0.5 * (q1 * v1 + qrf * vrf) - 0.5 * sR * (qrf - q1);
+      const double sL = 2.0 * fmax(fabs(vlf), fabs(v0));
+      const double FL = 0.5 * (qlf * vlf + q0 * v0) - 0.5 * sL * (q0 - qlf);
+      const double surf = (M.phi1[le] * FR - M.phi0[le] * FL) / M.w[le];
+      rate -= (surf - vol) / hh[e];
+    }
+    const double uc = q[i];
+    const double base = a != 0.0 ? a * P.u0[comp][i] : 0.0;
+    P.out[comp][i] = base + b * (uc + dt * rate);
+  }
+}
+
+inline unsigned grid_for(long long tot) {
+  long long b = (tot + kBlock - 1) / kBlock;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+template <int N>
+hipError_t launch_line_N(const LineLaunch& L, hipStream_t s) {
+  LineMats<N> M;
+  constexpr int n = N + 1;
+  for (int i = 0; i < n * n; ++i) {
+    M.A0[i] = L.A0[i];
+    M.A1[i] = L.A1[i];
+  }
+  for (int i = 0; i < n; ++i) M.w[i] = L.w[i];
+  const int nz = L.dim == 3 ? L.nc[2] : 1;
+  const long long tot = (long long)L.nc[0] * L.nc[1] * nz * (L.dim == 3 ? n * n * n : n * n);
+  if (L.dim == 3)
+    hipLaunchKernelGGL((k_line<N, 3>), dim3(grid_for(tot)), dim3(kBlock), 0, s, M, L.in, L.out,
+                       L.nc[0], L.nc[1], nz, L.d, L.o0, L.o1, L.coef, L.wperp, L.accum);
+  else
+    hipLaunchKernelGGL((k_line<N, 2>), dim3(grid_for(tot)), dim3(kBlock), 0, s, M, L.in, L.out,
+                       L.nc[0], L.nc[1], nz, L.d, L.o0, L.o1, L.coef, L.wperp, L.accum);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t launch_conv_N(const ConvLaunch& L, hipStream_t s) {
+  ConvMats<N> M;
+  constexpr int n = N + 1;
+  for (int i = 0; i < n; ++i) {
+    M.w[i] = L.w[i];
+    M.phi0[i] = L.phi0[i];
+    M.phi1[i] = L.phi1[i];
+  }
+  for (int i = 0; i < n * n; ++i) M.Kv[i] = L.Kv[i];
+  ConvPtrs P;
+  for (int c = 0; c < 3; ++c) {
+    P.ucur[c] = L.ucur[c];
+    P.u0[c] = L.u0[c];
+    P.out[c] = L.out[c];
+  }
+  const int nz = L.dim == 3 ? L.nc[2] : 1;
+  const long long tot =
+      (long long)L.nc[0] * L.nc[1] * nz * (L.dim == 3 ? n * n * n : n * n) * L.dim;
+  if (L.dim == 3)
+    hipLaunchKernelGGL((k_convect<N, 3>), dim3(grid_for(tot)), dim3(kBlock), 0, s, M, P, L.nc[0],
+                       L.nc[1], nz, L.h[0], L.h[1], L.h[2], L.a, L.b, L.dt);
+  else
+    hipLaunchKernelGGL((k_convect<N, 2>), dim3(grid_for(tot)), dim3(kBlock), 0, s, M, P, L.nc[0],
+                       L.nc[1], nz, L.h[0], L.h[1], L.h[2], L.a, L.b, L.dt);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_line(const LineLaunch& L, hipStream_t s) {
+  switch (L.N) {
+    case 0: return launch_line_N<0>(L, s);
+    case 1: return launch_line_N<1>(L, s);
+    case 2: return launch_line_N<2>(L, s);
+    case 3: return launch_line_N<3>(L, s);
+    case 4: return launch_line_N<4>(L, s);
+    case 5: return launch_line_N<5>(L, s);
+    case 6: return launch_line_N<6>(L, s);
+    case 7: return launch_line_N<7>(L, s);
+    case 8: return launch_line_N<8>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_convect_stage(const ConvLaunch& L, hipStream_t s) {
+  switch (L.N) {
+    case 0: return launch_conv_N<0>(L, s);
+    case 1: return launch_conv_N<1>(L, s);
+    case 2: return launch_conv_N<2>(L, s);
+    case 3: return launch_conv_N<3>(L, s);
+    case 4: return launch_conv_N<4>(L, s);
+    case 5: return launch_conv_N<5>(L, s);
+    case 6: return launch_conv_N<6>(L, s);
+    case 7: return launch_conv_N<7>(L, s);
+    case 8: return launch_conv_N<8>(L, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace pdk

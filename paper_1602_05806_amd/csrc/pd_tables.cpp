@@ -1,0 +1,187 @@
+// Host FP64 construction of the 1D tables (arXiv:1602.05806, Section 2.1, eqs. (matrices),
+// (pSyst), (l2forward)). Computed once per context and uploaded to the device.
+#include "pd_tables.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace pdh {
+namespace {
+
+// n-point Gauss-Legendre rule on [-1,1] by Newton iteration on the Legendre three-term
+// recurrence, mapped to [0,1].
+void gauss_legendre01(int n, double* x01, double* w01) {
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+      }
+      double pn = (n == 1) ? x : p1;
+      double pnm1 = (n == 1) ? 1.0 : p0;
+      dp = n * (x * pn - pnm1) / (x * x - 1.0);
+      double dx = pn / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    // recompute derivative at the converged root
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = pk;
+    }
+    double pn = (n == 1) ? x : p1, pnm1 = (n == 1) ? 1.0 : p0;
+    dp = n * (x * pn - pnm1) / (x * x - 1.0);
+    double w = 2.0 / ((1.0 - x * x) * dp * dp);
+    // store ascending on [0,1]
+    x01[n - 1 - i] = 0.5 * (x + 1.0);
+    w01[n - 1 - i] = 0.5 * w;
+  }
+}
+
+double lag(const double* xi, int n, int p, double s) {
+  double v = 1.0;
+  for (int q = 0; q < n; ++q)
+    if (q != p) v *= (s - xi[q]) / (xi[p] - xi[q]);
+  return v;
+}
+
+double dlag(const double* xi, int n, int p, double s) {
+  double tot = 0.0;
+  for (int r = 0; r < n; ++r) {
+    if (r == p) continue;
+    double v = 1.0 / (xi[p] - xi[r]);
+    for (int q = 0; q < n; ++q)
+      if (q != p && q != r) v *= (s - xi[q]) / (xi[p] - xi[q]);
+    tot += v;
+  }
+  return tot;
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (row-major), eigenvectors in
+// the columns of V.
+void jacobi_eig(int n, double* A, double* V, double* lam) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) V[i * n + j] = (i == j);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += A[i * n + j] * A[i * n + j];
+    if (off < 1e-300) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {          // A <- A J
+          double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {          // A <- J^T A
+          double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {          // V <- V J
+          double vkp = V[k * n + p], vkq = V[k * n + q];
+          V[k * n + p] = c * vkp - s * vkq;
+          V[k * n + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i) lam[i] = A[i * n + i];
+}
+
+}  // namespace
+
+bool build_table(int N, Table1D* t, std::string* err) {
+  if (N < 0 || N > kMaxN) {
+    if (err) *err = "degree N must be in [0, 8]";
+    return false;
+  }
+  *t = Table1D{};
+  const int n = N + 1;
+  t->N = N;
+  t->n = n;
+  gauss_legendre01(n, t->xi, t->w);
+  // Quadrature for the integrals: N+2 points (exact to degree 2N+3 >= 2N).
+  const int nq = N + 2;
+  double qx[kMaxn + 2], qw[kMaxn + 2];
+  gauss_legendre01(nq, qx, qw);
+  const double* xi = t->xi;
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      double ir = 0, il = 0, ml = 0;
+      for (int k = 0; k < nq; ++k) {
+        double s = qx[k];
+        ir += qw[k] * lag(xi, n, p, 0.5 + 0.5 * s) * dlag(xi, n, q, 0.5 * s);
+        il += qw[k] * lag(xi, n, p, 0.5 * s) * dlag(xi, n, q, 0.5 + 0.5 * s);
+        ml += qw[k] * lag(xi, n, p, 0.5 * s) * lag(xi, n, q, 0.5 + 0.5 * s);
+      }
+      // eq. (matrices): jump at the dual-cell midpoint plus the two half-cell integrals
+      t->Rt[p * n + q] = lag(xi, n, p, 0.5) * lag(xi, n, q, 0.0) + 0.5 * ir;
+      t->Lt[p * n + q] = lag(xi, n, p, 0.5) * lag(xi, n, q, 1.0) - 0.5 * il;
+      t->ML[p * n + q] = 0.5 * ml;
+    }
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) t->MR[p * n + q] = t->ML[q * n + p];
+  // Pressure blocks of eq. (pSyst) with R-bar = L~^T, L-bar = R~^T:
+  //   C = L~^T M^-1 L~ + R~^T M^-1 R~,  R = -L~^T M^-1 R~,  L = R^T.
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      double c = 0, r = 0;
+      for (int m = 0; m < n; ++m) {
+        double wi = 1.0 / t->w[m];
+        c += t->Lt[m * n + p] * wi * t->Lt[m * n + q] + t->Rt[m * n + p] * wi * t->Rt[m * n + q];
+        r -= t->Lt[m * n + p] * wi * t->Rt[m * n + q];
+      }
+      t->Cb[p * n + q] = c;
+      t->Rb[p * n + q] = r;
+    }
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      t->Lb[p * n + q] = t->Rb[q * n + p];
+      if (q > p) {   // symmetrise C against rounding
+        double s = 0.5 * (t->Cb[p * n + q] + t->Cb[q * n + p]);
+        t->Cb[p * n + q] = t->Cb[q * n + p] = s;
+      }
+    }
+  for (int p = 0; p < n; ++p) {
+    t->phi0[p] = lag(xi, n, p, 0.0);
+    t->phi1[p] = lag(xi, n, p, 1.0);
+    for (int m = 0; m < n; ++m) t->Kv[p * n + m] = t->w[m] * dlag(xi, n, p, xi[m]) / t->w[p];
+  }
+  // Null space of (R~ - L~): the cell-periodic solutions of D P = 0. Eigenvectors of
+  // S = (R~-L~)^T (R~-L~) with eigenvalue below 1e-12 * max.
+  double S[kMaxn * kMaxn], V[kMaxn * kMaxn], lam[kMaxn];
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      double s = 0;
+      for (int m = 0; m < n; ++m)
+        s += (t->Rt[m * n + p] - t->Lt[m * n + p]) * (t->Rt[m * n + q] - t->Lt[m * n + q]);
+      S[p * n + q] = s;
+    }
+  jacobi_eig(n, S, V, lam);
+  double lmax = 0;
+  for (int i = 0; i < n; ++i) lmax = std::fmax(lmax, std::fabs(lam[i]));
+  t->nnull = 0;
+  std::memset(t->Pnull, 0, sizeof(t->Pnull));
+  for (int i = 0; i < n; ++i) {
+    if (lmax == 0.0 || std::fabs(lam[i]) <= 1e-12 * lmax) {
+      ++t->nnull;
+      for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q) t->Pnull[p * n + q] += V[p * n + i] * V[q * n + i];
+    }
+  }
+  return true;
+}
+
+}  // namespace pdh

@@ -1,0 +1,31 @@
+// Host-side 1D reference-element tables (FP64) of the staggered spectral DG scheme,
+// arXiv:1602.05806 Section 2.1: Gauss-Legendre nodal basis on [0,1], the matrices of eq. (matrices),
+// the pressure blocks of eq. (pSyst), the L2-projection matrices of eq. (l2forward), and the
+// cell-periodic null space of the 1D weak gradient.
+#pragma once
+#include <string>
+
+namespace pdh {
+
+constexpr int kMaxN = 8;                 // supported degrees 0..kMaxN
+constexpr int kMaxn = kMaxN + 1;
+
+struct Table1D {
+  int N = 0, n = 1;
+  double xi[kMaxn], w[kMaxn];            // GL nodes / weights on [0,1], sum w = 1
+  double Rt[kMaxn * kMaxn];              // R~  (row p, column q), eq. (matrices)
+  double Lt[kMaxn * kMaxn];              // L~
+  double Cb[kMaxn * kMaxn];              // C  = L~^T M^-1 L~ + R~^T M^-1 R~  (diagonal block)
+  double Rb[kMaxn * kMaxn];              // R  = -L~^T M^-1 R~  (couples cell i to i+1)
+  double Lb[kMaxn * kMaxn];              // L  = R^T            (couples cell i to i-1)
+  double ML[kMaxn * kMaxn], MR[kMaxn * kMaxn];   // eq. (l2forward), MR = ML^T
+  double phi0[kMaxn], phi1[kMaxn];       // phi_p(0), phi_p(1)
+  double Kv[kMaxn * kMaxn];              // Kv[k][m] = w_m phi_k'(xi_m) / w_k (collocated volume term)
+  int nnull = 0;                         // dimension of null(R~ - L~) (1 for even N, 2 for odd N)
+  double Pnull[kMaxn * kMaxn];           // orthogonal projector onto null(R~ - L~)
+};
+
+// Fills t for degree N. Returns false (with a message) for unsupported N.
+bool build_table(int N, Table1D* t, std::string* err);
+
+}  // namespace pdh

@@ -1,0 +1,370 @@
+// Streaming vector kernels of the conjugate-gradient loop (arXiv:1602.05806 Section 2.1: the
+// pressure system is solved by a matrix-free CG method) and of the null-space projection.
+// Every reduction accumulates in FP64, sums per block in a fixed order and finishes in the last
+// block to arrive (deterministic: repeated runs give bit-identical scalars).
+#include "pd_device.h"
+#include "pd_launch.h"
+
+namespace pdk {
+
+namespace {
+
+constexpr int kStreamBlocks = kMaxStreamPartials;
+
+inline unsigned stream_blocks(long long n, int per_thread) {
+  long long b = (n + (long long)kBlock * per_thread - 1) / ((long long)kBlock * per_thread);
+  if (b < 1) b = 1;
+  if (b > kStreamBlocks) b = kStreamBlocks;
+  return (unsigned)b;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dot(const T* __restrict__ a, const T* __restrict__ b,
+                                                long long n, double* __restrict__ partials) {
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    s += (double)a[i] * (double)b[i];
+  s = block_sum_all<kBlock>(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// Single-block finalize of a stand-alone reduction.
+__global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ partials, int n,
+                                                     CgState* st, int fin) {
+  const double s = sum_partials<kBlock>(partials, n);
+  if (threadIdx.x == 0) {
+    if (fin == FIN_BNORM) {
+      st->bnorm2 = s;
+      st->tol2 = st->aux * st->aux * s;
+    } else {
+      st->aux = s;
+    }
+  }
+}
+
+// CG iteration k, second half: alpha_k = rho_k / <p_k, A p_k> (sigma re-summed from the apply
+// kernel's block partials), x += alpha p; r -= alpha q; block partials of <r_{k+1}, r_{k+1}>.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T* __restrict__ p,
+                                                      const T* __restrict__ q, T* __restrict__ r,
+                                                      long long n, CgState* st, int k,
+                                                      const double* __restrict__ sigpart, int nsig,
+                                                      double* __restrict__ rho_next) {
+  if (st->done) return;
+  // The first J elements of this thread are loaded before sigma is reduced (latency overlap).
+  constexpr int J = 4;
+  const long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  T xv[J], pv[J], qv[J], rv[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const long long i = i0 + j * stride;
+    if (i < n) {
+      xv[j] = x[i];
+      pv[j] = p[i];
+      qv[j] = q[i];
+      rv[j] = r[i];
+    }
+  }
+  const double sigma = sum_partials<kBlock>(sigpart, nsig);
+  const double alpha = st->rho / sigma;
+  if (!(sigma > 0.0) || !isfinite(alpha)) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+      st->sigma = sigma;
+      st->status = -5;
+      st->iter = k;
+      st->done = 1;
+    }
+    return;
+  }
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->sigma = sigma;
+    st->alpha = alpha;
+  }
+  const T a = (T)alpha;
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const long long i = i0 + j * stride;
+    if (i < n) {
+      x[i] = xv[j] + a * pv[j];
+      const T rn = rv[j] - a * qv[j];
+      r[i] = rn;
+      s += (double)rn * (double)rn;
+    }
+  }
+  for (long long i = i0 + J * stride; i < n; i += stride) {
+    x[i] = x[i] + a * p[i];
+    const T rn = r[i] - a * q[i];
+    r[i] = rn;
+    s += (double)rn * (double)rn;
+  }
+  s = block_sum_all<kBlock>(s);
+  if (threadIdx.x == 0) rho_next[blockIdx.x] = s;
+}
+
+// r = b - q (q may be null: r = b), with block partials of <r, r>.
+__global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ b,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ r, long long n,
+                                                     double* __restrict__ partials) {
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const double v = q ? b[i] - q[i] : b[i];
+    r[i] = v;
+    s += v * v;
+  }
+  s = block_sum_all<kBlock>(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_f32_scaled(const double* __restrict__ r64,
+                                                          float* __restrict__ r32, long long n,
+                                                          const CgState* st) {
+  const double nrm2 = st->aux;
+  const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    r32[i] = (float)(sc * r64[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_f32_scaled(double* __restrict__ x64,
+                                                           const float* __restrict__ d32,
+                                                           long long n, const CgState* st) {
+  const double sc = sqrt(st->aux);
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    x64[i] += sc * (double)d32[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpby(double a, const double* __restrict__ x, double b,
+                                                  double* __restrict__ y, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];   // b == 0: y is write-only
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_zero(T* __restrict__ x, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    x[i] = T(0);
+}
+
+__global__ void k_state_init(CgState* st, int maxit, double rtol) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->rho = 0.0;
+    st->sigma = 0.0;
+    st->alpha = 0.0;
+    st->beta = 0.0;
+    st->bnorm2 = 0.0;
+    st->tol2 = 0.0;
+    st->aux = rtol;
+    st->iter = 0;
+    st->maxit = maxit;
+    st->done = 0;
+    st->status = 0;
+  }
+}
+
+struct W9 {
+  double w[9];
+};
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_mass(W9 W, int n, const double* __restrict__ x,
+                                                 double* __restrict__ y, long long ncells) {
+  const int NC = DIM == 3 ? n * n * n : n * n;
+  const long long tot = ncells * NC;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * kBlock) {
+    const int l = (int)(i % NC);
+    const int l1 = l % n, l2 = (l / n) % n, l3 = l / (n * n);
+    double wt = W.w[l1] * W.w[l2];
+    if (DIM == 3) wt *= W.w[l3];
+    y[i] = wt * x[i];
+  }
+}
+
+// ---- null-space projection: per-node sums over cells, then correction per node
+constexpr int kNullBlocks = 256;
+
+struct P81 {
+  double P[81];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_node_sums(const T* __restrict__ v, long long ncells,
+                                                      int NC, double* __restrict__ part) {
+  const long long per = (ncells + gridDim.x - 1) / gridDim.x;
+  const long long c0 = (long long)blockIdx.x * per;
+  const long long c1 = c0 + per < ncells ? c0 + per : ncells;
+  for (int l = threadIdx.x; l < NC; l += kBlock) {
+    double s = 0.0;
+    for (long long c = c0; c < c1; ++c) s += (double)v[c * NC + l];
+    part[(size_t)blockIdx.x * NC + l] = s;
+  }
+}
+
+// corr = (P (x) ... (x) P) (sum of the node partials) / ncells  (single block)
+__global__ __launch_bounds__(kBlock) void k_null_finalize(const double* __restrict__ part,
+                                                          int nblk, long long ncells, int NC,
+                                                          int dim, int n, P81 P,
+                                                          double* __restrict__ corr) {
+  __shared__ double S[kMaxNC], U[kMaxNC];
+  for (int l = threadIdx.x; l < NC; l += kBlock) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * NC + l];
+    S[l] = s / (double)ncells;
+  }
+  __syncthreads();
+  for (int d = 0; d < dim; ++d) {
+    int stride = 1;
+    for (int e = 0; e < d; ++e) stride *= n;
+    for (int l = threadIdx.x; l < NC; l += kBlock) {
+      const int ld = (l / stride) % n;
+      const int base = l - ld * stride;
+      double s = 0.0;
+      for (int m = 0; m < n; ++m) s += P.P[ld * n + m] * S[base + m * stride];
+      U[l] = s;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < NC; l += kBlock) S[l] = U[l];
+    __syncthreads();
+  }
+  for (int l = threadIdx.x; l < NC; l += kBlock) corr[l] = S[l];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sub_nodes(T* __restrict__ v, long long tot, int NC,
+                                                      const double* __restrict__ corr) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * kBlock)
+    v[i] = (T)((double)v[i] - corr[i % NC]);
+}
+
+}  // namespace
+
+unsigned stream_grid(long long n) { return stream_blocks(n, 4); }
+
+hipError_t launch_dot(bool fp32, const void* a, const void* b, long long n, double* partials,
+                      hipStream_t s) {
+  const unsigned G = stream_blocks(n, 4);
+  if (fp32)
+    hipLaunchKernelGGL(k_dot<float>, dim3(G), dim3(kBlock), 0, s, (const float*)a,
+                       (const float*)b, n, partials);
+  else
+    hipLaunchKernelGGL(k_dot<double>, dim3(G), dim3(kBlock), 0, s, (const double*)a,
+                       (const double*)b, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int nparts, CgState* st, int fin,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, partials, nparts, st, fin);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(bool fp32, void* x, const void* p, const void* q, void* r,
+                            long long n, CgState* st, int k, const double* sigpart, int nsig,
+                            double* rho_next, hipStream_t s) {
+  const unsigned G = stream_blocks(n, 4);
+  if (fp32)
+    hipLaunchKernelGGL(k_cg_update<float>, dim3(G), dim3(kBlock), 0, s, (float*)x,
+                       (const float*)p, (const float*)q, (float*)r, n, st, k, sigpart, nsig,
+                       rho_next);
+  else
+    hipLaunchKernelGGL(k_cg_update<double>, dim3(G), dim3(kBlock), 0, s, (double*)x,
+                       (const double*)p, (const double*)q, (double*)r, n, st, k, sigpart, nsig,
+                       rho_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const double* b, const double* q, double* r, long long n,
+                           double* partials, hipStream_t s) {
+  const unsigned G = stream_blocks(n, 4);
+  hipLaunchKernelGGL(k_residual, dim3(G), dim3(kBlock), 0, s, b, q, r, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32_scaled(const double* r64, float* r32, long long n, const CgState* st,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32_scaled, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, r64, r32,
+                     n, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f32_scaled(double* x64, const float* d32, long long n, const CgState* st,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(k_add_f32_scaled, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, x64, d32,
+                     n, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(double a, const double* x, double b, double* y, long long n,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(bool fp32, void* x, long long n, hipStream_t s) {
+  if (fp32)
+    hipLaunchKernelGGL(k_zero<float>, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, (float*)x, n);
+  else
+    hipLaunchKernelGGL(k_zero<double>, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, (double*)x,
+                       n);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_init(CgState* st, int maxit, double rtol, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, rtol);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass(int dim, int N, const double* w, const double* x, double* y,
+                       long long ncells, hipStream_t s) {
+  W9 W;
+  for (int i = 0; i < 9; ++i) W.w[i] = i <= N ? w[i] : 0.0;
+  const int n = N + 1;
+  const long long tot = ncells * (dim == 3 ? n * n * n : n * n);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_mass<3>, dim3(stream_blocks(tot, 4)), dim3(kBlock), 0, s, W, n, x, y,
+                       ncells);
+  else
+    hipLaunchKernelGGL(k_mass<2>, dim3(stream_blocks(tot, 4)), dim3(kBlock), 0, s, W, n, x, y,
+                       ncells);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_null(bool fp32, void* v, long long ncells, int dim, int n,
+                               const double* Pnull_host, double* part, double* corr,
+                               hipStream_t s) {
+  P81 P;
+  for (int i = 0; i < 81; ++i) P.P[i] = i < n * n ? Pnull_host[i] : 0.0;
+  const int NC = dim == 3 ? n * n * n : n * n;
+  const unsigned G = ncells < kNullBlocks ? (unsigned)ncells : (unsigned)kNullBlocks;
+  if (fp32)
+    hipLaunchKernelGGL(k_node_sums<float>, dim3(G), dim3(kBlock), 0, s, (const float*)v, ncells,
+                       NC, part);
+  else
+    hipLaunchKernelGGL(k_node_sums<double>, dim3(G), dim3(kBlock), 0, s, (const double*)v,
+                       ncells, NC, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_null_finalize, dim3(1), dim3(kBlock), 0, s, (const double*)part, (int)G,
+                     ncells, NC, dim, n, P, corr);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long tot = ncells * NC;
+  if (fp32)
+    hipLaunchKernelGGL(k_sub_nodes<float>, dim3(stream_blocks(tot, 4)), dim3(kBlock), 0, s,
+                       (float*)v, tot, NC, (const double*)corr);
+  else
+    hipLaunchKernelGGL(k_sub_nodes<double>, dim3(stream_blocks(tot, 4)), dim3(kBlock), 0, s,
+                       (double*)v, tot, NC, (const double*)corr);
+  return hipGetLastError();
+}
+
+}  // namespace pdk

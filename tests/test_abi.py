@@ -1,0 +1,41 @@
+"""The C-ABI library loads on any host and exports every entry point declared in include/pd.h
+(no compute calls: those need a GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "pd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pd_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ["pd_setup", "pd_apply", "pd_cg_solve", "pd_project_velocity", "pd_step"]:
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(pd):
+    lib = ctypes.CDLL(pd.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert sorted(pd.EXPORTED) == declared_symbols()
+
+
+def test_setup_rejects_bad_arguments_without_touching_the_device(pd):
+    import pytest
+    for args in [(4, (4, 4), (1.0, 1.0), 2, 1e-3, 0.6, 0.0),      # dim
+                 (2, (0, 4), (1.0, 1.0), 2, 1e-3, 0.6, 0.0),      # cells
+                 (2, (4, 4), (1.0, 1.0), 9, 1e-3, 0.6, 0.0),      # N
+                 (2, (4, 4), (1.0, 1.0), 2, -1.0, 0.6, 0.0),      # dt
+                 (2, (4, 4), (1.0, 1.0), 2, 1e-3, 0.3, 0.0)]:     # theta
+        with pytest.raises(pd.PdError) as e:
+            pd.pd_setup(*args, stream=0)
+        assert e.value.code == pd.PD_EINVAL
+    with pytest.raises(pd.PdError) as e:
+        pd.pd_setup(2, (4, 4), (1.0, 1.0), 2, 1e-3, 0.6, 0.0, periodic_mask=1, stream=0)
+    assert e.value.code == pd.PD_EINVAL

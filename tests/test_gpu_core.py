@@ -1,0 +1,248 @@
+"""GPU parity of the operator apply, the CG solves and the support operators against the oracle.
+
+Every case prints its parameters before touching the GPU so that a failure names its case."""
+import numpy as np
+import pytest
+
+from oracle import layout
+from oracle.operators import (Grid, pressure_operator, viscous_operator, div_rhs, grad_update,
+                              apply_at)
+from oracle.solvers import FastDiag
+from oracle.step import dual_to_main, main_to_dual, rk3, StepOracle
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a, dtype=None):
+    import torch
+    return torch.tensor(np.asarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def mass_norm(grid, v_tensor):
+    W = np.ones(grid.shape())
+    for d in range(grid.dim):
+        shp = [1] * grid.dim
+        shp[grid.dim - 1 - d] = -1
+        W = W * np.tile(grid.tab.w, grid.cells[d]).reshape(shp)
+    return np.sqrt(np.sum(W * v_tensor ** 2))
+
+
+APPLY_CASES = [
+    (2, (5, 3), 3), (2, (16, 16), 3), (2, (9, 17), 6), (2, (3, 2), 0), (2, (11, 7), 8),
+    (2, (1, 4), 2), (2, (13, 5), 5),
+    (3, (5, 6, 9), 4), (3, (3, 3, 3), 3), (3, (2, 3, 9), 1), (3, (3, 2, 2), 8), (3, (4, 4, 5), 2),
+    (3, (9, 2, 3), 0), (3, (3, 2, 6), 6),
+]
+
+
+@pytest.mark.parametrize("dim,cells,N", APPLY_CASES)
+@pytest.mark.parametrize("op", [0, 1])
+def test_apply_fp64_fp32(pd, dim, cells, N, op):
+    import torch
+    print(f"apply dim={dim} cells={cells} N={N} op={op}", flush=True)
+    L = (1.0, 0.7, 1.3)[:dim]
+    dt, nu = 1e-3, 0.37
+    g = Grid(cells, L, N)
+    ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, nu)
+    rng = np.random.default_rng(100 + N)
+    x = rng.standard_normal(g.ndof)
+    A = pressure_operator(g, dt) if op == 0 else viscous_operator(g, dt, nu)
+    ref = layout.tensor_to_blocked(A @ layout.blocked_to_tensor(x, cells, g.n).reshape(-1), cells, g.n)
+    y = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+    pd.pd_apply(ctx, op, pd.PD_FP64, dev(x), y)
+    got = host(y)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-13 * scale
+    y32 = torch.empty(g.ndof, dtype=torch.float32, device="cuda")
+    pd.pd_apply(ctx, op, pd.PD_FP32, dev(x, torch.float32), y32)
+    got32 = host(y32)
+    assert np.linalg.norm(got32 - ref) <= 3e-6 * np.linalg.norm(ref)
+    ctx.close()
+
+
+def _solve_case(pd, dim, cells, N, op, prec, project_rhs, rtol, seed):
+    import torch
+    print(f"solve dim={dim} cells={cells} N={N} op={op} prec={prec} seed={seed}", flush=True)
+    L = (1.0,) * dim
+    dt, nu = 5e-4, 1e-2
+    g = Grid(cells, L, N)
+    fd = FastDiag(g)
+    b = synthetic.random_rhs(seed, g.ndof)
+    bt = layout.blocked_to_tensor(b, cells, g.n)
+    if op == 0:
+        ref_t = fd.solve(bt, 0.0, dt)
+    else:
+        ref_t = fd.solve(bt, 1.0, nu * dt)
+    ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, nu)
+    x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    info = pd.pd_cg_solve(ctx, op, prec, dev(b), x, rtol, 200000)
+    got_t = layout.blocked_to_tensor(host(x), cells, g.n)
+    err = mass_norm(g, got_t - ref_t) / mass_norm(g, ref_t)
+    ctx.close()
+    return info, err
+
+
+@pytest.mark.parametrize("dim,cells,N", [(2, (16, 16), 3), (2, (12, 9), 6), (2, (7, 8), 2),
+                                         (3, (5, 4, 6), 3), (3, (4, 4, 4), 4)])
+@pytest.mark.parametrize("prec", [0, 2])
+def test_pressure_solve_matches_min_norm(pd, dim, cells, N, prec):
+    info, err = _solve_case(pd, dim, cells, N, 0, prec, True, 1e-12, 11)
+    print(info, err)
+    assert info["status"] == pd.PD_OK
+    assert info["rel_res_true"] <= 2e-12
+    assert err <= 1e-9
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_viscous_solve(pd, prec):
+    info, err = _solve_case(pd, 2, (10, 12), 4, 1, prec, False, 1e-12, 12)
+    assert info["status"] == pd.PD_OK
+    assert err <= 1e-11
+
+
+def test_status_codes(pd):
+    import torch
+    cells, N = (6, 6), 2
+    ctx = pd.pd_setup(2, cells, (1.0, 1.0), N, 1e-3, 0.6, 0.0)
+    g = Grid(cells, (1.0, 1.0), N)
+    b = synthetic.random_rhs(3, g.ndof)
+    x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(b), x, 1e-12, 2)
+    assert info["status"] == pd.PD_ENOCONV and info["iters"] == 2
+    bn = b.copy()
+    bn[5] = np.nan
+    x.zero_()
+    info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(bn), x, 1e-12, 100)
+    assert info["status"] == pd.PD_EBREAKDOWN
+    x.zero_()
+    info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(np.zeros(g.ndof)), x, 1e-12, 100)
+    assert info["status"] == pd.PD_OK and float(x.abs().max()) == 0.0
+    with pytest.raises(pd.PdError):
+        pd.pd_cg_solve(ctx, 7, pd.PD_FP64, dev(b), x, 1e-12, 100)
+    ctx.close()
+    with pytest.raises(pd.PdError):
+        pd.pd_setup(2, (4, 4), (1.0, 1.0), 9, 1e-3, 0.6, 0.0)
+
+
+@pytest.mark.parametrize("dim,cells,N", [(2, (6, 5), 3), (2, (4, 7), 6), (3, (3, 4, 5), 2),
+                                         (3, (4, 3, 3), 3)])
+def test_line_operators(pd, dim, cells, N):
+    import torch
+    print(f"line ops dim={dim} cells={cells} N={N}", flush=True)
+    L = (1.0, 0.8, 1.2)[:dim]
+    dt = 2e-3
+    g = Grid(cells, L, N)
+    ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, 0.0)
+    rng = np.random.default_rng(5)
+    U = [rng.standard_normal(g.ndof) for _ in range(dim)]
+    q = rng.standard_normal(g.ndof)
+    Ut = [layout.blocked_to_tensor(u, cells, g.n) for u in U]
+    # b = sum_d B_d U_d
+    ref = sum(div_rhs(g, d) @ Ut[d].reshape(-1) for d in range(dim))
+    b = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+    ud = [dev(u) for u in U]
+    pd.pd_rhs_div(ctx, ud, b)
+    ref_b = layout.tensor_to_blocked(ref.reshape(g.shape()), cells, g.n)
+    assert np.abs(host(b) - ref_b).max() <= 1e-13 * np.abs(ref_b).max()
+    # velocity update
+    pd.pd_project_velocity(ctx, dev(q), ud)
+    qt = layout.blocked_to_tensor(q, cells, g.n).reshape(-1)
+    for d in range(dim):
+        ref_u = Ut[d].reshape(-1) - grad_update(g, d, dt) @ qt
+        ref_u = layout.tensor_to_blocked(ref_u.reshape(g.shape()), cells, g.n)
+        assert np.abs(host(ud[d]) - ref_u).max() <= 1e-13 * np.abs(ref_u).max()
+    # L2 projections
+    for d in range(dim):
+        out = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+        pd.pd_l2_project(ctx, d, 0, dev(U[d]), out)
+        ref_m = layout.tensor_to_blocked(dual_to_main(g, Ut[d], d), cells, g.n)
+        assert np.abs(host(out) - ref_m).max() <= 1e-13 * np.abs(ref_m).max()
+        pd.pd_l2_project(ctx, d, 1, dev(U[d]), out)
+        ref_s = layout.tensor_to_blocked(main_to_dual(g, Ut[d], d), cells, g.n)
+        assert np.abs(host(out) - ref_s).max() <= 1e-13 * np.abs(ref_s).max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("dim,cells,N", [(2, (6, 5), 3), (3, (3, 4, 3), 2)])
+def test_convection_rk3(pd, dim, cells, N):
+    print(f"convection dim={dim} cells={cells} N={N}", flush=True)
+    L = (1.0,) * dim
+    dt = 1e-3
+    g = Grid(cells, L, N)
+    ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, 0.0)
+    rng = np.random.default_rng(9)
+    V = [0.3 * rng.standard_normal(g.ndof) for _ in range(dim)]
+    Vt = [layout.blocked_to_tensor(v, cells, g.n) for v in V]
+    ref = rk3(g, Vt, dt)
+    vd = [dev(v) for v in V]
+    pd.pd_convect(ctx, vd)
+    for d in range(dim):
+        r = layout.tensor_to_blocked(ref[d], cells, g.n)
+        assert np.abs(host(vd[d]) - r).max() <= 1e-13 * np.abs(r).max()
+    ctx.close()
+
+
+def _tgv_initial(g):
+    coords = synthetic.staggered_coords(g.cells, g.lengths, g.tab.xi)
+    U = synthetic.tgv2d([(coords[0][0], coords[0][1]), (coords[1][0], coords[1][1])])
+    return U
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_step_tgv2d_16_N3(pd, prec):
+    import torch
+    cfg = synthetic.CONFIGS["tgv2d_16_N3"]
+    cells, N = cfg["cells"], cfg["N"]
+    print(f"step tgv2d cells={cells} N={N} prec={prec}", flush=True)
+    g = Grid(cells, cfg["lengths"], N)
+    so = StepOracle(g, cfg["dt"], cfg["theta"], cfg["nu"])
+    Ut = _tgv_initial(g)
+    P0 = np.zeros(g.shape())
+    ref = so.step(Ut, P0)
+    ctx = pd.pd_setup(2, cells, cfg["lengths"], N, cfg["dt"], cfg["theta"], cfg["nu"])
+    pd.pd_configure(ctx, pd.PD_CFG_STEP_PREC, prec)
+    pd.pd_configure(ctx, pd.PD_CFG_P_RTOL, 1e-12)
+    pd.pd_configure(ctx, pd.PD_CFG_V_RTOL, 1e-13)
+    ud = [dev(layout.tensor_to_blocked(u, cells, g.n)) for u in Ut]
+    p = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    infos = pd.pd_step(ctx, ud, p)
+    print(infos)
+    assert all(i["status"] == pd.PD_OK for i in infos[:2] + infos[3:])
+    for d in range(2):
+        r = ref["U_new"][d]
+        got = layout.blocked_to_tensor(host(ud[d]), cells, g.n)
+        assert mass_norm(g, got - r) <= 1e-10 * mass_norm(g, r)
+    got_p = layout.blocked_to_tensor(host(p), cells, g.n)
+    assert mass_norm(g, got_p - ref["P_new"]) <= 1e-9 * mass_norm(g, ref["P_new"])
+    ctx.close()
+
+
+def test_full_size_apply_sampled(pd):
+    """3D 64^3 N=4 (32.8M DoFs) and 2D 256^2 N=6: sampled outputs of pd_apply against the
+    block definition evaluated one output at a time."""
+    import torch
+    for dim, cells, N in [(2, (256, 256), 6), (3, (64, 64, 64), 4)]:
+        print(f"full-size apply dim={dim} cells={cells} N={N}", flush=True)
+        L = (1.0,) * dim
+        g = Grid(cells, L, N)
+        ctx = pd.pd_setup(dim, cells, L, N, 1e-3, 0.6, 1e-3)
+        rng = np.random.default_rng(77)
+        x = rng.standard_normal(g.ndof)
+        y = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+        pd.pd_apply(ctx, 0, pd.PD_FP64, dev(x), y)
+        yt = layout.blocked_to_tensor(host(y), cells, g.n)
+        xt = layout.blocked_to_tensor(x, cells, g.n)
+        shp = g.shape()
+        idx = np.stack([rng.integers(0, s, size=200) for s in shp], axis=1)
+        # include the periodic seams
+        idx[:4] = 0
+        idx[4:8] = np.array(shp) - 1
+        ref = apply_at(g, xt, idx, 0.0, 1e-3)
+        got = yt[tuple(idx.T)]
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        ctx.close()
