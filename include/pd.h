@@ -46,8 +46,11 @@ enum {
 
 /* Precision of a call. PD_FP64: FP64 arrays and arithmetic. PD_FP32: FP32 arrays and arithmetic
  * with FP64 dot-product accumulation (pd_apply only). PD_FP32_REFINE64: FP64 arrays at the
- * boundary; the solve runs FP32 conjugate-gradient inner solves on the FP64 residual and
- * accumulates the corrections in FP64 (iterative refinement), stopping on the FP64 residual. */
+ * boundary; the solve runs one conjugate-gradient iteration on FP32 vectors (operator applies
+ * and vector updates in FP32, dot products accumulated in FP64) and periodically flushes the
+ * FP32 correction into the FP64 solution and replaces the FP32 residual by the FP64 residual
+ * b - A x (iterative refinement by residual replacement, keeping the search direction); it
+ * stops on the FP64 residual. */
 enum { PD_FP64 = 0, PD_FP32 = 1, PD_FP32_REFINE64 = 2 };
 
 /* Operators. PD_OP_PRESSURE: A_p = dt * K with K = sum_d h_d^-2 (M on the other directions)
@@ -58,12 +61,15 @@ enum { PD_FP64 = 0, PD_FP32 = 1, PD_FP32_REFINE64 = 2 };
  * definite, A_p positive semi-definite with null space Z = null of the weak gradient. */
 enum { PD_OP_PRESSURE = 0, PD_OP_VISCOUS = 1 };
 
-/* Per-solve report. iters: total CG iterations (inner iterations summed for refinement);
- * outer_iters: refinement outer iterations (1 for PD_FP64); status: PD_OK / PD_ENOCONV /
- * PD_EBREAKDOWN; rel_res_recur: final recurrence residual ||r||/||b||; rel_res_true: true FP64
- * residual ||b - A x||/||b|| recomputed at exit; ms: wall time of the solve on the stream. */
+/* Per-solve report. iters: CG iterations (for PD_FP32_REFINE64 the FP32 iterations);
+ * outer_iters: FP64 residual recomputations of the refinement (1 for PD_FP64); restarts:
+ * refinement replacements that also restarted the search direction; status: PD_OK /
+ * PD_ENOCONV / PD_EBREAKDOWN; rel_res_recur: last recurrence (FP64: CG recurrence; refinement:
+ * last FP64) residual / ||b||; rel_res_true: true FP64 residual ||b - A x||/||b|| recomputed at
+ * exit; ms: wall time of the solve on the stream. ||b|| is taken after the null-space projection
+ * for PD_OP_PRESSURE. */
 typedef struct {
-  int iters, outer_iters, status;
+  int iters, outer_iters, status, restarts;
   double rel_res_recur, rel_res_true, ms;
 } pd_solve_info;
 
@@ -139,13 +145,21 @@ int pd_step(pd_ctx* ctx, void* const u[3], void* p, pd_solve_info info[4], void*
  *   PD_CFG_V_RTOL        viscous tolerance in pd_step (default 1e-12)
  *   PD_CFG_MAXIT         iteration cap for the step's solves (default 100000)
  *   PD_CFG_CONVECTION    1 (default) = explicit convection on, 0 = off (unsteady Stokes step)
- *   PD_CFG_INNER_RTOL    inner FP32 tolerance of the refinement (default 1e-4)
+ *   PD_CFG_RU_FACTOR     PD_FP32_REFINE64: the FP32 residual is replaced by the FP64 residual
+ *                        b - A x each time it has dropped by this factor (default 0.1)
  *   PD_CFG_TIMING        1 = record HIP events around every launch of the operator kernel
  *                        inside solves (see pd_timing), 0 (default) = off
- *   PD_CFG_CHECK_EVERY   convergence poll interval of the solve loop in iterations (default 32) */
+ *   PD_CFG_CHECK_EVERY   convergence poll interval of the solve loop in iterations (default 32)
+ *   PD_CFG_KZ            3D operator kernel: planes per column segment (0 = automatic)
+ *   PD_CFG_TILES_PER_WG  2D operator kernel: tiles per persistent workgroup (0 = automatic)
+ *   PD_CFG_PREFETCH      1 (default) = the operator kernel prefetches the next tile (2D) or the
+ *                        next plane's halo (3D) into registers during compute, 0 = no prefetch
+ * The last three only change the launch shape; results are identical up to the block order of
+ * the dot-product partial sums. */
 enum {
   PD_CFG_STEP_PREC = 0, PD_CFG_P_RTOL = 1, PD_CFG_V_RTOL = 2, PD_CFG_MAXIT = 3,
-  PD_CFG_CONVECTION = 4, PD_CFG_INNER_RTOL = 5, PD_CFG_TIMING = 6, PD_CFG_CHECK_EVERY = 7
+  PD_CFG_CONVECTION = 4, PD_CFG_RU_FACTOR = 5, PD_CFG_TIMING = 6, PD_CFG_CHECK_EVERY = 7,
+  PD_CFG_KZ = 8, PD_CFG_TILES_PER_WG = 9, PD_CFG_PREFETCH = 10
 };
 int pd_configure(pd_ctx* ctx, int key, double value);
 

@@ -28,7 +28,8 @@ PD_OK, PD_EINVAL, PD_ENOMEM, PD_EDEVICE, PD_ENOCONV, PD_EBREAKDOWN = 0, -1, -2, 
 PD_FP64, PD_FP32, PD_FP32_REFINE64 = 0, 1, 2
 PD_OP_PRESSURE, PD_OP_VISCOUS = 0, 1
 (PD_CFG_STEP_PREC, PD_CFG_P_RTOL, PD_CFG_V_RTOL, PD_CFG_MAXIT, PD_CFG_CONVECTION,
- PD_CFG_INNER_RTOL, PD_CFG_TIMING, PD_CFG_CHECK_EVERY) = range(8)
+ PD_CFG_RU_FACTOR, PD_CFG_TIMING, PD_CFG_CHECK_EVERY, PD_CFG_KZ, PD_CFG_TILES_PER_WG,
+ PD_CFG_PREFETCH) = range(11)
 
 EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "pd_apply",
             "pd_cg_solve", "pd_rhs_div", "pd_project_velocity", "pd_project_null",
@@ -37,7 +38,7 @@ EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "
 
 class pd_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
-                ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("restarts", ctypes.c_int), ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("ms", ctypes.c_double)]
 
     def as_dict(self):

@@ -27,8 +27,9 @@ struct pd_ctx {
   std::string err;
   // settings
   int step_prec = PD_FP64;
-  double p_rtol = 1e-10, v_rtol = 1e-12, inner_rtol = 1e-4;
+  double p_rtol = 1e-10, v_rtol = 1e-12, ru_factor = 0.1;
   int maxit = 100000, convection = 1, timing = 0, check_every = 32;
+  int kz = 0, tiles_per_wg = 0, prefetch = 1;   // operator-kernel launch shape
   // device workspace
   CgState* st = nullptr;       // CG state of the (inner) solve
   CgState* st2 = nullptr;      // outer refinement / residual norms
@@ -96,6 +97,9 @@ pdk::ApplyLaunch base_launch(const pd_ctx* c, int op, bool fp32) {
   L.fp32 = fp32;
   op_coefs(c, op, &L.alpha, L.coef);
   L.tab = &c->optab;
+  L.kz_override = c->kz;
+  L.tiles_per_wg = c->tiles_per_wg;
+  L.prefetch = c->prefetch;
   return L;
 }
 
@@ -127,123 +131,241 @@ int read_state(pd_ctx* c, const CgState* dev, CgState* host, hipStream_t s) {
   return PD_OK;
 }
 
-// Conjugate gradients on A x = b in precision T (FP64 or FP32 vectors, FP64 scalars).
-//   r, pa, pb, q : workspace vectors; b may equal r when x_zero (then b is consumed).
-//   Returns PD_OK and fills iters/rel_recur/status from the device state.
+// Device buffers of one CG run: residual r, the two search-direction buffers (iteration k reads
+// buf[k % 2] and writes buf[(k + 1) % 2]) and q = A p.
 struct CgBuffers {
   void *r, *pa, *pb, *q;
 };
 
-int run_cg(pd_ctx* c, int op, bool fp32, void* x, const void* b, bool x_zero, double rtol,
-           int maxit, CgState* st, CgBuffers B, hipStream_t s, bool timed, int* iters,
-           double* rel_recur, int* status) {
-  const long long n = c->ndof;
-  const int nrho = (int)pdk::stream_grid(n);
-  double* rho[2] = {c->rhopart, c->rhopart + pdk::kMaxStreamPartials};
-  PD_HIP(c, pdk::launch_state_init(st, maxit, rtol, s));
-  int rc = dot_into(c, fp32, b, b, st, pdk::FIN_BNORM, s);
-  if (rc) return rc;
-  // r_0 and the partials of <r_0, r_0> (iteration 0 reads them)
-  if (x_zero) {
-    if (b != B.r) {
-      if (fp32) return fail(c, PD_EINVAL, "internal: FP32 CG expects b == r");
-      PD_HIP(c, pdk::launch_residual((const double*)b, nullptr, (double*)B.r, n, rho[0], s));
-    } else {
-      PD_HIP(c, pdk::launch_dot(fp32, B.r, B.r, n, rho[0], s));
-    }
-  } else {
-    if (fp32) return fail(c, PD_EINVAL, "internal: FP32 CG needs a zero start");
-    rc = plain_apply(c, op, false, x, B.q, s);
-    if (rc) return rc;
-    PD_HIP(c, pdk::launch_residual((const double*)b, (const double*)B.q, (double*)B.r, n, rho[0], s));
-  }
-  PD_HIP(c, pdk::launch_zero(fp32, B.pa, n, s));
+// A chunked conjugate-gradient run on the device, FP64 or FP32 vectors (FP64 scalars).
+// Iteration k = apply kernel (p_k = r_k + beta_k p_{k-1}, q = A p_k, partials of <p_k, q>) +
+// update kernel (x += alpha p_k, r -= alpha q, partials of <r_{k+1}, r_{k+1}>). The run can be
+// stopped by a host predicate on the polled state and resumed at the exact iteration.
+struct CgRun {
+  int op = 0;
+  bool fp32 = false;
+  void* x = nullptr;
+  CgBuffers B{};
+  CgState* st = nullptr;
+  hipStream_t s = nullptr;
+  bool timed = false;
+  int k = 0;                 // next iteration to launch / iterations completed after a stop
+  int nrho = 0, nsig = 0;
+  double* rho[2] = {nullptr, nullptr};
+  pdk::ApplyLaunch L;
+};
 
-  pdk::ApplyLaunch L = base_launch(c, op, fp32);
-  L.fuse = 1;
-  L.st = st;
-  L.nrho = nrho;
-  L.sigpart = c->sigpart;
-  const int nsig = (int)pdk::apply_blocks(L);
-  void* pold = B.pa;
-  void* pnew = B.pb;
+// Prepare a run whose residual r_0 and the partials of <r_0, r_0> (in rho[0]) are in place and
+// whose CG state holds tol2 / maxit.
+int cg_prepare(pd_ctx* c, CgRun* R) {
+  R->nrho = (int)pdk::stream_grid(c->ndof);
+  R->rho[0] = c->rhopart;
+  R->rho[1] = c->rhopart + pdk::kMaxStreamPartials;
+  R->L = base_launch(c, R->op, R->fp32);
+  R->L.fuse = 1;
+  R->L.st = R->st;
+  R->L.nrho = R->nrho;
+  R->L.sigpart = c->sigpart;
+  R->nsig = (int)pdk::apply_blocks(R->L);
+  R->k = 0;
+  PD_HIP(c, pdk::launch_zero(R->fp32, R->B.pa, c->ndof, R->s));
+  return PD_OK;
+}
+
+int cg_launch(pd_ctx* c, CgRun* R) {
+  const int k = R->k;
+  void* buf[2] = {R->B.pa, R->B.pb};
+  pdk::ApplyLaunch& L = R->L;
+  L.k = k;
+  L.rho_cur = R->rho[k & 1];
+  L.x = R->B.r;
+  L.pold = buf[k & 1];
+  L.pnew = buf[(k + 1) & 1];
+  L.y = R->B.q;
+  if (R->timed) {
+    while (c->tev.size() < 2 * (size_t)(k + 1)) {
+      hipEvent_t e;
+      PD_HIP(c, hipEventCreate(&e));
+      c->tev.push_back(e);
+    }
+    PD_HIP(c, hipEventRecord(c->tev[2 * k], R->s));
+  }
+  PD_HIP(c, pdk::launch_apply(L, R->s));
+  if (R->timed) PD_HIP(c, hipEventRecord(c->tev[2 * k + 1], R->s));
+  PD_HIP(c, pdk::launch_cg_update(R->fp32, R->x, buf[(k + 1) & 1], R->B.q, R->B.r, c->ndof, R->st,
+                                  k, c->sigpart, R->nsig, R->rho[(k + 1) & 1], R->s));
+  ++R->k;
+  return PD_OK;
+}
+
+// Launch iterations in chunks until the device reports done or stop(polled state) is true; the
+// next chunk is already queued while a chunk's state is inspected. On return the stream is
+// synchronised, *fin holds the final state and R->k the number of completed iterations.
+template <typename Pred>
+int cg_run_until(pd_ctx* c, CgRun* R, int maxit, Pred stop, CgState* fin) {
   const int chunk = c->check_every > 0 ? c->check_every : 32;
   int slot = 0;
   bool pending[2] = {false, false};
   bool finished = false;
-  const int tslot = fp32 ? 1 : 0;
-  size_t nt = 0;
-  int k = 0;
   while (!finished) {
-    for (int i = 0; i < chunk; ++i, ++k) {
-      L.k = k;
-      L.rho_cur = rho[k & 1];
-      L.x = B.r;
-      L.pold = pold;
-      L.pnew = pnew;
-      L.y = B.q;
-      if (timed) {
-        if (c->tev.size() < 2 * (nt + 1)) {
-          hipEvent_t e0, e1;
-          PD_HIP(c, hipEventCreate(&e0));
-          PD_HIP(c, hipEventCreate(&e1));
-          c->tev.push_back(e0);
-          c->tev.push_back(e1);
-        }
-        PD_HIP(c, hipEventRecord(c->tev[2 * nt], s));
-      }
-      PD_HIP(c, pdk::launch_apply(L, s));
-      if (timed) {
-        PD_HIP(c, hipEventRecord(c->tev[2 * nt + 1], s));
-        ++nt;
-      }
-      PD_HIP(c, pdk::launch_cg_update(fp32, x, pnew, B.q, B.r, n, st, k, c->sigpart, nsig,
-                                      rho[(k + 1) & 1], s));
-      void* t = pold;
-      pold = pnew;
-      pnew = t;
+    for (int i = 0; i < chunk; ++i) {
+      int rc = cg_launch(c, R);
+      if (rc) return rc;
     }
-    PD_HIP(c, hipMemcpyAsync(&c->hst[slot], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    PD_HIP(c, hipEventRecord(c->ev[slot], s));
+    PD_HIP(c, hipMemcpyAsync(&c->hst[slot], R->st, sizeof(CgState), hipMemcpyDeviceToHost, R->s));
+    PD_HIP(c, hipEventRecord(c->ev[slot], R->s));
     pending[slot] = true;
     const int prev = slot ^ 1;
     if (pending[prev]) {
       PD_HIP(c, hipEventSynchronize(c->ev[prev]));
       pending[prev] = false;
-      if (c->hst[prev].done) finished = true;
+      if (c->hst[prev].done || stop(c->hst[prev])) finished = true;
     }
     slot ^= 1;
-    if (k > maxit + 2 * chunk) finished = true;
+    if (R->k > maxit + 2 * chunk) finished = true;
   }
-  CgState fin;
-  rc = read_state(c, st, &fin, s);
+  int rc = read_state(c, R->st, fin, R->s);
   if (rc) return rc;
-  *iters = fin.iter;
-  *rel_recur = fin.bnorm2 > 0 ? std::sqrt(fin.rho / fin.bnorm2) : 0.0;
-  *status = fin.done ? fin.status : PD_ENOCONV;
-  if (timed) {
-    const size_t use = (size_t)fin.iter < nt ? (size_t)fin.iter : nt;
-    for (size_t i = 0; i < use; ++i) {
-      float ms = 0.f;
-      PD_HIP(c, hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]));
+  if (fin->done) R->k = fin->iter;
+  return PD_OK;
+}
+
+void cg_collect_timing(pd_ctx* c, const CgRun& R) {
+  if (!R.timed) return;
+  const int tslot = R.fp32 ? 1 : 0;
+  for (int i = 0; i < R.k && 2 * (size_t)i + 1 < c->tev.size(); ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]) == hipSuccess) {
       c->t_ms[tslot] += ms;
       c->t_cnt[tslot] += 1;
     }
   }
-  return PD_OK;
 }
 
-// ||b - A x|| / ||b|| in FP64 (uses q64, r64 and st2).
-int true_residual(pd_ctx* c, int op, const double* b, const double* x, double bnorm,
-                  hipStream_t s, double* rel) {
+// r64 = b - A x in FP64 (projected for the pressure operator); *norm = ||r64||.
+int fp64_residual(pd_ctx* c, int op, const double* b, const double* x, hipStream_t s,
+                  double* norm) {
   int rc = plain_apply(c, op, false, x, c->q64, s);
   if (rc) return rc;
   PD_HIP(c, pdk::launch_residual(b, c->q64, c->r64, c->ndof, c->tmppart, s));
-  PD_HIP(c, pdk::launch_finalize(c->tmppart, (int)pdk::stream_grid(c->ndof), c->st2, pdk::FIN_AUX, s));
+  if (op == PD_OP_PRESSURE) {
+    rc = project_null(c, false, c->r64, s);
+    if (rc) return rc;
+  }
+  rc = dot_into(c, false, c->r64, c->r64, c->st2, pdk::FIN_AUX, s);
+  if (rc) return rc;
   CgState h;
   rc = read_state(c, c->st2, &h, s);
   if (rc) return rc;
-  *rel = bnorm > 0 ? std::sqrt(h.aux) / bnorm : std::sqrt(h.aux);
+  *norm = std::sqrt(h.aux);
+  return PD_OK;
+}
+
+// FP64 conjugate gradients from the initial guess in x.
+int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, double bnorm, int maxit,
+               bool timed, pd_solve_info* inf, hipStream_t s) {
+  CgRun R;
+  R.op = op;
+  R.fp32 = false;
+  R.x = x;
+  R.B = CgBuffers{c->r64, c->pa64, c->pb64, c->q64};
+  R.st = c->st;
+  R.s = s;
+  R.timed = timed;
+  int rc = plain_apply(c, op, false, x, c->q64, s);
+  if (rc) return rc;
+  PD_HIP(c, pdk::launch_residual(b, c->q64, c->r64, c->ndof, c->rhopart, s));
+  PD_HIP(c, pdk::launch_state_set(c->st, maxit, rtol * rtol * bnorm * bnorm, s));
+  if ((rc = cg_prepare(c, &R))) return rc;
+  CgState fin;
+  rc = cg_run_until(c, &R, maxit, [](const CgState&) { return false; }, &fin);
+  if (rc) return rc;
+  cg_collect_timing(c, R);
+  inf->iters = R.k;
+  inf->outer_iters = 1;
+  inf->rel_res_recur = std::sqrt(fin.rho) / bnorm;
+  inf->status = fin.done ? fin.status : PD_ENOCONV;
+  return PD_OK;
+}
+
+// FP32 conjugate gradients with FP64 residual replacement: one CG run on FP32 vectors (r, p,
+// A p and the correction d; FP64 dot products). Whenever the recurrence residual has dropped by
+// ru_factor since the last replacement, or meets the tolerance, the correction is flushed into
+// the FP64 solution (x += s d), the true residual b - A x is recomputed in FP64 and replaces the
+// FP32 residual. The search direction is kept, so the run keeps its Krylov information (unlike
+// restarted refinement). Stops on the FP64 residual.
+int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, double bnorm,
+                 int maxit, bool timed, pd_solve_info* inf, hipStream_t s) {
+  const long long n = c->ndof;
+  double res = 0.0;
+  int rc = fp64_residual(c, op, b, x, s, &res);
+  if (rc) return rc;
+  inf->outer_iters = 0;
+  inf->iters = 0;
+  inf->rel_res_recur = res / bnorm;
+  if (!std::isfinite(res)) {
+    inf->status = PD_EBREAKDOWN;
+    return PD_OK;
+  }
+  if (res <= rtol * bnorm) {
+    inf->status = PD_OK;
+    return PD_OK;
+  }
+  const double scale = res;                     // the FP32 vectors hold r / scale
+  const double tol_rel = rtol * bnorm / scale;  // recurrence tolerance in scaled units
+  CgRun R;
+  R.op = op;
+  R.fp32 = true;
+  R.x = c->d32;
+  R.B = CgBuffers{c->r32, c->pa32, c->pb32, c->q32};
+  R.st = c->st;
+  R.s = s;
+  R.timed = timed;
+  PD_HIP(c, pdk::launch_zero(true, c->d32, n, s));
+  PD_HIP(c, pdk::launch_to_f32_dot(c->r64, c->r32, n, 1.0 / scale, c->rhopart, s));
+  PD_HIP(c, pdk::launch_state_set(c->st, maxit, tol_rel * tol_rel, s));
+  if ((rc = cg_prepare(c, &R))) return rc;
+  double ref = 1.0;                             // scaled residual norm at the last replacement
+  const double f = c->ru_factor;
+  inf->status = PD_ENOCONV;
+  for (;;) {
+    CgState fin;
+    rc = cg_run_until(c, &R, maxit,
+                      [&](const CgState& h) { return std::sqrt(h.rho) <= f * ref; }, &fin);
+    if (rc) return rc;
+    // flush the FP32 correction and recompute the true residual in FP64
+    PD_HIP(c, pdk::launch_flush_f32(x, c->d32, n, scale, s));
+    rc = fp64_residual(c, op, b, x, s, &res);
+    if (rc) return rc;
+    ++inf->outer_iters;
+    inf->rel_res_recur = res / bnorm;
+    if (!std::isfinite(res) || (fin.done && fin.status == PD_EBREAKDOWN)) {
+      inf->status = PD_EBREAKDOWN;
+      break;
+    }
+    if (res <= rtol * bnorm) {
+      inf->status = PD_OK;
+      break;
+    }
+    if (R.k >= maxit) {
+      inf->status = PD_ENOCONV;
+      break;
+    }
+    // residual replacement: r32 = r64 / scale with the partials of <r32, r32> for iteration R.k.
+    // If the FP32 recurrence residual had drifted well below the true one, beta would be huge
+    // and the old direction would swamp the new residual: restart the direction (p_old = 0).
+    const double rec = std::sqrt(fin.rho);
+    if (!(res / scale <= 4.0 * rec)) {
+      void* buf[2] = {R.B.pa, R.B.pb};
+      PD_HIP(c, pdk::launch_zero(true, buf[R.k & 1], n, s));
+      ++inf->restarts;
+    }
+    PD_HIP(c, pdk::launch_to_f32_dot(c->r64, c->r32, n, 1.0 / scale, R.rho[R.k & 1], s));
+    PD_HIP(c, pdk::launch_state_set(c->st, maxit, tol_rel * tol_rel, s));
+    ref = res / scale;
+  }
+  cg_collect_timing(c, R);
+  inf->iters = R.k;
   return PD_OK;
 }
 
@@ -259,92 +381,36 @@ int solve(pd_ctx* c, int op, int prec, const double* b_in, double* x, double rto
   const long long n = c->ndof;
   PD_HIP(c, hipEventRecord(c->t0, s));
   const double* b = b_in;
+  int rc;
   if (op == PD_OP_PRESSURE) {
     PD_HIP(c, pdk::launch_axpby(1.0, b_in, 0.0, c->bw64, n, s));
-    int rc = project_null(c, false, c->bw64, s);
-    if (rc) return rc;
-    rc = project_null(c, false, x, s);
-    if (rc) return rc;
+    if ((rc = project_null(c, false, c->bw64, s))) return rc;
+    if ((rc = project_null(c, false, x, s))) return rc;
     b = c->bw64;
   }
   const bool timed = c->timing && op == PD_OP_PRESSURE;
-  // ||b||
-  int rc = dot_into(c, false, b, b, c->st2, pdk::FIN_AUX, s);
-  if (rc) return rc;
+  if ((rc = dot_into(c, false, b, b, c->st2, pdk::FIN_AUX, s))) return rc;
   CgState h;
-  rc = read_state(c, c->st2, &h, s);
-  if (rc) return rc;
+  if ((rc = read_state(c, c->st2, &h, s))) return rc;
   const double bnorm = std::sqrt(h.aux);
   pd_solve_info inf{};
   inf.status = PD_OK;
   if (bnorm == 0.0) {
     PD_HIP(c, pdk::launch_zero(false, x, n, s));
+  } else if (!std::isfinite(bnorm)) {
+    inf.status = PD_EBREAKDOWN;
   } else if (prec == PD_FP64) {
-    CgBuffers B{c->r64, c->pa64, c->pb64, c->q64};
-    rc = run_cg(c, op, false, x, b, false, rtol, maxit, c->st, B, s, timed, &inf.iters,
-                &inf.rel_res_recur, &inf.status);
-    if (rc) return rc;
-    inf.outer_iters = 1;
+    if ((rc = solve_fp64(c, op, b, x, rtol, bnorm, maxit, timed, &inf, s))) return rc;
   } else {
-    CgBuffers B{c->r32, c->pa32, c->pb32, c->q32};
-    int total = 0, outer = 0;
-    double res = 0.0;
-    inf.status = PD_ENOCONV;
-    for (outer = 0; outer < 60; ++outer) {
-      rc = plain_apply(c, op, false, x, c->q64, s);
-      if (rc) return rc;
-      PD_HIP(c, pdk::launch_axpby(-1.0, c->q64, 0.0, c->r64, n, s));
-      PD_HIP(c, pdk::launch_axpby(1.0, b, 1.0, c->r64, n, s));
-      if (op == PD_OP_PRESSURE) {
-        rc = project_null(c, false, c->r64, s);
-        if (rc) return rc;
-      }
-      rc = dot_into(c, false, c->r64, c->r64, c->st2, pdk::FIN_AUX, s);
-      if (rc) return rc;
-      rc = read_state(c, c->st2, &h, s);
-      if (rc) return rc;
-      res = std::sqrt(h.aux) / bnorm;
-      if (!std::isfinite(res)) {
-        inf.status = PD_EBREAKDOWN;
-        break;
-      }
-      if (res <= rtol) {
-        inf.status = PD_OK;
-        break;
-      }
-      if (total >= maxit) {
-        inf.status = PD_ENOCONV;
-        break;
-      }
-      double tin = c->inner_rtol;
-      const double need = 0.3 * rtol / res;
-      if (need > tin) tin = need;
-      if (tin > 0.5) tin = 0.5;
-      PD_HIP(c, pdk::launch_to_f32_scaled(c->r64, c->r32, n, c->st2, s));
-      PD_HIP(c, pdk::launch_zero(true, c->d32, n, s));
-      int it = 0, st_in = 0;
-      double rr = 0;
-      rc = run_cg(c, op, true, c->d32, c->r32, true, tin, maxit - total, c->st, B, s, timed,
-                  &it, &rr, &st_in);
-      if (rc) return rc;
-      total += it;
-      PD_HIP(c, pdk::launch_add_f32_scaled(x, c->d32, n, c->st2, s));
-      if (st_in == PD_EBREAKDOWN) {
-        inf.status = PD_EBREAKDOWN;
-        break;
-      }
-    }
-    inf.iters = total;
-    inf.outer_iters = outer + 1;
-    inf.rel_res_recur = res;
+    if ((rc = solve_refine(c, op, b, x, rtol, bnorm, maxit, timed, &inf, s))) return rc;
   }
   if (op == PD_OP_PRESSURE) {
-    rc = project_null(c, false, x, s);
-    if (rc) return rc;
+    if ((rc = project_null(c, false, x, s))) return rc;
   }
-  if (bnorm > 0.0) {
-    rc = true_residual(c, op, b, x, bnorm, s, &inf.rel_res_true);
-    if (rc) return rc;
+  if (bnorm > 0.0 && std::isfinite(bnorm)) {
+    double res = 0.0;
+    if ((rc = fp64_residual(c, op, b, x, s, &res))) return rc;
+    inf.rel_res_true = res / bnorm;
   }
   PD_HIP(c, hipEventRecord(c->t1, s));
   PD_HIP(c, hipEventSynchronize(c->t1));
@@ -744,9 +810,9 @@ int pd_configure(pd_ctx* c, int key, double v) {
     case PD_CFG_CONVECTION:
       c->convection = v != 0.0;
       break;
-    case PD_CFG_INNER_RTOL:
-      if (!(v > 0 && v < 1)) return fail(c, PD_EINVAL, "inner rtol must be in (0, 1)");
-      c->inner_rtol = v;
+    case PD_CFG_RU_FACTOR:
+      if (!(v > 0 && v < 1)) return fail(c, PD_EINVAL, "replacement factor must be in (0, 1)");
+      c->ru_factor = v;
       break;
     case PD_CFG_TIMING:
       c->timing = v != 0.0;
@@ -754,6 +820,17 @@ int pd_configure(pd_ctx* c, int key, double v) {
     case PD_CFG_CHECK_EVERY:
       if (!(v >= 1)) return fail(c, PD_EINVAL, "check interval must be >= 1");
       c->check_every = (int)v;
+      break;
+    case PD_CFG_KZ:
+      if (!(v >= 0)) return fail(c, PD_EINVAL, "planes per segment must be >= 0");
+      c->kz = (int)v;
+      break;
+    case PD_CFG_TILES_PER_WG:
+      if (!(v >= 0)) return fail(c, PD_EINVAL, "tiles per workgroup must be >= 0");
+      c->tiles_per_wg = (int)v;
+      break;
+    case PD_CFG_PREFETCH:
+      c->prefetch = v != 0.0;
       break;
     default:
       return fail(c, PD_EINVAL, "unknown configuration key");

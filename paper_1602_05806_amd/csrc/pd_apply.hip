@@ -69,7 +69,7 @@ template <typename T, int N, typename F>
 __device__ __forceinline__ void line3(const Blk<T, N>& B, const T (&vl)[N + 1],
                                       const T (&vc)[N + 1], const T (&vr)[N + 1], F&& out) {
   constexpr int n = N + 1;
-  constexpr bool pairs = 2 * 3 * n * (int)sizeof(T) / 4 <= 48;   // SGPRs of two rows
+  constexpr bool pairs = 2 * 3 * n * (int)sizeof(T) / 4 <= 36;   // SGPRs of two rows
   if constexpr (pairs) {
 #pragma unroll 1
     for (int l = 0; l + 1 < n; l += 2) {
@@ -98,22 +98,24 @@ template <typename T, int N>
 struct Tile2D {
   static constexpr int n = N + 1, NC = n * n;
   static constexpr bool fits(int tx, int ty) {
-    return (2 * tx * ty + 2 * tx + 2 * ty) * NC * (int)sizeof(T) <= 40960;
+    return ((tx + 2) * (ty + 2) + tx * ty) * NC * (int)sizeof(T) <= 40960;
   }
   static constexpr int TX = fits(8, 8) ? 8 : fits(8, 4) ? 8 : fits(4, 4) ? 4 : fits(4, 2) ? 4 : 2;
   static constexpr int TY = fits(8, 8) ? 8 : fits(8, 4) ? 4 : fits(4, 4) ? 4 : fits(4, 2) ? 2 : 2;
 };
 
-template <typename T, int N, int FUSE>
+// 2D: LDS holds the tile and its face halos as a (TX+2) x (TY+2) box of cells (corners unused),
+// box cell (bi, bj) = tile cell (bi-1, bj-1). Box row bj is one contiguous run of cells in global
+// memory unless it crosses the periodic seam, so staging is a flat copy per row.
+template <typename T, int N, int FUSE, int PF>
 __global__ __launch_bounds__(256) void k_apply2d(ApplyArgs<T> a, Blk<T, N> B) {
   using TL = Tile2D<T, N>;
   constexpr int n = N + 1, NC = n * n, TX = TL::TX, TY = TL::TY, NT = TX * TY;
-  constexpr int S_XL = NT, S_XR = NT + TY, S_YL = NT + 2 * TY, S_YR = NT + 2 * TY + TX;
-  constexpr int NS = NT + 2 * TY + 2 * TX;
-  constexpr int NW = 256 / 64;                 // waves
-  constexpr int SPW = (NS + NW - 1) / NW;      // cells staged per wave
-  constexpr int LR = (NC + 63) / 64;           // lane rounds per cell
-  __shared__ T xs[NS * NC];
+  constexpr int BX = TX + 2;                    // box width in cells
+  constexpr int RI = BX * NC;                   // elements of an interior box row
+  constexpr int RH = TX * NC;                   // elements of a halo box row (no corners)
+  constexpr int JI = (RI + 255) / 256, JH = (RH + 255) / 256;
+  __shared__ T xs[(TY + 2) * BX * NC];
   __shared__ T ys[NT * NC];
   if (FUSE) {
     if (a.st->done) return;
@@ -121,117 +123,132 @@ __global__ __launch_bounds__(256) void k_apply2d(ApplyArgs<T> a, Blk<T, N> B) {
   const T* __restrict__ xg = a.x;
   const T* __restrict__ pg = a.pold;
   T* __restrict__ png = a.pnew;
-  const unsigned tile = xcd_remap(blockIdx.x, gridDim.x);
-  const int tx0 = (int)(tile % (unsigned)a.ntx) * TX;
-  const int ty0 = (int)(tile / (unsigned)a.ntx) * TY;
-  // Staging: each wave copies whole cells (slot -> cell mapping is wave-uniform, so it runs on
-  // the scalar unit); every global load is issued before anything waits on memory.
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  __shared__ int sbase[NS];      // cell index of each slot (written and read by its own wave)
-  __shared__ int sown[NS];
-  T rv[SPW][LR], pv[SPW][LR];
+  T* __restrict__ yg = a.y;
+  // Persistent workgroups: this one owns the contiguous tile range [t_begin, t_end) (each XCD
+  // gets a contiguous range of workgroups, so neighbouring tiles share an L2).
+  const unsigned lw = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntiles = a.ntx * a.nty;
+  const int t_begin = (int)lw * a.kz;           // kz = tiles per workgroup in 2D
+  const int t_end = min(t_begin + a.kz, ntiles);
+  const int tid = threadIdx.x;
+  T rvi[TY][JI], pvi[TY][JI], rvh[2][JH], pvh[2][JH];
+
+  // global element index of box element e of box row bj (bj in 0..TY+1) of the tile at (tx0, ty0)
+  auto gindex = [&](int tx0, int ty0, int bj, int e) -> size_t {
+    const int first = (bj == 0 || bj == TY + 1) ? 0 : -1;   // first tile column of the row
+    const int cr = e / NC, l = e - cr * NC;
+    const int gi = wrap_small(tx0 + first + cr, a.nx);
+    const int gj = wrap_small(ty0 + bj - 1, a.ny);
+    return ((size_t)gj * a.nx + gi) * NC + l;
+  };
+  auto stage_load = [&](int tile) {
+    const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
+    const bool flat = tx0 >= 1 && tx0 + TX + 1 <= a.nx;        // no row crosses the x seam
 #pragma unroll
-  for (int i = 0; i < SPW; ++i) {
-    const int s = wave + NW * i;
-    if (s < NS) {
-      int ci, cj;
-      if (s < NT) { ci = s % TX; cj = s / TX; }
-      else if (s < S_XR) { ci = -1; cj = s - S_XL; }
-      else if (s < S_YL) { ci = TX; cj = s - S_XR; }
-      else if (s < S_YR) { ci = s - S_YL; cj = -1; }
-      else { ci = s - S_YR; cj = TY; }
-      const int ui = tx0 + ci, uj = ty0 + cj;
-      const int cell = wrap_small(uj, a.ny) * a.nx + wrap_small(ui, a.nx);
-      if (lane == 0) {
-        sbase[s] = cell;
-        sown[s] = s < NT && ui < a.nx && uj < a.ny;
-      }
-      const size_t cb = (size_t)cell * NC;
+    for (int bj = 0; bj < TY + 2; ++bj) {
+      const bool halo = bj == 0 || bj == TY + 1;
+      const int gj = wrap_small(ty0 + bj - 1, a.ny);
+      const size_t row0 = ((size_t)gj * a.nx + (halo ? tx0 : tx0 - 1)) * NC;
+      constexpr int J = JI > JH ? JI : JH;
 #pragma unroll
-      for (int r = 0; r < LR; ++r) {
-        const int l = lane + 64 * r;
-        if (l < NC) {
-          rv[i][r] = xg[cb + l];
-          if (FUSE) pv[i][r] = pg[cb + l];
+      for (int j = 0; j < J; ++j) {
+        const int e = tid + 256 * j;
+        if (e < (halo ? RH : RI)) {
+          const size_t g = flat ? row0 + e : gindex(tx0, ty0, bj, e);
+          T rv = xg[g], pv = T(0);
+          if (FUSE) pv = pg[g];
+          if (halo) {
+            if (j < JH) { rvh[bj ? 1 : 0][j] = rv; pvh[bj ? 1 : 0][j] = pv; }
+          } else if (j < JI) {
+            rvi[bj - 1][j] = rv;
+            pvi[bj - 1][j] = pv;
+          }
         }
       }
     }
-  }
+  };
+
+  if (t_begin < t_end) stage_load(t_begin);
   T beta = T(0);
   if (FUSE) {
     const IterScalars sc = iteration_scalars<256>(a.st, a.k, a.rho_cur, a.nrho);
     if (sc.stop) return;
     beta = (T)sc.beta;
   }
+  double dot = 0.0;
+  for (int tile = t_begin; tile < t_end; ++tile) {
+    const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
+    // registers -> LDS (p = r + beta p_old formed here; owned cells also stored to global)
 #pragma unroll
-  for (int i = 0; i < SPW; ++i) {
-    const int s = wave + NW * i;
-    if (s < NS) {
-      const size_t cb = (size_t)sbase[s] * NC;
-      const bool own = FUSE && sown[s];
+    for (int bj = 0; bj < TY + 2; ++bj) {
+      const bool halo = bj == 0 || bj == TY + 1;
+      constexpr int J = JI > JH ? JI : JH;
 #pragma unroll
-      for (int r = 0; r < LR; ++r) {
-        const int l = lane + 64 * r;
-        if (l < NC) {
-          T v = rv[i][r];
+      for (int j = 0; j < J; ++j) {
+        const int e = tid + 256 * j;
+        if (e < (halo ? RH : RI) && (halo ? j < JH : j < JI)) {
+          T v = halo ? rvh[bj ? 1 : 0][j] : rvi[bj - 1][j];
           if (FUSE) {
-            v = v + beta * pv[i][r];
-            if (own) png[cb + l] = v;
+            v = v + beta * (halo ? pvh[bj ? 1 : 0][j] : pvi[bj - 1][j]);
+            if (!halo) {
+              const int bi = e / NC;                 // box column: own cells are 1..TX
+              const int ui = tx0 + bi - 1, uj = ty0 + bj - 1;
+              if (bi >= 1 && bi <= TX && ui < a.nx && uj < a.ny)
+                png[((size_t)uj * a.nx + ui) * NC + (e - bi * NC)] = v;
+            }
           }
-          xs[s * NC + l] = v;
+          xs[(bj * BX + (halo ? 1 : 0)) * NC + e] = v;
         }
       }
     }
-  }
-  __syncthreads();
+    __syncthreads();
+    if (PF && tile + 1 < t_end) stage_load(tile + 1);   // in flight during the compute below
 
-  // x-lines: (cell c, l2); nodes l1 = 0..N
-  for (int L = threadIdx.x; L < NT * n; L += 256) {
-    const int c = L / n, l2 = L - c * n;
-    const int ci = c % TX, cj = c / TX;
-    const int sl = (ci == 0) ? S_XL + cj : c - 1;
-    const int sr = (ci == TX - 1) ? S_XR + cj : c + 1;
-    T vl[n], vc[n], vr[n];
+    // x-lines: (cell c, l2); nodes l1 = 0..N
+    for (int L = tid; L < NT * n; L += 256) {
+      const int c = L / n, l2 = L - c * n;
+      const int ci = c % TX, cj = c / TX;
+      const int bc = ((cj + 1) * BX + ci + 1) * NC + l2 * n;
+      T vl[n], vc[n], vr[n];
 #pragma unroll
-    for (int m = 0; m < n; ++m) {
-      vl[m] = xs[sl * NC + l2 * n + m];
-      vc[m] = xs[c * NC + l2 * n + m];
-      vr[m] = xs[sr * NC + l2 * n + m];
-    }
-    const T wgt = a.c0 * B.w[l2];
-    line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + l2 * n + l1] = wgt * v; });
-  }
-  __syncthreads();
-
-  // y-lines: (cell c, l1); nodes l2 = 0..N; final values are stored here
-  double dot = 0.0;
-  for (int L = threadIdx.x; L < NT * n; L += 256) {
-    const int c = L / n, l1 = L - c * n;
-    const int ci = c % TX, cj = c / TX;
-    const int sl = (cj == 0) ? S_YL + ci : c - TX;
-    const int sr = (cj == TY - 1) ? S_YR + ci : c + TX;
-    T vl[n], vc[n], vr[n];
-#pragma unroll
-    for (int m = 0; m < n; ++m) {
-      vl[m] = xs[sl * NC + m * n + l1];
-      vc[m] = xs[c * NC + m * n + l1];
-      vr[m] = xs[sr * NC + m * n + l1];
-    }
-    const int ui = tx0 + ci, uj = ty0 + cj;
-    const bool valid = ui < a.nx && uj < a.ny;
-    const size_t base = ((size_t)uj * a.nx + ui) * NC;
-    const T wgt = a.c1 * B.w[l1];
-    const T wm = a.alpha * B.w[l1];
-    T* __restrict__ yg = a.y;
-    line3<T, N>(B, vl, vc, vr, [&](int l2, T v) {
-      const T xc = xs[c * NC + l2 * n + l1];
-      const T val = ys[c * NC + l2 * n + l1] + wgt * v + wm * B.w[l2] * xc;
-      if (valid) {
-        yg[base + l2 * n + l1] = val;
-        dot += (double)xc * (double)val;
+      for (int m = 0; m < n; ++m) {
+        vl[m] = xs[bc - NC + m];
+        vc[m] = xs[bc + m];
+        vr[m] = xs[bc + NC + m];
       }
-    });
+      const T wgt = a.c0 * B.w[l2];
+      line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + l2 * n + l1] = wgt * v; });
+    }
+    __syncthreads();
+
+    // y-lines: (cell c, l1); nodes l2 = 0..N; final values are stored here
+    for (int L = tid; L < NT * n; L += 256) {
+      const int c = L / n, l1 = L - c * n;
+      const int ci = c % TX, cj = c / TX;
+      const int bc = ((cj + 1) * BX + ci + 1) * NC + l1;
+      T vl[n], vc[n], vr[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        vl[m] = xs[bc - BX * NC + m * n];
+        vc[m] = xs[bc + m * n];
+        vr[m] = xs[bc + BX * NC + m * n];
+      }
+      const int ui = tx0 + ci, uj = ty0 + cj;
+      const bool valid = ui < a.nx && uj < a.ny;
+      const size_t base = ((size_t)uj * a.nx + ui) * NC;
+      const T wgt = a.c1 * B.w[l1];
+      const T wm = a.alpha * B.w[l1];
+      line3<T, N>(B, vl, vc, vr, [&](int l2, T v) {
+        const T xc = xs[bc + l2 * n];
+        const T val = ys[c * NC + l2 * n + l1] + wgt * v + wm * B.w[l2] * xc;
+        if (valid) {
+          yg[base + l2 * n + l1] = val;
+          dot += (double)xc * (double)val;
+        }
+      });
+    }
+    __syncthreads();
+    if (!PF && tile + 1 < t_end) stage_load(tile + 1);
   }
   if (FUSE) {
     const double s = block_sum_all<256>(dot);
@@ -248,7 +265,7 @@ struct Tile3D {
   static constexpr int NTH = TX * TY * (N + 1) * (N + 1);
 };
 
-template <typename T, int N, int FUSE>
+template <typename T, int N, int FUSE, int PF>
 __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<T, N> B) {
   constexpr int n = N + 1, NP = n * n, NC = n * n * n;
   constexpr int TX = Tile3D<N>::TX, TY = Tile3D<N>::TY, NT = TX * TY, NTH = Tile3D<N>::NTH;
@@ -278,7 +295,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     else { hi = s - S_YR; hj = TY; }
     hbase[s] = wrapi(ty0 + hj, a.ny) * a.nx + wrapi(tx0 + hi, a.nx);
   }
-  // (hbase is first read after the barrier that follows the first plane's staging)
+  __syncthreads();   // hbase ready
 
   const int t = threadIdx.x;
   const int c = t / NP, lp = t - c * NP;          // cell in the plane tile, z-line (l1 + n l2)
@@ -332,69 +349,79 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   const T wm = a.alpha * B.w[zl1] * B.w[zl2];
   double dot = 0.0;
 
-  for (int k = k0; k < k1; ++k) {
-    {
-      const size_t bn = zbase(k + 1);
-      const bool own_next = valid && (k + 1 < k1);
-      T pn[n];
+  // x/y halo cells of a plane: one wave per cell (wave-uniform addressing). When the register
+  // budget allows, plane k+1's halo is prefetched during plane k's compute.
+  constexpr int NWV = NTH / 64;                // full waves (a partial last wave stays idle)
+  static_assert(NWV >= 1, "3D tile needs at least one full wave");
+  constexpr int HPW = (NH + NWV - 1) / NWV;
+  constexpr int LR = (NC + 63) / 64;
+  constexpr bool PREF = PF && HPW * LR <= 8;
+  constexpr int HR = PREF ? HPW : 1;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int lane = t & 63;
+  T hv[HR][LR], hp[HR][LR];
+  auto halo_load = [&](int k) {
+    const size_t pb = (size_t)wrap_small(k, a.nz) * plane;
 #pragma unroll
-      for (int l3 = 0; l3 < n; ++l3) {
-        zn[l3] = xg[bn + l3 * NP];
-        if (FUSE) pn[l3] = pg[bn + l3 * NP];
-      }
-      if (FUSE) {
+    for (int i = 0; i < HR; ++i) {
+      const int s = NT + wave + NWV * i;
+      if (wave < NWV && s < NS) {
+        const size_t g = (pb + (size_t)hbase[s]) * NC;
 #pragma unroll
-        for (int l3 = 0; l3 < n; ++l3) {
-          zn[l3] = zn[l3] + beta * pn[l3];
-          if (own_next) png[bn + l3 * NP] = zn[l3];
+        for (int r = 0; r < LR; ++r) {
+          const int l = lane + 64 * r;
+          if (l < NC) {
+            hv[i][r] = xg[g + l];
+            if (FUSE) hp[i][r] = pg[g + l];
+          }
         }
       }
     }
+  };
+  auto halo_store = [&]() {
+#pragma unroll
+    for (int i = 0; i < HR; ++i) {
+      const int s = NT + wave + NWV * i;
+      if (wave < NWV && s < NS) {
+#pragma unroll
+        for (int r = 0; r < LR; ++r) {
+          const int l = lane + 64 * r;
+          if (l < NC) xs[s * NC + l] = FUSE ? (T)(hv[i][r] + beta * hp[i][r]) : hv[i][r];
+        }
+      }
+    }
+  };
+  auto halo_direct = [&](int k) {
+    const size_t pb = (size_t)wrap_small(k, a.nz) * plane;
+#pragma unroll 1
+    for (int i = 0; i < HPW; ++i) {
+      const int s = NT + wave + NWV * i;
+      if (wave < NWV && s < NS) {
+        const size_t g = (pb + (size_t)hbase[s]) * NC;
+        for (int l = lane; l < NC; l += 64)
+          xs[s * NC + l] = FUSE ? (T)(xg[g + l] + beta * pg[g + l]) : xg[g + l];
+      }
+    }
+  };
+  if constexpr (PREF) halo_load(k0);
+
+  for (int k = k0; k < k1; ++k) {
 #pragma unroll
     for (int l3 = 0; l3 < n; ++l3) xs[c * NC + l3 * NP + lp] = zc[l3];
-    if (k == k0) __syncthreads();   // hbase ready
-    const size_t pbase = (size_t)wrap_small(k, a.nz) * plane;
-    {
-      // halo cells of plane k: one wave per cell (wave-uniform addressing)
-      constexpr int NWV = NTH / 64;            // full waves (a partial last wave stays idle)
-      static_assert(NWV >= 1, "3D tile needs at least one full wave");
-      constexpr int HPW = (NH + NWV - 1) / NWV;
-      constexpr int LR = (NC + 63) / 64;
-      const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-      const int lane = t & 63;
-      constexpr int PRE = HPW * LR <= 8 ? HPW : 1;   // halo cells preloaded per batch
-#pragma unroll 1
-      for (int i0 = 0; i0 < HPW; i0 += PRE) {
-        T hv[PRE][LR], hp[PRE][LR];
-#pragma unroll
-        for (int i = 0; i < PRE; ++i) {
-          const int s = NT + wave + NWV * (i0 + i);
-          if (wave < NWV && i0 + i < HPW && s < NS) {
-            const size_t g = (pbase + (size_t)hbase[s]) * NC;
-#pragma unroll
-            for (int r = 0; r < LR; ++r) {
-              const int l = lane + 64 * r;
-              if (l < NC) {
-                hv[i][r] = xg[g + l];
-                if (FUSE) hp[i][r] = pg[g + l];
-              }
-            }
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < PRE; ++i) {
-          const int s = NT + wave + NWV * (i0 + i);
-          if (wave < NWV && i0 + i < HPW && s < NS) {
-#pragma unroll
-            for (int r = 0; r < LR; ++r) {
-              const int l = lane + 64 * r;
-              if (l < NC) xs[s * NC + l] = FUSE ? (T)(hv[i][r] + beta * hp[i][r]) : hv[i][r];
-            }
-          }
-        }
-      }
-    }
+    if constexpr (PREF) halo_store();
+    else halo_direct(k);
     __syncthreads();
+    // plane k+1: own z-line and (prefetch) halo, in flight during the x/y phases
+    const size_t bn = zbase(k + 1);
+    T pn[n];
+#pragma unroll
+    for (int l3 = 0; l3 < n; ++l3) {
+      zn[l3] = xg[bn + l3 * NP];
+      if (FUSE) pn[l3] = pg[bn + l3 * NP];
+    }
+    if constexpr (PREF) {
+      if (k + 1 < k1) halo_load(k + 1);
+    }
     {  // x-line (l2, l3) of cell c
       T vl[n], vc[n], vr[n];
 #pragma unroll
@@ -418,6 +445,14 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
                   [&](int l2, T v) { ys[c * NC + yl3 * NP + l2 * n + yl1] += wy * v; });
     }
     __syncthreads();
+    if (FUSE) {
+      const bool own_next = valid && (k + 1 < k1);
+#pragma unroll
+      for (int l3 = 0; l3 < n; ++l3) {
+        zn[l3] = zn[l3] + beta * pn[l3];
+        if (own_next) png[bn + l3 * NP] = zn[l3];
+      }
+    }
     {  // own z-line (l1, l2) from registers; final values
       const size_t bc = zbase(k);
       T* __restrict__ yg = a.y;
@@ -472,15 +507,21 @@ static Geom geometry(const ApplyLaunch& L) {
     using TL = Tile2D<T, N>;
     g.ntx = (nx + TL::TX - 1) / TL::TX;
     g.nty = (ny + TL::TY - 1) / TL::TY;
+    // persistent workgroups: about 4 per CU on 256 CUs, each over kz consecutive tiles
+    const long long ntiles = (long long)g.ntx * g.nty;
+    long long per = 1;   // one tile per workgroup measured best on 256^2 N=6 (2D grids are small)
+    if (L.tiles_per_wg > 0) per = L.tiles_per_wg;
+    g.kz = (int)per;
     g.ntz = 1;
-    g.kz = 1;
+    g.blocks = (unsigned long long)((ntiles + per - 1) / per);
+    return g;
   } else {
     using TL = Tile3D<N>;
     g.ntx = (nx + TL::TX - 1) / TL::TX;
     g.nty = (ny + TL::TY - 1) / TL::TY;
     const long long cols = (long long)g.ntx * g.nty;
-    // planes per segment: aim at >= 2048 workgroups, segments of at least 4 planes
-    int kz = (int)((cols * nz) / 2048);
+    // planes per segment: about 1024 workgroups, segments of at least 4 planes (64^3 N=4: 16)
+    int kz = (int)((cols * nz) / 1024);
     if (kz < 4) kz = 4;
     if (kz > nz) kz = nz;
     if (L.kz_override > 0) kz = L.kz_override < nz ? L.kz_override : nz;
@@ -518,16 +559,22 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   a.kz = g.kz;
   if (g.blocks > (unsigned long long)kMaxPartials) return hipErrorInvalidValue;
   const unsigned G = (unsigned)g.blocks;
+  const bool pf = L.prefetch != 0;
   if (L.dim == 2) {
-    if (L.fuse)
-      hipLaunchKernelGGL((k_apply2d<T, N, 1>), dim3(G), dim3(256), 0, s, a, B);
-    else
-      hipLaunchKernelGGL((k_apply2d<T, N, 0>), dim3(G), dim3(256), 0, s, a, B);
+    if (L.fuse) {
+      if (pf) hipLaunchKernelGGL((k_apply2d<T, N, 1, 1>), dim3(G), dim3(256), 0, s, a, B);
+      else hipLaunchKernelGGL((k_apply2d<T, N, 1, 0>), dim3(G), dim3(256), 0, s, a, B);
+    } else {
+      hipLaunchKernelGGL((k_apply2d<T, N, 0, 0>), dim3(G), dim3(256), 0, s, a, B);
+    }
   } else {
-    if (L.fuse)
-      hipLaunchKernelGGL((k_apply3d<T, N, 1>), dim3(G), dim3(Tile3D<N>::NTH), 0, s, a, B);
-    else
-      hipLaunchKernelGGL((k_apply3d<T, N, 0>), dim3(G), dim3(Tile3D<N>::NTH), 0, s, a, B);
+    constexpr int NTH = Tile3D<N>::NTH;
+    if (L.fuse) {
+      if (pf) hipLaunchKernelGGL((k_apply3d<T, N, 1, 1>), dim3(G), dim3(NTH), 0, s, a, B);
+      else hipLaunchKernelGGL((k_apply3d<T, N, 1, 0>), dim3(G), dim3(NTH), 0, s, a, B);
+    } else {
+      hipLaunchKernelGGL((k_apply3d<T, N, 0, 0>), dim3(G), dim3(NTH), 0, s, a, B);
+    }
   }
   return hipGetLastError();
 }

@@ -28,7 +28,9 @@ struct ApplyLaunch {
   const double* rho_cur = nullptr;
   int nrho = 0;
   double* sigpart = nullptr;
-  int kz_override = 0;
+  int kz_override = 0;       // 3D: planes per column segment (0 = automatic)
+  int tiles_per_wg = 0;      // 2D: tiles per persistent workgroup (0 = automatic)
+  int prefetch = 1;          // prefetch the next tile (2D) / next plane's halo (3D) into registers
   const OpTables* tab = nullptr;
 };
 
@@ -50,12 +52,6 @@ hipError_t launch_cg_update(bool fp32, void* x, const void* p, const void* q, vo
 // r = b - q (q == nullptr: r = b) with partials of <r, r>
 hipError_t launch_residual(const double* b, const double* q, double* r, long long n,
                            double* partials, hipStream_t s);
-// r32 = (float)(r64 / sqrt(st->aux))
-hipError_t launch_to_f32_scaled(const double* r64, float* r32, long long n, const CgState* st,
-                                hipStream_t s);
-// x64 += sqrt(st->aux) * (double)d32
-hipError_t launch_add_f32_scaled(double* x64, const float* d32, long long n, const CgState* st,
-                                 hipStream_t s);
 // y = a*x + b*y (FP64); with b == 0 the old y is not read (it may hold NaN)
 hipError_t launch_axpby(double a, const double* x, double b, double* y, long long n,
                         hipStream_t s);
@@ -63,6 +59,13 @@ hipError_t launch_axpby(double a, const double* x, double b, double* y, long lon
 hipError_t launch_zero(bool fp32, void* x, long long n, hipStream_t s);
 // reset CG state for a new solve: maxit, rtol (kept in aux for FIN_BNORM), done = 0
 hipError_t launch_state_init(CgState* st, int maxit, double rtol, hipStream_t s);
+// set tol2 / maxit of a CG run and clear its done flag (resumes a stopped run)
+hipError_t launch_state_set(CgState* st, int maxit, double tol2, hipStream_t s);
+// r32 = (float)(inv * r64) with partials of <r32, r32> (residual replacement)
+hipError_t launch_to_f32_dot(const double* r64, float* r32, long long n, double inv,
+                             double* partials, hipStream_t s);
+// x64 += scale * (double)d32, then d32 = 0 (flush of the FP32 correction)
+hipError_t launch_flush_f32(double* x64, float* d32, long long n, double scale, hipStream_t s);
 // y = W^{(x)d} x (nodal mass weights), FP64
 hipError_t launch_mass(int dim, int N, const double* w, const double* x, double* y,
                        long long ncells, hipStream_t s);

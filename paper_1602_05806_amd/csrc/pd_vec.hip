@@ -120,25 +120,6 @@ __global__ __launch_bounds__(kBlock) void k_residual(const double* __restrict__ 
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_to_f32_scaled(const double* __restrict__ r64,
-                                                          float* __restrict__ r32, long long n,
-                                                          const CgState* st) {
-  const double nrm2 = st->aux;
-  const double sc = nrm2 > 0.0 ? 1.0 / sqrt(nrm2) : 0.0;
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock)
-    r32[i] = (float)(sc * r64[i]);
-}
-
-__global__ __launch_bounds__(kBlock) void k_add_f32_scaled(double* __restrict__ x64,
-                                                           const float* __restrict__ d32,
-                                                           long long n, const CgState* st) {
-  const double sc = sqrt(st->aux);
-  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (long long)gridDim.x * kBlock)
-    x64[i] += sc * (double)d32[i];
-}
-
 __global__ __launch_bounds__(kBlock) void k_axpby(double a, const double* __restrict__ x, double b,
                                                   double* __restrict__ y, long long n) {
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
@@ -166,6 +147,42 @@ __global__ void k_state_init(CgState* st, int maxit, double rtol) {
     st->maxit = maxit;
     st->done = 0;
     st->status = 0;
+  }
+}
+
+// Set the stopping data of a CG run: tol2 (squared absolute residual bound), maxit; clears done.
+__global__ void k_state_set(CgState* st, int maxit, double tol2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->tol2 = tol2;
+    st->maxit = maxit;
+    st->done = 0;
+    st->status = 0;
+  }
+}
+
+// r32 = (float)(r64 * inv) with block partials of <r32, r32> (in FP64).
+__global__ __launch_bounds__(kBlock) void k_to_f32_dot(const double* __restrict__ r64,
+                                                       float* __restrict__ r32, long long n,
+                                                       double inv, double* __restrict__ partials) {
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    const float v = (float)(inv * r64[i]);
+    r32[i] = v;
+    s += (double)v * (double)v;
+  }
+  s = block_sum_all<kBlock>(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// x64 += scale * (double)d32; d32 = 0
+__global__ __launch_bounds__(kBlock) void k_flush_f32(double* __restrict__ x64,
+                                                      float* __restrict__ d32, long long n,
+                                                      double scale) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    x64[i] += scale * (double)d32[i];
+    d32[i] = 0.0f;
   }
 }
 
@@ -289,20 +306,6 @@ hipError_t launch_residual(const double* b, const double* q, double* r, long lon
   return hipGetLastError();
 }
 
-hipError_t launch_to_f32_scaled(const double* r64, float* r32, long long n, const CgState* st,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_to_f32_scaled, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, r64, r32,
-                     n, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_add_f32_scaled(double* x64, const float* d32, long long n, const CgState* st,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_add_f32_scaled, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, x64, d32,
-                     n, st);
-  return hipGetLastError();
-}
-
 hipError_t launch_axpby(double a, const double* x, double b, double* y, long long n,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_axpby, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, a, x, b, y, n);
@@ -320,6 +323,24 @@ hipError_t launch_zero(bool fp32, void* x, long long n, hipStream_t s) {
 
 hipError_t launch_state_init(CgState* st, int maxit, double rtol, hipStream_t s) {
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, maxit, rtol);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_set(CgState* st, int maxit, double tol2, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_set, dim3(1), dim3(64), 0, s, st, maxit, tol2);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32_dot(const double* r64, float* r32, long long n, double inv,
+                             double* partials, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32_dot, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, r64, r32, n,
+                     inv, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush_f32(double* x64, float* d32, long long n, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_flush_f32, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, x64, d32, n,
+                     scale);
   return hipGetLastError();
 }
 
