@@ -25,6 +25,38 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1602_05806_amd/csrc/pd_apply.hip", "paper_1602_05806_amd/csrc/pd_device.h"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, prec):
+    """HBM bytes per launch of the fused apply kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the plain-copy calibration), or None when the
+    summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"apply_{prec}_{workload}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    try:
+        return 1024.0 * (float(kv["fetch_kib_per_dispatch"]) * float(kv["copy_fetch_factor"]) +
+                         float(kv["write_kib_per_dispatch"]) * float(kv["copy_write_factor"]))
+    except (KeyError, ValueError):
+        return None
+
+
 METRIC = "pressure-CG DoF-iterations/s + HBM GB/s, FP64 vs FP32+FP64-refine at 1e-10"
 
 
@@ -92,6 +124,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rand2d_256_N6")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the pressure path is measured on one "
@@ -102,6 +136,13 @@ def main():
     import paper_1602_05806_amd as pd
     import synthetic
 
+    if args.calibrate_copy:
+        src = torch.randn(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = dict(synthetic.CONFIGS[args.workload])
     cfg.setdefault("steps", 1)
     dim = len(cfg["cells"])
@@ -168,7 +209,8 @@ def main():
         "algorithmic_gbs_cg": ndof * r64["iters"] * 80.0 / (r64["psolve_ms"] * 1e-3) / 1e9,
         "rel_res_true_max": r64["rel_res_true"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": measured_traffic(args.workload, "fp64"),
                      "kernel": "k_apply (fused CG form, FP64)",
                      "avg_launch_us": 1e3 * avg_ms, "launches": kt["launches"],
                      "bytes_per_launch": kt["bytes_per_launch"]},
@@ -182,7 +224,9 @@ def main():
             "rel_res_true_max": r32["rel_res_true"],
             "apply_kernel": {"avg_launch_us": 1e3 * avg32, "achieved_gbs": ach32,
                              "frac": (ach32 / HBM_PEAK_GBS) if ach32 else None,
-                             "bytes_per_launch": kt32["bytes_per_launch"]}},
+                             "bytes_per_launch": kt32["bytes_per_launch"],
+                             "traffic": measured_traffic(args.workload, "fp32")}},
+        "kernel_source_hash": kernel_source_hash(),
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg)
