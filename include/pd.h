@@ -61,15 +61,18 @@ enum { PD_FP64 = 0, PD_FP32 = 1, PD_FP32_REFINE64 = 2 };
  * definite, A_p positive semi-definite with null space Z = null of the weak gradient. */
 enum { PD_OP_PRESSURE = 0, PD_OP_VISCOUS = 1 };
 
-/* Per-solve report. iters: CG iterations (for PD_FP32_REFINE64 the FP32 iterations);
+/* Per-solve report. iters: CG iterations (FP32 plus FP64 ones for PD_FP32_REFINE64);
  * outer_iters: FP64 residual recomputations of the refinement (1 for PD_FP64); restarts:
- * refinement replacements that also restarted the search direction; status: PD_OK /
+ * refinement replacements that also restarted the search direction; fallback_iter: for
+ * PD_FP32_REFINE64, the iteration at which the solve continued in FP64 because the FP64
+ * residual had stopped decreasing under FP32 iterations (FP32 rounding of A p dominates the
+ * smallest eigenvalues once eps_32 * cond(A) approaches 1), -1 if it never did; status: PD_OK /
  * PD_ENOCONV / PD_EBREAKDOWN; rel_res_recur: last recurrence (FP64: CG recurrence; refinement:
  * last FP64) residual / ||b||; rel_res_true: true FP64 residual ||b - A x||/||b|| recomputed at
  * exit; ms: wall time of the solve on the stream. ||b|| is taken after the null-space projection
  * for PD_OP_PRESSURE. */
 typedef struct {
-  int iters, outer_iters, status, restarts;
+  int iters, outer_iters, status, restarts, fallback_iter, reserved;
   double rel_res_recur, rel_res_true, ms;
 } pd_solve_info;
 
@@ -93,6 +96,16 @@ int pd_sizes(const pd_ctx* ctx, long long* ncells, long long* ndof, int* dim);
 
 /* Copy the N+1 Gauss-Legendre nodes and weights on [0,1] used by ctx to host arrays. */
 int pd_nodes(const pd_ctx* ctx, double* xi, double* w);
+
+/* Host-only query of the FP64 1D tables the library builds for degree N (0..8), no device use:
+ * which = PD_TAB_NODES (N+1 Gauss-Legendre nodes on [0,1]), PD_TAB_WEIGHTS (N+1 weights),
+ * PD_TAB_L / PD_TAB_C / PD_TAB_R ((N+1)^2 entries, row-major: the blocks L, C, R of the 1D
+ * pressure operator of eq. (pSyst) / (PerPrSyst)), PD_TAB_PNULL ((N+1)^2: orthogonal projector
+ * onto the cell-periodic kernel of the weak gradient, null(R~ - L~)). out must hold that many
+ * doubles. Returns the number of values written, or PD_EINVAL. */
+enum { PD_TAB_NODES = 0, PD_TAB_WEIGHTS = 1, PD_TAB_L = 2, PD_TAB_C = 3, PD_TAB_R = 4,
+       PD_TAB_PNULL = 5 };
+int pd_table_1d(int N, int which, double* out);
 
 /* y = A x for op PD_OP_PRESSURE or PD_OP_VISCOUS; x, y: ndof elements of precision prec
  * (PD_FP64 or PD_FP32). Matrix-free: tensor-product application of the 1D blocks along each
@@ -154,12 +167,14 @@ int pd_step(pd_ctx* ctx, void* const u[3], void* p, pd_solve_info info[4], void*
  *   PD_CFG_TILES_PER_WG  2D operator kernel: tiles per persistent workgroup (0 = automatic)
  *   PD_CFG_PREFETCH      1 (default) = the operator kernel prefetches the next tile (2D) or the
  *                        next plane's halo (3D) into registers during compute, 0 = no prefetch
- * The last three only change the launch shape; results are identical up to the block order of
+ *   PD_CFG_TILE_VARIANT  2D operator kernel tile shape: 0 (default) = the largest tile of cells
+ *                        whose LDS box fits, 1 / 2 = one / two sizes smaller (more workgroups)
+ * The last four only change the launch shape; results are identical up to the block order of
  * the dot-product partial sums. */
 enum {
   PD_CFG_STEP_PREC = 0, PD_CFG_P_RTOL = 1, PD_CFG_V_RTOL = 2, PD_CFG_MAXIT = 3,
   PD_CFG_CONVECTION = 4, PD_CFG_RU_FACTOR = 5, PD_CFG_TIMING = 6, PD_CFG_CHECK_EVERY = 7,
-  PD_CFG_KZ = 8, PD_CFG_TILES_PER_WG = 9, PD_CFG_PREFETCH = 10
+  PD_CFG_KZ = 8, PD_CFG_TILES_PER_WG = 9, PD_CFG_PREFETCH = 10, PD_CFG_TILE_VARIANT = 11
 };
 int pd_configure(pd_ctx* ctx, int key, double value);
 
@@ -171,6 +186,69 @@ int pd_configure(pd_ctx* ctx, int key, double value);
  * (reads r and p_old, writes p and A p: 4 words per DoF). Synchronises with the last stream. */
 int pd_timing(pd_ctx* ctx, int prec, double* total_ms, long long* launches,
               double* bytes_per_launch, int reset);
+
+/* ---- Batched 2D pressure solves -------------------------------------------------------------
+ * A batch holds `count` independent periodic 2D pressure systems A_p x = b (the PD_OP_PRESSURE
+ * operator above, applied problem by problem): problem j has ncell[2j] x ncell[2j+1] cells on a
+ * len[2j] x len[2j+1] domain and degree N[j] (0..8); all share dt. Batch vectors are packed: one
+ * FP64 array in which problem j occupies elements [off[j], off[j+1]) in the element-blocked
+ * layout of a single 2D problem (pd_batch_layout gives off). A solve advances all problems
+ * together, each with its own CG scalars, stopping test and iteration count: a fixed chunk of
+ * iterations (plus, for PD_FP32_REFINE64, the FP64 residual replacement of every unfinished
+ * problem) is captured once into a HIP graph and replayed until every problem has stopped. */
+typedef struct pd_batch pd_batch;
+
+/* pd_batch_setup flags. PD_BATCH_AUTOTUNE: pick the operator tile shape (the three variants of
+ * PD_CFG_TILE_VARIANT) per (degree, size bucket, precision) by timing the shapes on the batch's
+ * own problems; size bucket = the largest power of two <= max(ncell). Choices are read from and
+ * added to the text file named by the environment variable PD_AUTOTUNE_CACHE when it is set
+ * (one "key variant" pair per line). PD_BATCH_RETUNE: time every bucket again, ignoring cached
+ * choices. Without flags, cached choices are used where present, else variant 0. */
+enum { PD_BATCH_AUTOTUNE = 1, PD_BATCH_RETUNE = 2 };
+
+/* Create a batch (tables, descriptors, packed workspace; tuning if asked). ncell, len: 2*count
+ * host values; N: count host values; dt > 0. On error *out is NULL and the message is available
+ * from pd_batch_last_error(NULL). Synchronises. */
+int pd_batch_setup(pd_batch** out, int count, const int* ncell, const double* len, const int* N,
+                   double dt, unsigned flags, void* hip_stream);
+
+/* Release the batch's device memory and graphs (waits for the device). NULL is ignored. */
+void pd_batch_destroy(pd_batch* batch);
+
+/* Last error message of batch (or of the last failed pd_batch_setup if NULL). Never NULL. */
+const char* pd_batch_last_error(const pd_batch* batch);
+
+/* offsets: count + 1 host values; offsets[j] = first packed element of problem j,
+ * offsets[count] = total packed length. */
+int pd_batch_layout(const pd_batch* batch, long long* offsets);
+
+/* variants: count host values; tile variant (0..2) problem j uses in precision prec (PD_FP64, or
+ * PD_FP32 for the inner iterations of PD_FP32_REFINE64). */
+int pd_batch_variants(const pd_batch* batch, int prec, int* variants);
+
+/* Settings (key, value):
+ *   PD_BCFG_CHUNK  iterations per graph replay: even, 2..4096 (default 64). With
+ *                  PD_FP32_REFINE64 the FP64 residual is replaced once per chunk.
+ *   PD_BCFG_GRAPH  1 (default) = replay the captured graph, 0 = enqueue the same kernels one by
+ *                  one each chunk (identical arithmetic; for comparison and debugging).
+ *   PD_BCFG_RU_FACTOR  PD_FP32_REFINE64: a problem's FP32 iterations pause (until the chunk's
+ *                  residual replacement) once their residual has dropped by this factor below the
+ *                  last replaced one, in (0, 1) (default 1e-2). This keeps fast-converging
+ *                  problems from iterating on FP32 rounding noise. */
+enum { PD_BCFG_CHUNK = 0, PD_BCFG_GRAPH = 1, PD_BCFG_RU_FACTOR = 2 };
+int pd_batch_configure(pd_batch* batch, int key, double value);
+
+/* Solve every problem of the batch: b = packed FP64 right-hand sides (read only; each problem's
+ * part is first projected onto range(A_p) as in pd_cg_solve), x = packed FP64 solutions (out;
+ * the initial guess is zero; each problem's result is projected onto range(A_p), the minimum
+ * norm solution). prec: PD_FP64 (stop when the recurrence residual <= rtol ||b_j||) or
+ * PD_FP32_REFINE64 (stop when the FP64 residual b_j - A x_j recomputed at a chunk end is
+ * <= rtol ||b_j||). maxit caps each problem's iterations. info: count entries or NULL; ms is the
+ * whole batch's time; rel_res_true is recomputed in FP64 for every problem after the solve;
+ * outer_iters counts residual replacements. Synchronises. Returns PD_OK when every problem
+ * converged, else PD_EBREAKDOWN if any problem broke down, else PD_ENOCONV. */
+int pd_batch_cg_solve(pd_batch* batch, int prec, const void* b, void* x, double rtol, int maxit,
+                      pd_solve_info* info, void* hip_stream);
 
 #ifdef __cplusplus
 }

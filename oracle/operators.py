@@ -177,6 +177,48 @@ def apply_along(mat, X, axis):
     return np.moveaxis(Y, 0, axis)
 
 
+def null_basis_tiled(nc, N):
+    """Orthonormal basis of null(D) for nc periodic cells without a size-nc SVD: the kernel of
+    the periodic weak gradient is cell-periodic (the same polynomial in every cell; Section 2.1,
+    end), so the per-cell modes are read off the kernel on 3 cells and tiled over nc cells."""
+    n = N + 1
+    Z3 = null_basis_1d(3, N)
+    if Z3.shape[1] == 0:
+        return np.zeros((nc * n, 0))
+    modes, _ = np.linalg.qr(Z3[:n])                 # per-cell modes, orthonormal in R^n
+    return np.tile(modes, (nc, 1)) / np.sqrt(nc)
+
+
+def apply_operator(grid, X, alpha, beta, absolute=False):
+    """(alpha M^{xyz} + beta K) X for a tensor-layout X without assembling the d-dimensional
+    matrix: K = sum_d h_d^-2 (M on the other directions) (x) H_d applied one direction at a time
+    with the 1D sparse H_d and the diagonal 1D masses (eq. pSyst).
+
+    absolute=True gives |alpha M + beta K| |X| (entrywise absolute values of the operator and of
+    X), the scale of the rounding error of any floating-point evaluation of the product."""
+    X = np.asarray(X, dtype=np.float64).reshape(grid.shape())
+    if absolute:
+        X = np.abs(X)
+        alpha, beta = abs(alpha), abs(beta)
+    masses = [mass_1d(grid.cells[d], grid.N) for d in range(grid.dim)]
+    out = np.zeros_like(X)
+    if alpha != 0.0:
+        MX = X
+        for d in range(grid.dim):
+            MX = apply_along(masses[d], MX, grid.dim - 1 - d)
+        out = out + alpha * MX
+    for d in range(grid.dim):
+        H = pressure_1d(grid.cells[d], grid.N)
+        if absolute:
+            H = abs(H)
+        T = apply_along(H, X, grid.dim - 1 - d)
+        for e in range(grid.dim):
+            if e != d:
+                T = apply_along(masses[e], T, grid.dim - 1 - e)
+        out = out + beta / grid.h[d] ** 2 * T
+    return out
+
+
 def project_null(grid, X, Zs):
     """v <- v - Z Z^T v with Z = kron of the per-direction orthonormal bases Zs[d].
 

@@ -29,16 +29,22 @@ PD_FP64, PD_FP32, PD_FP32_REFINE64 = 0, 1, 2
 PD_OP_PRESSURE, PD_OP_VISCOUS = 0, 1
 (PD_CFG_STEP_PREC, PD_CFG_P_RTOL, PD_CFG_V_RTOL, PD_CFG_MAXIT, PD_CFG_CONVECTION,
  PD_CFG_RU_FACTOR, PD_CFG_TIMING, PD_CFG_CHECK_EVERY, PD_CFG_KZ, PD_CFG_TILES_PER_WG,
- PD_CFG_PREFETCH) = range(11)
+ PD_CFG_PREFETCH, PD_CFG_TILE_VARIANT) = range(12)
+PD_BATCH_AUTOTUNE, PD_BATCH_RETUNE = 1, 2
+PD_BCFG_CHUNK, PD_BCFG_GRAPH, PD_BCFG_RU_FACTOR = 0, 1, 2
+PD_TAB_NODES, PD_TAB_WEIGHTS, PD_TAB_L, PD_TAB_C, PD_TAB_R, PD_TAB_PNULL = range(6)
 
-EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "pd_apply",
+EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "pd_table_1d", "pd_apply",
             "pd_cg_solve", "pd_rhs_div", "pd_project_velocity", "pd_project_null",
-            "pd_l2_project", "pd_convect", "pd_step", "pd_configure", "pd_timing"]
+            "pd_l2_project", "pd_convect", "pd_step", "pd_configure", "pd_timing",
+            "pd_batch_setup", "pd_batch_destroy", "pd_batch_last_error", "pd_batch_layout",
+            "pd_batch_variants", "pd_batch_configure", "pd_batch_cg_solve"]
 
 
 class pd_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int), ("status", ctypes.c_int),
-                ("restarts", ctypes.c_int), ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
+                ("restarts", ctypes.c_int), ("fallback_iter", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("rel_res_recur", ctypes.c_double), ("rel_res_true", ctypes.c_double),
                 ("ms", ctypes.c_double)]
 
     def as_dict(self):
@@ -56,6 +62,7 @@ _lib.pd_last_error.restype = ctypes.c_char_p
 _lib.pd_sizes.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong),
                           ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)]
 _lib.pd_nodes.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.pd_table_1d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
 _lib.pd_apply.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
 _lib.pd_cg_solve.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double,
                              ctypes.c_int, ctypes.POINTER(pd_solve_info), _vp]
@@ -69,6 +76,18 @@ _lib.pd_configure.argtypes = [_vp, ctypes.c_int, ctypes.c_double]
 _lib.pd_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double),
                            ctypes.c_int]
+_lib.pd_batch_setup.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                ctypes.c_double, ctypes.c_uint, _vp]
+_lib.pd_batch_destroy.argtypes = [_vp]
+_lib.pd_batch_destroy.restype = None
+_lib.pd_batch_last_error.argtypes = [_vp]
+_lib.pd_batch_last_error.restype = ctypes.c_char_p
+_lib.pd_batch_layout.argtypes = [_vp, ctypes.POINTER(ctypes.c_longlong)]
+_lib.pd_batch_variants.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+_lib.pd_batch_configure.argtypes = [_vp, ctypes.c_int, ctypes.c_double]
+_lib.pd_batch_cg_solve.argtypes = [_vp, ctypes.c_int, _vp, _vp, ctypes.c_double, ctypes.c_int,
+                                   ctypes.POINTER(pd_solve_info), _vp]
 
 
 class PdError(RuntimeError):
@@ -159,6 +178,15 @@ def pd_nodes(ctx):
     return list(xi), list(w)
 
 
+def pd_table_1d(N, which):
+    """Host-only: the library's FP64 1D table `which` (PD_TAB_*) for degree N, as a list."""
+    out = (ctypes.c_double * 81)()
+    cnt = _lib.pd_table_1d(int(N), int(which), out)
+    if cnt < 0:
+        raise PdError(cnt, f"pd_table_1d: bad degree {N} or table {which}")
+    return list(out)[:cnt]
+
+
 def _dtype(prec):
     import torch
     return torch.float32 if prec == PD_FP32 else torch.float64
@@ -238,3 +266,82 @@ def pd_timing(ctx, prec, reset=True):
     _check(ctx, _lib.pd_timing(ctx.handle, prec, ctypes.byref(ms), ctypes.byref(cnt),
                                ctypes.byref(by), 1 if reset else 0))
     return dict(total_ms=ms.value, launches=cnt.value, bytes_per_launch=by.value)
+
+
+class Batch:
+    """Owns one pd_batch: .count problems, packed layout .offsets (count + 1), .total DoFs."""
+
+    def __init__(self, handle, count):
+        self._h = handle
+        self.count = count
+        off = (ctypes.c_longlong * (count + 1))()
+        _bcheck(self, _lib.pd_batch_layout(self._h, off))
+        self.offsets = list(off)
+        self.total = self.offsets[-1]
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch destroyed")
+        return self._h
+
+    def close(self):
+        if self._h is not None:
+            _lib.pd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bcheck(batch, rc, allow=()):
+    if rc == PD_OK or rc in allow:
+        return rc
+    h = None if batch is None else batch._h
+    msg = _lib.pd_batch_last_error(h)
+    raise PdError(rc, msg.decode() if msg else "")
+
+
+def pd_batch_setup(ncell, length, N, dt, flags=0, stream=None):
+    """ncell, length: sequences of (nx, ny) / (Lx, Ly) pairs; N: degrees."""
+    count = len(N)
+    if len(ncell) != count or len(length) != count:
+        raise ValueError("ncell, length and N must have one entry per problem")
+    nc = (ctypes.c_int * (2 * count))(*[int(v) for p in ncell for v in p])
+    ln = (ctypes.c_double * (2 * count))(*[float(v) for p in length for v in p])
+    nn = (ctypes.c_int * count)(*[int(v) for v in N])
+    h = ctypes.c_void_p()
+    rc = _lib.pd_batch_setup(ctypes.byref(h), count, nc, ln, nn, float(dt), int(flags),
+                             ctypes.c_void_p(_stream(stream)))
+    if rc != PD_OK:
+        raise PdError(rc, _lib.pd_batch_last_error(None).decode())
+    return Batch(h, count)
+
+
+def pd_batch_destroy(batch):
+    batch.close()
+
+
+def pd_batch_variants(batch, prec):
+    v = (ctypes.c_int * batch.count)()
+    _bcheck(batch, _lib.pd_batch_variants(batch.handle, prec, v))
+    return list(v)
+
+
+def pd_batch_configure(batch, key, value):
+    _bcheck(batch, _lib.pd_batch_configure(batch.handle, int(key), float(value)))
+
+
+def pd_batch_cg_solve(batch, prec, b, x, rtol, maxit, stream=None):
+    """Solves every problem; returns (rc, list of per-problem solve-info dicts). Non-convergence
+    and breakdown are reported through rc and the infos, other failures raise."""
+    import torch
+    info = (pd_solve_info * batch.count)()
+    rc = _lib.pd_batch_cg_solve(batch.handle, prec, _ptr(b, batch.total, torch.float64),
+                                _ptr(x, batch.total, torch.float64), float(rtol), int(maxit),
+                                info, ctypes.c_void_p(_stream(stream)))
+    _bcheck(batch, rc, allow=(PD_ENOCONV, PD_EBREAKDOWN))
+    return rc, [i.as_dict() for i in info]

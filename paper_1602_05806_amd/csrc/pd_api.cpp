@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -30,6 +31,7 @@ struct pd_ctx {
   double p_rtol = 1e-10, v_rtol = 1e-12, ru_factor = 0.1;
   int maxit = 100000, convection = 1, timing = 0, check_every = 32;
   int kz = 0, tiles_per_wg = 0, prefetch = 1;   // operator-kernel launch shape
+  int tile_variant = 0;                          // 2D tile shape (0 = largest fitting)
   // device workspace
   CgState* st = nullptr;       // CG state of the (inner) solve
   CgState* st2 = nullptr;      // outer refinement / residual norms
@@ -100,6 +102,7 @@ pdk::ApplyLaunch base_launch(const pd_ctx* c, int op, bool fp32) {
   L.kz_override = c->kz;
   L.tiles_per_wg = c->tiles_per_wg;
   L.prefetch = c->prefetch;
+  L.tile_variant = c->tile_variant;
   return L;
 }
 
@@ -313,6 +316,13 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
   }
   const double scale = res;                     // the FP32 vectors hold r / scale
   const double tol_rel = rtol * bnorm / scale;  // recurrence tolerance in scaled units
+  const double f = c->ru_factor;
+  // The FP32 iterations stop on the device once their residual has dropped by f below the last
+  // replaced one (or reached the final tolerance); each stop is followed by a replacement.
+  auto inner_tol2 = [&](double ref) {
+    const double t = std::fmax(f * ref, tol_rel);
+    return t * t;
+  };
   CgRun R;
   R.op = op;
   R.fp32 = true;
@@ -323,15 +333,16 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
   R.timed = timed;
   PD_HIP(c, pdk::launch_zero(true, c->d32, n, s));
   PD_HIP(c, pdk::launch_to_f32_dot(c->r64, c->r32, n, 1.0 / scale, c->rhopart, s));
-  PD_HIP(c, pdk::launch_state_set(c->st, maxit, tol_rel * tol_rel, s));
+  PD_HIP(c, pdk::launch_state_set(c->st, maxit, inner_tol2(1.0), s));
   if ((rc = cg_prepare(c, &R))) return rc;
   double ref = 1.0;                             // scaled residual norm at the last replacement
-  const double f = c->ru_factor;
+  double best = 1.0;                            // smallest scaled FP64 residual so far
+  int stall = 0;                                // replacements in a row without a new best
+  int stalled = 0;                              // FP32 breakdowns in a row without progress
   inf->status = PD_ENOCONV;
   for (;;) {
     CgState fin;
-    rc = cg_run_until(c, &R, maxit,
-                      [&](const CgState& h) { return std::sqrt(h.rho) <= f * ref; }, &fin);
+    rc = cg_run_until(c, &R, maxit, [](const CgState&) { return false; }, &fin);
     if (rc) return rc;
     // flush the FP32 correction and recompute the true residual in FP64
     PD_HIP(c, pdk::launch_flush_f32(x, c->d32, n, scale, s));
@@ -339,7 +350,7 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
     if (rc) return rc;
     ++inf->outer_iters;
     inf->rel_res_recur = res / bnorm;
-    if (!std::isfinite(res) || (fin.done && fin.status == PD_EBREAKDOWN)) {
+    if (!std::isfinite(res)) {
       inf->status = PD_EBREAKDOWN;
       break;
     }
@@ -351,18 +362,48 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
       inf->status = PD_ENOCONV;
       break;
     }
+    // FP32 arithmetic has stopped reducing the FP64 residual (it grew beyond twice the best
+    // one, or no new best for 16 replacements: eps_32 cond(A) near 1 makes FP32 A p meaningless
+    // for the smallest eigenvalues): continue with FP64 iterations from the current x.
+    const double r = res / scale;
+    if (r < best) {
+      best = r;
+      stall = 0;
+    } else {
+      ++stall;
+    }
+    if (r > 2.0 * best || stall >= 16) {
+      cg_collect_timing(c, R);
+      inf->fallback_iter = R.k;
+      pd_solve_info i64{};
+      rc = solve_fp64(c, op, b, x, rtol, bnorm, std::max(0, maxit - R.k), timed, &i64, s);
+      if (rc) return rc;
+      inf->iters = R.k + i64.iters;
+      inf->status = i64.status;
+      inf->rel_res_recur = i64.rel_res_recur;
+      return PD_OK;
+    }
+    // An FP32 breakdown (<p, A p> <= 0 once the FP32 residual is rounding noise, which on a
+    // singular operator includes null-space components) ends the inner run; the FP64 residual
+    // replaces it and the direction restarts. Two in a row without progress end the solve.
+    const bool broke = fin.done && fin.status == PD_EBREAKDOWN;
+    stalled = broke && !(res / scale < 0.5 * ref) ? stalled + 1 : 0;
+    if (stalled >= 2) {
+      inf->status = PD_EBREAKDOWN;
+      break;
+    }
     // residual replacement: r32 = r64 / scale with the partials of <r32, r32> for iteration R.k.
     // If the FP32 recurrence residual had drifted well below the true one, beta would be huge
     // and the old direction would swamp the new residual: restart the direction (p_old = 0).
     const double rec = std::sqrt(fin.rho);
-    if (!(res / scale <= 4.0 * rec)) {
+    if (broke || !(res / scale <= 4.0 * rec)) {
       void* buf[2] = {R.B.pa, R.B.pb};
       PD_HIP(c, pdk::launch_zero(true, buf[R.k & 1], n, s));
       ++inf->restarts;
     }
     PD_HIP(c, pdk::launch_to_f32_dot(c->r64, c->r32, n, 1.0 / scale, R.rho[R.k & 1], s));
-    PD_HIP(c, pdk::launch_state_set(c->st, maxit, tol_rel * tol_rel, s));
     ref = res / scale;
+    PD_HIP(c, pdk::launch_state_set(c->st, maxit, inner_tol2(ref), s));
   }
   cg_collect_timing(c, R);
   inf->iters = R.k;
@@ -395,6 +436,7 @@ int solve(pd_ctx* c, int op, int prec, const double* b_in, double* x, double rto
   const double bnorm = std::sqrt(h.aux);
   pd_solve_info inf{};
   inf.status = PD_OK;
+  inf.fallback_iter = -1;
   if (bnorm == 0.0) {
     PD_HIP(c, pdk::launch_zero(false, x, n, s));
   } else if (!std::isfinite(bnorm)) {
@@ -685,6 +727,26 @@ int pd_nodes(const pd_ctx* c, double* xi, double* w) {
   return PD_OK;
 }
 
+int pd_table_1d(int N, int which, double* out) {
+  if (!out || which < PD_TAB_NODES || which > PD_TAB_PNULL) return PD_EINVAL;
+  pdh::Table1D t;
+  std::string e;
+  if (!pdh::build_table(N, &t, &e)) return PD_EINVAL;
+  const int n = t.n;
+  const double* src = nullptr;
+  int cnt = n * n;
+  switch (which) {
+    case PD_TAB_NODES: src = t.xi; cnt = n; break;
+    case PD_TAB_WEIGHTS: src = t.w; cnt = n; break;
+    case PD_TAB_L: src = t.Lb; break;
+    case PD_TAB_C: src = t.Cb; break;
+    case PD_TAB_R: src = t.Rb; break;
+    default: src = t.Pnull; break;
+  }
+  for (int i = 0; i < cnt; ++i) out[i] = src[i];
+  return cnt;
+}
+
 int pd_apply(pd_ctx* c, int op, int prec, const void* x, void* y, void* hip_stream) {
   if (!c) return PD_EINVAL;
   if (op != PD_OP_PRESSURE && op != PD_OP_VISCOUS) return fail(c, PD_EINVAL, "unknown operator");
@@ -831,6 +893,10 @@ int pd_configure(pd_ctx* c, int key, double v) {
       break;
     case PD_CFG_PREFETCH:
       c->prefetch = v != 0.0;
+      break;
+    case PD_CFG_TILE_VARIANT:
+      if (!(v == 0 || v == 1 || v == 2)) return fail(c, PD_EINVAL, "tile variant must be 0, 1 or 2");
+      c->tile_variant = (int)v;
       break;
     default:
       return fail(c, PD_EINVAL, "unknown configuration key");

@@ -1,0 +1,248 @@
+// Shared pieces of the operator-apply kernels (single-problem and batched launches): kernel
+// argument block, periodic index wrap, the 1D three-cell line operator and the 2D tile body.
+// See pd_apply.hip for the design notes.
+#pragma once
+#include "pd_device.h"
+
+namespace pdk {
+
+template <typename T>
+struct ApplyArgs {
+  const T* x;       // operand (FUSE = 0) or residual r (FUSE = 1)
+  const T* pold;    // FUSE = 1: previous search direction
+  T* pnew;          // FUSE = 1: new search direction (must not alias pold)
+  T* y;             // result
+  int nx, ny, nz;
+  int ntx, nty, ntz;
+  int kz;           // 3D: planes per column segment
+  T alpha;          // mass coefficient
+  T c0, c1, c2;     // coefficient of each direction (beta / h_d^2)
+  // FUSE = 1: CG iteration k, partials of rho_k and rho_{k-1}, sigma partials (one per block)
+  CgState* st;
+  int k;              // iteration index, or offset from *kbase when kbase is set
+  const int* kbase;   // device-resident iteration base (graph-replayed batched runs) or null
+  const double* rho_cur;
+  int nrho;
+  double* sigpart;
+};
+
+__device__ __forceinline__ int wrapi(int i, int m) {
+  i %= m;
+  return i < 0 ? i + m : i;
+}
+
+
+// One output row l of the 1D three-cell operator: sum_m L[l][m] vl[m] + C[l][m] vc[m] + R[l][m] vr[m],
+// with three independent accumulators (the FMA latency is not serialised over 3(N+1) terms).
+// Called with a run-time row index from a rolled loop, so the coefficients of the rows being
+// computed are scalar-loaded per iteration instead of keeping all 3(N+1)^2 of them live.
+template <typename T, int N>
+__device__ __forceinline__ T row3(const Blk<T, N>& B, int l, const T (&vl)[N + 1],
+                                  const T (&vc)[N + 1], const T (&vr)[N + 1]) {
+  constexpr int n = N + 1;
+  T al = T(0), ac = T(0), ar = T(0);
+#pragma unroll
+  for (int m = 0; m < n; ++m) {
+    al += B.L[l * n + m] * vl[m];
+    ac += B.C[l * n + m] * vc[m];
+    ar += B.R[l * n + m] * vr[m];
+  }
+  return (al + ac) + ar;
+}
+
+// Apply the 1D three-cell operator to one line: out(l) = op(l) for every row l, two rows per
+// iteration where the scalar-register budget allows it.
+template <typename T, int N, typename F>
+__device__ __forceinline__ void line3(const Blk<T, N>& B, const T (&vl)[N + 1],
+                                      const T (&vc)[N + 1], const T (&vr)[N + 1], F&& out) {
+  constexpr int n = N + 1;
+  constexpr bool pairs = 2 * 3 * n * (int)sizeof(T) / 4 <= 36;   // SGPRs of two rows
+  if constexpr (pairs) {
+#pragma unroll 1
+    for (int l = 0; l + 1 < n; l += 2) {
+      const T r0 = row3<T, N>(B, l, vl, vc, vr);
+      const T r1 = row3<T, N>(B, l + 1, vl, vc, vr);
+      out(l, r0);
+      out(l + 1, r1);
+    }
+    if (n & 1) out(n - 1, row3<T, N>(B, n - 1, vl, vc, vr));
+  } else {
+#pragma unroll 1
+    for (int l = 0; l < n; ++l) out(l, row3<T, N>(B, l, vl, vc, vr));
+  }
+}
+
+__device__ __forceinline__ int wrap_small(int i, int m) {
+  // i in [-m, 2m) for every caller except grids narrower than a tile (loop handles those)
+  while (i < 0) i += m;
+  while (i >= m) i -= m;
+  return i;
+}
+
+// ------------------------------------------------------------------ 2D tile kernel
+
+// 2D tile shapes. Variant V = 0 is the largest of 8x8, 8x4, 4x4, 4x2, 2x2 whose LDS footprint
+// (box + accumulator) fits 40 KB; V = 1 and V = 2 are the next one and two sizes down (more
+// workgroups and occupancy, more halo). The batched solver's autotuner picks V per size bucket.
+template <typename T, int N, int V = 0>
+struct Tile2D {
+  static constexpr int n = N + 1, NC = n * n;
+  static constexpr bool fits(int tx, int ty) {
+    return ((tx + 2) * (ty + 2) + tx * ty) * NC * (int)sizeof(T) <= 40960;
+  }
+  static constexpr int first = fits(8, 8) ? 0 : fits(8, 4) ? 1 : fits(4, 4) ? 2 : fits(4, 2) ? 3 : 4;
+  static constexpr int idx = first + V < 4 ? first + V : 4;
+  static constexpr int TX = idx == 0 ? 8 : idx == 1 ? 8 : idx == 2 ? 4 : idx == 3 ? 4 : 2;
+  static constexpr int TY = idx == 0 ? 8 : idx == 1 ? 4 : idx == 2 ? 4 : idx == 3 ? 2 : 2;
+};
+
+// 2D: LDS holds the tile and its face halos as a (TX+2) x (TY+2) box of cells (corners unused),
+// box cell (bi, bj) = tile cell (bi-1, bj-1). Box row bj is one contiguous run of cells in global
+// memory unless it crosses the periodic seam, so staging is a flat copy per row.
+template <typename T, int N, int V, int FUSE, int PF>
+__device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T, N>& B,
+                                             int t_begin, int t_end, int slot) {
+  using TL = Tile2D<T, N, V>;
+  constexpr int n = N + 1, NC = n * n, TX = TL::TX, TY = TL::TY, NT = TX * TY;
+  constexpr int BX = TX + 2;                    // box width in cells
+  constexpr int RI = BX * NC;                   // elements of an interior box row
+  constexpr int RH = TX * NC;                   // elements of a halo box row (no corners)
+  constexpr int JI = (RI + 255) / 256, JH = (RH + 255) / 256;
+  __shared__ T xs[(TY + 2) * BX * NC];
+  __shared__ T ys[NT * NC];
+  if (FUSE) {
+    if (a.st->done) return;
+  }
+  const T* __restrict__ xg = a.x;
+  const T* __restrict__ pg = a.pold;
+  T* __restrict__ png = a.pnew;
+  T* __restrict__ yg = a.y;
+  const int tid = threadIdx.x;
+  T rvi[TY][JI], pvi[TY][JI], rvh[2][JH], pvh[2][JH];
+
+  // global element index of box element e of box row bj (bj in 0..TY+1) of the tile at (tx0, ty0)
+  auto gindex = [&](int tx0, int ty0, int bj, int e) -> size_t {
+    const int first = (bj == 0 || bj == TY + 1) ? 0 : -1;   // first tile column of the row
+    const int cr = e / NC, l = e - cr * NC;
+    const int gi = wrap_small(tx0 + first + cr, a.nx);
+    const int gj = wrap_small(ty0 + bj - 1, a.ny);
+    return ((size_t)gj * a.nx + gi) * NC + l;
+  };
+  auto stage_load = [&](int tile) {
+    const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
+    const bool flat = tx0 >= 1 && tx0 + TX + 1 <= a.nx;        // no row crosses the x seam
+#pragma unroll
+    for (int bj = 0; bj < TY + 2; ++bj) {
+      const bool halo = bj == 0 || bj == TY + 1;
+      const int gj = wrap_small(ty0 + bj - 1, a.ny);
+      const size_t row0 = ((size_t)gj * a.nx + (halo ? tx0 : tx0 - 1)) * NC;
+      constexpr int J = JI > JH ? JI : JH;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int e = tid + 256 * j;
+        if (e < (halo ? RH : RI)) {
+          const size_t g = flat ? row0 + e : gindex(tx0, ty0, bj, e);
+          T rv = xg[g], pv = T(0);
+          if (FUSE) pv = pg[g];
+          if (halo) {
+            if (j < JH) { rvh[bj ? 1 : 0][j] = rv; pvh[bj ? 1 : 0][j] = pv; }
+          } else if (j < JI) {
+            rvi[bj - 1][j] = rv;
+            pvi[bj - 1][j] = pv;
+          }
+        }
+      }
+    }
+  };
+
+  if (t_begin < t_end) stage_load(t_begin);
+  T beta = T(0);
+  if (FUSE) {
+    const IterScalars sc = iteration_scalars<256>(a.st, a.kbase ? *a.kbase + a.k : a.k,
+                                                  a.rho_cur, a.nrho, t_begin == 0);
+    if (sc.stop) return;
+    beta = (T)sc.beta;
+  }
+  double dot = 0.0;
+  for (int tile = t_begin; tile < t_end; ++tile) {
+    const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
+    // registers -> LDS (p = r + beta p_old formed here; owned cells also stored to global)
+#pragma unroll
+    for (int bj = 0; bj < TY + 2; ++bj) {
+      const bool halo = bj == 0 || bj == TY + 1;
+      constexpr int J = JI > JH ? JI : JH;
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const int e = tid + 256 * j;
+        if (e < (halo ? RH : RI) && (halo ? j < JH : j < JI)) {
+          T v = halo ? rvh[bj ? 1 : 0][j] : rvi[bj - 1][j];
+          if (FUSE) {
+            // beta = 0 (first iteration, restart) must not read p_old, which may hold anything
+            if (beta != T(0)) v = v + beta * (halo ? pvh[bj ? 1 : 0][j] : pvi[bj - 1][j]);
+            if (!halo) {
+              const int bi = e / NC;                 // box column: own cells are 1..TX
+              const int ui = tx0 + bi - 1, uj = ty0 + bj - 1;
+              if (bi >= 1 && bi <= TX && ui < a.nx && uj < a.ny)
+                png[((size_t)uj * a.nx + ui) * NC + (e - bi * NC)] = v;
+            }
+          }
+          xs[(bj * BX + (halo ? 1 : 0)) * NC + e] = v;
+        }
+      }
+    }
+    __syncthreads();
+    if (PF && tile + 1 < t_end) stage_load(tile + 1);   // in flight during the compute below
+
+    // x-lines: (cell c, l2); nodes l1 = 0..N
+    for (int L = tid; L < NT * n; L += 256) {
+      const int c = L / n, l2 = L - c * n;
+      const int ci = c % TX, cj = c / TX;
+      const int bc = ((cj + 1) * BX + ci + 1) * NC + l2 * n;
+      T vl[n], vc[n], vr[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        vl[m] = xs[bc - NC + m];
+        vc[m] = xs[bc + m];
+        vr[m] = xs[bc + NC + m];
+      }
+      const T wgt = a.c0 * B.w[l2];
+      line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + l2 * n + l1] = wgt * v; });
+    }
+    __syncthreads();
+
+    // y-lines: (cell c, l1); nodes l2 = 0..N; final values are stored here
+    for (int L = tid; L < NT * n; L += 256) {
+      const int c = L / n, l1 = L - c * n;
+      const int ci = c % TX, cj = c / TX;
+      const int bc = ((cj + 1) * BX + ci + 1) * NC + l1;
+      T vl[n], vc[n], vr[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        vl[m] = xs[bc - BX * NC + m * n];
+        vc[m] = xs[bc + m * n];
+        vr[m] = xs[bc + BX * NC + m * n];
+      }
+      const int ui = tx0 + ci, uj = ty0 + cj;
+      const bool valid = ui < a.nx && uj < a.ny;
+      const size_t base = ((size_t)uj * a.nx + ui) * NC;
+      const T wgt = a.c1 * B.w[l1];
+      const T wm = a.alpha * B.w[l1];
+      line3<T, N>(B, vl, vc, vr, [&](int l2, T v) {
+        const T xc = xs[bc + l2 * n];
+        const T val = ys[c * NC + l2 * n + l1] + wgt * v + wm * B.w[l2] * xc;
+        if (valid) {
+          yg[base + l2 * n + l1] = val;
+          dot += (double)xc * (double)val;
+        }
+      });
+    }
+    __syncthreads();
+    if (!PF && tile + 1 < t_end) stage_load(tile + 1);
+  }
+  if (FUSE) {
+    const double s = block_sum_all<256>(dot);
+    if (threadIdx.x == 0) a.sigpart[slot] = s;
+  }
+}
+
+}  // namespace pdk

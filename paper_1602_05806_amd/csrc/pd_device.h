@@ -35,11 +35,24 @@ struct CgState {
   double bnorm2;     // <b, b>
   double tol2;       // (rtol ||b||)^2
   double aux;        // scalar result of a stand-alone reduction (FIN_AUX), rtol input of FIN_BNORM
+  double scale;      // batched refinement: the FP32 vectors hold r / scale
+  double ref;        // batched refinement: FP64 residual / scale at the last replacement
+  double best;       // batched refinement: smallest FP64 residual / scale so far
   int iter;          // iterations completed when done
   int maxit;
-  int done;          // 1 once converged, out of iterations or broken down
+  int done;          // 1 once converged, out of iterations or broken down (batched refinement:
+                     // the FP32 iterations of this problem pause until the next replacement)
   int status;        // 0 ok, -4 no convergence, -5 breakdown
-  int pad[2];
+  int restart_k;     // iteration at which beta is forced to 0 (direction restart), -1 = none
+  int restarts;      // direction restarts so far (batched refinement)
+  int fin;           // batched: 1 once the problem is finished
+  int even_stop;     // 1: the tol2 stop is taken at even iterations only (batched refinement)
+  int fresh;         // batched: 1 = the next executed iteration starts a new direction (beta = 0)
+  int mode64;        // batched: 0 = FP32 iterations with FP64 replacement, 1 = FP64 iterations
+  int switched;      // batched: set when the problem has just switched to FP64 iterations
+  int stall;         // batched refinement: replacements in a row without a new best residual
+  int fallback_k;    // batched refinement: iteration of the switch to FP64, -1 = none
+  int pad;
 };
 
 // Finalizers of the stand-alone reductions (dot kernel + single-block finalize kernel).
@@ -89,19 +102,21 @@ struct IterScalars {
   bool stop;
 };
 
+// `writer`: the one block of the problem that mirrors the scalars into st.
 template <int NT>
 __device__ __forceinline__ IterScalars iteration_scalars(CgState* st, int k,
-                                                         const double* rho_cur, int nrho) {
+                                                         const double* rho_cur, int nrho,
+                                                         bool writer) {
   IterScalars r;
   r.rho = sum_partials<NT>(rho_cur, nrho);
   const double rho_old = k > 0 ? st->rho_hist[(k + 1) & 1] : 0.0;
-  r.beta = k > 0 ? r.rho / rho_old : 0.0;
+  r.beta = (k > 0 && k != st->restart_k && !st->fresh) ? r.rho / rho_old : 0.0;
   int status = 1;                               // 1 = keep iterating
   if (!isfinite(r.rho)) status = -5;
-  else if (r.rho <= st->tol2) status = 0;
+  else if (r.rho <= st->tol2 && !(st->even_stop && (k & 1))) status = 0;
   else if (k >= st->maxit) status = -4;
   r.stop = status != 1;
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+  if (threadIdx.x == 0 && writer) {
     st->rho_hist[k & 1] = r.rho;
     st->rho = r.rho;
     st->beta = r.beta;

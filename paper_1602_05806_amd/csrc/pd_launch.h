@@ -31,6 +31,7 @@ struct ApplyLaunch {
   int kz_override = 0;       // 3D: planes per column segment (0 = automatic)
   int tiles_per_wg = 0;      // 2D: tiles per persistent workgroup (0 = automatic)
   int prefetch = 1;          // prefetch the next tile (2D) / next plane's halo (3D) into registers
+  int tile_variant = 0;      // 2D tile shape (0 = largest fitting, 1 / 2 = one / two sizes smaller)
   const OpTables* tab = nullptr;
 };
 
@@ -104,5 +105,81 @@ struct ConvLaunch {
   double a = 0.0, b = 1.0, dt = 0.0;                     // out = a u0 + b (ucur + dt L(ucur))
 };
 hipError_t launch_convect_stage(const ConvLaunch& L, hipStream_t s);
+
+// ---- batched 2D solves (pd_batch.hip)
+constexpr int kMaxNC2D = 81;      // (N+1)^2 for N = 8
+constexpr int kNsBlocksBatch = 64;
+
+// One problem of a batch (device-resident array, one per precision: the tile counts and the
+// sigma-partial offsets depend on the tile shape of that precision).
+struct BProb {
+  int nx, ny, N, NC;
+  long long dof_off, ndof, ncells;
+  int ntx, nty;          // operator tiles of the chosen tile variant
+  int sig_off, nsig;     // partials of <p, A p> written by the operator kernel
+  int nupd;              // blocks per problem of the streaming kernels (= partials of <r, r>)
+  int nns;               // node-sum blocks of the null-space projection
+  int variant;
+  double c0, c1, alpha;  // operator coefficients: alpha M + c0 (x-part) + c1 (y-part)
+  double rtol;
+  double ru;             // refinement: FP32 iterations pause once their residual dropped by ru
+};
+
+// Arguments shared by the batched kernels (passed by value). The streaming, projection and
+// finalize kernels serve the problems of `list` (count entries); block b of a streaming kernel
+// belongs to list entry i with upd_off[i] <= b < upd_off[i+1].
+struct BatchIter {
+  const BProb* probs;
+  CgState* st;           // one CG state per problem
+  const int* list;       // problem indices
+  const int* upd_off;    // cumulative streaming blocks over list, count + 1 entries
+  const int* ns_off;     // cumulative node-sum blocks over list, count + 1 entries
+  int count, upd_blocks, ns_blocks;
+  int want;              // serve problems with mode64 == want (-1: any; -2: residual check)
+  int skip_fin;          // non-iterating kernels skip finished problems
+  double* rho;           // problems x 2 x kMaxStreamPartials (iteration parity)
+  double* sig;           // sigma partials (one buffer per precision)
+  double* tmp;           // problems x kMaxStreamPartials
+  double* nsp;           // problems x kNsBlocksBatch x kMaxNC2D node-sum partials
+  double* corr;          // problems x kMaxNC2D null-space corrections
+  const double* pnull;   // 9 x 81 projectors onto null(R~ - L~), by degree
+  const int* kbase;      // device iteration base of the replayed chunk
+  int koff;              // iteration offset of this launch within the chunk
+};
+
+// Problems of one (degree, tile variant) group served by one operator launch.
+struct BatchGroup {
+  int N, variant;
+  const int* grp;        // problem indices (device)
+  const int* toff;       // cumulative tiles, ng + 1 entries (device)
+  int ng;
+  unsigned blocks;
+};
+
+// fuse: CG iteration form (skips problems whose done flag is set or whose mode differs from
+// it.want); else y = A x for the group's problems that are not finished.
+hipError_t launch_apply_batch(const BatchIter& it, const BatchGroup& g, bool fp32, bool fuse,
+                              const void* x, const void* pold, void* pnew, void* y,
+                              const OpTables& tb, hipStream_t s);
+hipError_t launch_update_batch(const BatchIter& it, bool fp32, void* x, const void* p,
+                               const void* q, void* r, hipStream_t s);
+// Streaming passes over the list (problems with fin set are skipped except by mode 1):
+// 0: r64 = b - q64 (partials of <r64, r64> into tmp); 1: x64 += scale d32, d32 = 0;
+// 2: r32 = r64 / scale (partials into the rho slot koff & 1), problems in FP32 mode;
+// 3: partials of <r64, r64> into tmp; 4: r64 = b (partials into rho slot 0);
+// 5: partials of <r64, r64> into the rho slot koff & 1 for problems that just (re)started FP64
+//    iterations from a recomputed residual.
+hipError_t launch_stream_batch(int mode, const BatchIter& it, const double* b, const double* q64,
+                               double* r64, double* x64, float* v32, hipStream_t s);
+// what 0: aux = sum; 1: refinement start; 2: FP64 start; 3: chunk-end decision (see kernel)
+hipError_t launch_finalize_batch(int what, const BatchIter& it, hipStream_t s);
+hipError_t launch_project_null_batch(const BatchIter& it, double* v, hipStream_t s);
+hipError_t launch_tick(int* kbase, int by, hipStream_t s);
+hipError_t launch_zero_all(bool fp32, void* v, long long n, hipStream_t s);
+// reset every state: maxit, tol2, precision mode (0 FP32 refinement, 1 FP64)
+hipError_t launch_state_init_batch(CgState* st, int count, int maxit, double tol2, int mode64,
+                                   hipStream_t s);
+// tile counts of the 2D operator for a tile variant (host helper)
+void tiles2d(int N, bool fp32, int variant, int nx, int ny, int* ntx, int* nty);
 
 }  // namespace pdk

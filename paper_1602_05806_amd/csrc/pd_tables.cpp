@@ -160,7 +160,10 @@ bool build_table(int N, Table1D* t, std::string* err) {
     for (int m = 0; m < n; ++m) t->Kv[p * n + m] = t->w[m] * dlag(xi, n, p, xi[m]) / t->w[p];
   }
   // Null space of (R~ - L~): the cell-periodic solutions of D P = 0. Eigenvectors of
-  // S = (R~-L~)^T (R~-L~) with eigenvalue below 1e-12 * max.
+  // S = (R~-L~)^T (R~-L~) whose eigenvalue (a squared singular value of R~-L~) is below
+  // (1e-8 ||(R~, L~)||_F)^2. The scale is that of R~ and L~ themselves, not of S: for N = 1,
+  // R~ - L~ vanishes up to rounding and every eigenvalue of S is rounding noise. Over degrees
+  // 0..8 the null singular values are below 1e-15 and the others above 8e-3 of that norm.
   double S[kMaxn * kMaxn], V[kMaxn * kMaxn], lam[kMaxn];
   for (int p = 0; p < n; ++p)
     for (int q = 0; q < n; ++q) {
@@ -170,12 +173,12 @@ bool build_table(int N, Table1D* t, std::string* err) {
       S[p * n + q] = s;
     }
   jacobi_eig(n, S, V, lam);
-  double lmax = 0;
-  for (int i = 0; i < n; ++i) lmax = std::fmax(lmax, std::fabs(lam[i]));
+  double ref2 = 0;
+  for (int i = 0; i < n * n; ++i) ref2 += t->Rt[i] * t->Rt[i] + t->Lt[i] * t->Lt[i];
   t->nnull = 0;
   std::memset(t->Pnull, 0, sizeof(t->Pnull));
   for (int i = 0; i < n; ++i) {
-    if (lmax == 0.0 || std::fabs(lam[i]) <= 1e-12 * lmax) {
+    if (std::fabs(lam[i]) <= 1e-16 * ref2) {
       ++t->nnull;
       for (int p = 0; p < n; ++p)
         for (int q = 0; q < n; ++q) t->Pnull[p * n + q] += V[p * n + i] * V[q * n + i];

@@ -147,6 +147,10 @@ __global__ void k_state_init(CgState* st, int maxit, double rtol) {
     st->maxit = maxit;
     st->done = 0;
     st->status = 0;
+    st->restart_k = -1;
+    st->even_stop = 0;
+    st->fresh = 0;
+    st->scale = 1.0;
   }
 }
 
@@ -157,6 +161,9 @@ __global__ void k_state_set(CgState* st, int maxit, double tol2) {
     st->maxit = maxit;
     st->done = 0;
     st->status = 0;
+    st->restart_k = -1;
+    st->even_stop = 0;
+    st->fresh = 0;
   }
 }
 

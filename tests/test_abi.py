@@ -39,3 +39,27 @@ def test_setup_rejects_bad_arguments_without_touching_the_device(pd):
     with pytest.raises(pd.PdError) as e:
         pd.pd_setup(2, (4, 4), (1.0, 1.0), 2, 1e-3, 0.6, 0.0, periodic_mask=1, stream=0)
     assert e.value.code == pd.PD_EINVAL
+
+
+def test_host_tables_match_oracle(pd):
+    """The library's host-built FP64 tables (nodes, weights, pressure blocks and the null-space
+    projector the solves use) equal the oracle's for every degree. Odd degrees have a
+    two-dimensional cell-periodic kernel; for N = 1, R~ - L~ vanishes identically, so the
+    projector is the identity."""
+    import numpy as np
+    from oracle.basis import tables
+    from oracle.operators import null_basis_tiled
+    for N in range(9):
+        t = tables(N)
+        n = N + 1
+        got = {w: np.array(pd.pd_table_1d(N, w)) for w in range(6)}
+        assert np.abs(got[pd.PD_TAB_NODES] - t.xi).max() <= 1e-15
+        assert np.abs(got[pd.PD_TAB_WEIGHTS] - t.w).max() <= 1e-15
+        for which, blk in ((pd.PD_TAB_L, t.Lblk), (pd.PD_TAB_C, t.Cblk), (pd.PD_TAB_R, t.Rblk)):
+            assert np.abs(got[which].reshape(n, n) - blk).max() <= 1e-11 * np.abs(blk).max()
+        Z = null_basis_tiled(1, N)
+        assert np.abs(got[pd.PD_TAB_PNULL].reshape(n, n) - Z @ Z.T).max() <= 1e-12
+        assert round(float(np.trace(got[pd.PD_TAB_PNULL].reshape(n, n)))) == (1 if N % 2 == 0 else 2)
+    import pytest
+    with pytest.raises(pd.PdError):
+        pd.pd_table_1d(9, 0)

@@ -1,0 +1,294 @@
+"""GPU parity of the batched 2D pressure solver: each problem of a batch against the oracle's
+direct minimum-norm solution, against the same problem solved alone, graph replay against
+eager launches, per-problem status isolation, the autotuner cache, and the full 64-problem
+workload through properties that hold at any size (FP64 oracle residual, orthogonality to the
+null space) plus direct solutions of the smaller problems.
+
+Every case prints its parameters before touching the GPU so that a failure names its case."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import layout
+from oracle.operators import Grid, apply_operator, null_basis_tiled, apply_along
+from oracle.solvers import FastDiag
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+DT = 5e-4
+
+# (nx, ny, Lx, Ly, N): ragged shapes (not multiples of any tile), 1-cell-wide strips, every
+# degree 0..8, odd degrees (4-dimensional null space) and unequal cell sizes
+SMALL = [(5, 3, 1.0, 0.7, 3), (16, 16, 1.0, 1.0, 6), (9, 17, 1.3, 1.0, 2), (1, 4, 1.0, 1.0, 2),
+         (11, 7, 1.0, 1.0, 8), (3, 2, 0.5, 1.0, 0), (13, 5, 1.0, 1.0, 5), (24, 19, 1.0, 1.2, 1),
+         (7, 8, 1.0, 1.0, 4), (10, 12, 2.0, 1.0, 7), (33, 9, 1.0, 1.0, 3), (2, 2, 1.0, 1.0, 6)]
+
+
+def dev(a):
+    import torch
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def mass_norm(g, T):
+    W = np.ones(g.shape())
+    for d in range(g.dim):
+        shp = [1] * g.dim
+        shp[g.dim - 1 - d] = -1
+        W = W * np.tile(g.tab.w, g.cells[d]).reshape(shp)
+    return np.sqrt(np.sum(W * T ** 2))
+
+
+def make_batch(pd, probs, flags=0):
+    ncell = [(p[0], p[1]) for p in probs]
+    length = [(p[2], p[3]) for p in probs]
+    N = [p[4] for p in probs]
+    return pd.pd_batch_setup(ncell, length, N, DT, flags)
+
+
+def packed_rhs(probs, seed0):
+    parts = []
+    for j, p in enumerate(probs):
+        nd = p[0] * p[1] * (p[4] + 1) ** 2
+        parts.append(synthetic.random_rhs(seed0 + j, nd))
+    return parts
+
+
+def test_batch_layout_and_args(pd):
+    print("batch layout", flush=True)
+    B = make_batch(pd, SMALL)
+    nd = [p[0] * p[1] * (p[4] + 1) ** 2 for p in SMALL]
+    assert B.offsets == list(np.concatenate([[0], np.cumsum(nd)]))
+    for prec in (pd.PD_FP64, pd.PD_FP32):
+        v = pd.pd_batch_variants(B, prec)
+        assert len(v) == len(SMALL) and set(v) <= {0, 1, 2}
+    with pytest.raises(pd.PdError):
+        pd.pd_batch_configure(B, pd.PD_BCFG_CHUNK, 7)
+    with pytest.raises(pd.PdError):
+        pd.pd_batch_configure(B, 99, 1)
+    import torch
+    x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+    with pytest.raises(pd.PdError):
+        pd.pd_batch_cg_solve(B, pd.PD_FP32, x, x, 1e-10, 10)
+    B.close()
+    with pytest.raises(pd.PdError):
+        pd.pd_batch_setup([(4, 4)], [(1.0, 1.0)], [9], DT)
+    with pytest.raises(pd.PdError):
+        pd.pd_batch_setup([(0, 4)], [(1.0, 1.0)], [2], DT)
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_batch_matches_direct_and_single(pd, prec):
+    """Every problem of the batch equals the oracle's minimum-norm direct solution and the same
+    problem solved alone by pd_cg_solve."""
+    import torch
+    print(f"batch small prec={prec}", flush=True)
+    B = make_batch(pd, SMALL)
+    parts = packed_rhs(SMALL, 500)
+    b = np.concatenate(parts)
+    x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+    rc, infos = pd.pd_batch_cg_solve(B, prec, dev(b), x, 1e-12, 200000)
+    assert rc == pd.PD_OK, infos
+    xh = x.cpu().numpy()
+    for j, p in enumerate(SMALL):
+        nx, ny, Lx, Ly, N = p
+        print(f"  problem {j}: {p} info={infos[j]}", flush=True)
+        assert infos[j]["status"] == pd.PD_OK
+        # FP64 stops on its recurrence residual, which drifts below the true one over thousands
+        # of iterations (6.4e-12 true at 8.4e-13 recurrence after 6048 iterations for N = 7);
+        # the refinement stops on the recomputed FP64 residual itself
+        assert infos[j]["rel_res_true"] <= (1e-11 if prec == pd.PD_FP64 else 1e-12)
+        g = Grid((nx, ny), (Lx, Ly), N)
+        xj = xh[B.offsets[j]:B.offsets[j + 1]]
+        ref = FastDiag(g).solve(layout.blocked_to_tensor(parts[j], (nx, ny), N + 1), 0.0, DT)
+        got = layout.blocked_to_tensor(xj, (nx, ny), N + 1)
+        err = mass_norm(g, got - ref) / mass_norm(g, ref)
+        print(f"    error vs direct {err:.2e}", flush=True)
+        assert err <= 1e-10
+        ctx = pd.pd_setup(2, (nx, ny), (Lx, Ly), N, DT, 0.6, 0.0)
+        xs = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+        info = pd.pd_cg_solve(ctx, 0, prec, dev(parts[j]), xs, 1e-12, 200000)
+        assert info["status"] == pd.PD_OK
+        alone = layout.blocked_to_tensor(xs.cpu().numpy(), (nx, ny), N + 1)
+        assert mass_norm(g, got - alone) <= 2e-10 * mass_norm(g, ref)
+        if prec == pd.PD_FP64:
+            # the recurrence is the same CG in the same precision: the iteration counts agree up
+            # to the rounding of the dot products (different partial-sum order)
+            assert abs(info["iters"] - infos[j]["iters"]) <= max(3, info["iters"] // 50)
+        ctx.close()
+    B.close()
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_batch_graph_equals_eager(pd, prec):
+    """Replaying the captured graph and enqueueing the same kernels one by one give bit-identical
+    results; in FP64 the chunk length only changes when the host notices convergence."""
+    import torch
+    print(f"batch graph vs eager prec={prec}", flush=True)
+    probs = SMALL[:6]
+    B = make_batch(pd, probs)
+    b = dev(np.concatenate(packed_rhs(probs, 600)))
+    outs = []
+    for graph, chunk in [(1, 64), (0, 64), (1, 16)]:
+        pd.pd_batch_configure(B, pd.PD_BCFG_GRAPH, graph)
+        pd.pd_batch_configure(B, pd.PD_BCFG_CHUNK, chunk)
+        x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+        rc, infos = pd.pd_batch_cg_solve(B, prec, b, x, 1e-11, 100000)
+        assert rc == pd.PD_OK
+        outs.append((x.cpu().numpy(), [i["iters"] for i in infos]))
+    assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
+    if prec == pd.PD_FP64:
+        assert np.array_equal(outs[0][0], outs[2][0]) and outs[0][1] == outs[2][1]
+    else:
+        ref = outs[0][0]
+        d = np.linalg.norm(outs[2][0] - ref) / np.linalg.norm(ref)
+        print(f"  chunk 16 vs 64 relative difference {d:.2e}", flush=True)
+        assert d <= 1e-7
+    # a second solve on the same batch (graph reused) reproduces the first
+    pd.pd_batch_configure(B, pd.PD_BCFG_GRAPH, 1)
+    pd.pd_batch_configure(B, pd.PD_BCFG_CHUNK, 64)
+    x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+    pd.pd_batch_cg_solve(B, prec, b, x, 1e-11, 100000)
+    assert np.array_equal(x.cpu().numpy(), outs[0][0])
+    B.close()
+
+
+def test_batch_status_isolation(pd):
+    """A zero right-hand side, a NaN and an iteration cap in single problems do not disturb the
+    other problems of the batch."""
+    import torch
+    probs = SMALL[:5]
+    print("batch status isolation", flush=True)
+    B = make_batch(pd, probs)
+    parts = packed_rhs(probs, 700)
+    parts[1] = np.zeros_like(parts[1])
+    parts[3] = parts[3].copy()
+    parts[3][7] = np.nan
+    b = dev(np.concatenate(parts))
+    for prec in (pd.PD_FP64, pd.PD_FP32_REFINE64):
+        print(f"  prec={prec}", flush=True)
+        x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+        rc, infos = pd.pd_batch_cg_solve(B, prec, b, x, 1e-12, 200000)
+        assert rc == pd.PD_EBREAKDOWN
+        st = [i["status"] for i in infos]
+        assert st == [pd.PD_OK, pd.PD_OK, pd.PD_OK, pd.PD_EBREAKDOWN, pd.PD_OK]
+        xh = x.cpu().numpy()
+        assert np.all(xh[B.offsets[1]:B.offsets[2]] == 0.0)
+        for j in (0, 2, 4):
+            nx, ny, Lx, Ly, N = probs[j]
+            g = Grid((nx, ny), (Lx, Ly), N)
+            ref = FastDiag(g).solve(layout.blocked_to_tensor(parts[j], (nx, ny), N + 1), 0.0, DT)
+            got = layout.blocked_to_tensor(xh[B.offsets[j]:B.offsets[j + 1]], (nx, ny), N + 1)
+            assert mass_norm(g, got - ref) <= 1e-9 * mass_norm(g, ref)
+    # iteration cap: every problem stops at maxit (FP64 exactly; refinement at the cap too)
+    parts = packed_rhs(probs, 710)
+    x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+    rc, infos = pd.pd_batch_cg_solve(B, pd.PD_FP64, dev(np.concatenate(parts)), x, 1e-14, 5)
+    assert rc == pd.PD_ENOCONV
+    assert all(i["status"] == pd.PD_ENOCONV and i["iters"] == 5 for i in infos)
+    B.close()
+
+
+def test_batch_autotune_cache(pd, tmp_path):
+    """The autotuner writes one choice per (degree, size bucket, precision) to the cache file;
+    a batch set up later without tuning reads the same choices; results do not depend on them
+    beyond rounding."""
+    import torch
+    path = str(tmp_path / "tune.txt")
+    old = os.environ.get("PD_AUTOTUNE_CACHE")
+    os.environ["PD_AUTOTUNE_CACHE"] = path
+    try:
+        probs = SMALL[:8]
+        print("batch autotune", flush=True)
+        B = make_batch(pd, probs, pd.PD_BATCH_AUTOTUNE)
+        v64 = pd.pd_batch_variants(B, pd.PD_FP64)
+        v32 = pd.pd_batch_variants(B, pd.PD_FP32)
+        lines = open(path).read().split("\n")
+        keys = {ln.split()[0]: int(ln.split()[1]) for ln in lines if ln.strip()}
+        def bucket(s):
+            b = 1
+            while b * 2 <= s:
+                b *= 2
+            return b
+        want = set()
+        for p in probs:
+            for pr in ("fp32", "fp64"):
+                want.add(f"gfx950:pressure2d:N{p[4]}:s{bucket(max(p[0], p[1]))}:{pr}")
+        assert set(keys) == want
+        for j, p in enumerate(probs):
+            k = f"gfx950:pressure2d:N{p[4]}:s{bucket(max(p[0], p[1]))}"
+            assert v32[j] == keys[k + ":fp32"] and v64[j] == keys[k + ":fp64"]
+        B2 = make_batch(pd, probs)
+        assert pd.pd_batch_variants(B2, pd.PD_FP64) == v64
+        assert pd.pd_batch_variants(B2, pd.PD_FP32) == v32
+        b = dev(np.concatenate(packed_rhs(probs, 800)))
+        x1 = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+        x2 = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+        pd.pd_batch_cg_solve(B, pd.PD_FP64, b, x1, 1e-12, 100000)
+        os.environ.pop("PD_AUTOTUNE_CACHE")
+        B3 = make_batch(pd, probs)                   # no cache: variant 0 everywhere
+        assert pd.pd_batch_variants(B3, pd.PD_FP64) == [0] * len(probs)
+        pd.pd_batch_cg_solve(B3, pd.PD_FP64, b, x2, 1e-12, 100000)
+        assert float((x1 - x2).norm()) <= 1e-9 * float(x1.norm())
+        for bb in (B, B2, B3):
+            bb.close()
+    finally:
+        if old is None:
+            os.environ.pop("PD_AUTOTUNE_CACHE", None)
+        else:
+            os.environ["PD_AUTOTUNE_CACHE"] = old
+
+
+def test_batch_full_workload(pd):
+    """The 64-problem workload (sides 45..253, N 2..8, about 77M DoFs) solved in FP32 with FP64
+    residual replacement to 1e-10: every problem's FP64 residual b - A x recomputed by the oracle
+    (matrix-free, direction by direction) is <= 1e-10 ||b||, x is orthogonal to the null space,
+    and the problems with at most 80 cells per side match the oracle's direct solution."""
+    import torch
+    specs = synthetic.batch_problems(seed=4)
+    probs = [(p["side"], p["side"], 1.0, 1.0, p["N"]) for p in specs]
+    print(f"batch full workload: {len(probs)} problems", flush=True)
+    B = make_batch(pd, probs)
+    parts = []
+    for p, sp in zip(probs, specs):
+        r = synthetic.random_rhs(sp["seed"], p[0] * p[1] * (p[4] + 1) ** 2)
+        parts.append(r / np.linalg.norm(r))
+    b = dev(np.concatenate(parts))
+    x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+    rc, infos = pd.pd_batch_cg_solve(B, pd.PD_FP32_REFINE64, b, x, 1e-10, 300000)
+    print(f"  rc={rc} ms={infos[0]['ms']:.1f} max iters={max(i['iters'] for i in infos)}", flush=True)
+    for j, (p, i) in enumerate(zip(probs, infos)):
+        print(f"  {j:2d} side {p[0]:3d} N {p[4]} status {i['status']:2d} iters {i['iters']:6d} "
+              f"replacements {i['outer_iters']:4d} restarts {i['restarts']:3d} "
+              f"fp64 from {i['fallback_iter']:6d} res {i['rel_res_true']:.2e}", flush=True)
+    assert rc == pd.PD_OK
+    xh = x.cpu().numpy()
+    del x, b
+    for j, (p, sp) in enumerate(zip(probs, specs)):
+        nx, ny, Lx, Ly, N = p
+        n = N + 1
+        g = Grid((nx, ny), (Lx, Ly), N)
+        X = layout.blocked_to_tensor(xh[B.offsets[j]:B.offsets[j + 1]], (nx, ny), n)
+        Bt = layout.blocked_to_tensor(parts[j], (nx, ny), n)
+        Z = [null_basis_tiled(nx, N), null_basis_tiled(ny, N)]
+        C = apply_along(Z[1].T, apply_along(Z[0].T, Bt, 1), 0)
+        Bp = Bt - apply_along(Z[1], apply_along(Z[0], C, 1), 0)
+        R = Bp - apply_operator(g, X, 0.0, DT)
+        rel = np.linalg.norm(R) / np.linalg.norm(Bp)
+        zx = np.abs(apply_along(Z[1].T, apply_along(Z[0].T, X, 1), 0)).max()
+        # two FP64 evaluations of b - A x (the GPU's, which stopped the solve, and this one)
+        # differ by rounding of order eps |A| |x|: about 1e-10 ||b|| for the N = 7 problems,
+        # whose condition numbers reach 1e8 - 1e9; each term has 3 (N+1) + 1 products
+        roundoff = 3 * (N + 1) * np.finfo(float).eps * \
+            np.linalg.norm(apply_operator(g, X, 0.0, DT, absolute=True)) / np.linalg.norm(Bp)
+        if N % 2 == 1 and N > 3:
+            print(f"  problem {j} {p}: rel res {rel:.2e} rounding scale {roundoff:.2e}", flush=True)
+        assert rel <= 1.05e-10 + roundoff, (j, p, rel, roundoff, infos[j])
+        assert zx <= 1e-9 * np.abs(X).max(), (j, p, zx)
+        if nx <= 80:
+            ref = FastDiag(g).solve(Bt, 0.0, DT)
+            err = mass_norm(g, X - ref) / mass_norm(g, ref)
+            print(f"  problem {j} {p}: rel res {rel:.2e} err {err:.2e}", flush=True)
+            assert err <= 1e-6
+    B.close()

@@ -88,7 +88,10 @@ def _solve_case(pd, dim, cells, N, op, prec, project_rhs, rtol, seed):
 
 
 @pytest.mark.parametrize("dim,cells,N", [(2, (16, 16), 3), (2, (12, 9), 6), (2, (7, 8), 2),
-                                         (3, (5, 4, 6), 3), (3, (4, 4, 4), 4)])
+                                         (2, (3, 2), 0), (2, (9, 7), 1), (2, (6, 5), 5),
+                                         (2, (5, 6), 7), (2, (4, 5), 8),
+                                         (3, (5, 4, 6), 3), (3, (4, 4, 4), 4), (3, (4, 3, 5), 1),
+                                         (3, (3, 4, 2), 0)])
 @pytest.mark.parametrize("prec", [0, 2])
 def test_pressure_solve_matches_min_norm(pd, dim, cells, N, prec):
     info, err = _solve_case(pd, dim, cells, N, 0, prec, True, 1e-12, 11)

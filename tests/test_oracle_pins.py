@@ -13,7 +13,7 @@ from oracle import layout
 from oracle.basis import Tables, gauss_legendre_01
 from oracle.operators import (Grid, pressure_operator, viscous_operator, grad_1d, div_rhs,
                               grad_update, null_basis_1d, project_null, stiffness, full_mass,
-                              apply_at, pressure_1d)
+                              apply_at, pressure_1d, apply_operator, null_basis_tiled)
 from oracle.solvers import FastDiag, cg, dense_min_norm
 from oracle.step import StepOracle, convective_rate, rk3, dual_to_main, main_to_dual
 import synthetic
@@ -243,6 +243,37 @@ def test_apply_at_matches_assembled():
         idx = np.stack([np.random.default_rng(3).integers(0, s, 30) for s in g.shape()], 1)
         got = apply_at(g, x, idx, 0.7, 0.3)
         assert np.abs(got - y[tuple(idx.T)]).max() <= 1e-12 * np.abs(y).max()
+
+
+def test_apply_operator_matches_assembled():
+    """The matrix-free direction-by-direction application used for full-size residual checks
+    equals the assembled operator alpha M + beta K."""
+    for cells, N in [((5, 4), 3), ((7, 3), 0), ((3, 4, 3), 2), ((4, 2, 3), 5)]:
+        g = Grid(cells, (1.0, 0.9, 1.2)[:len(cells)], N)
+        x = np.random.default_rng(5).standard_normal(g.shape())
+        for alpha, beta in [(0.0, 1e-3), (0.7, 0.3)]:
+            y = ((full_mass(g) * alpha + beta * stiffness(g)) @ x.reshape(-1)).reshape(g.shape())
+            got = apply_operator(g, x, alpha, beta)
+            assert np.abs(got - y).max() <= 1e-13 * np.abs(y).max()
+            A = abs(full_mass(g) * alpha + beta * stiffness(g))
+            ya = (A @ np.abs(x).reshape(-1)).reshape(g.shape())
+            got = apply_operator(g, x, alpha, beta, absolute=True)
+            assert np.abs(got - ya).max() <= 1e-13 * np.abs(ya).max()
+
+
+@pytest.mark.parametrize("N", range(9))
+def test_null_basis_tiled_spans_null_space(N):
+    """The tiled cell-periodic kernel spans the same space as the SVD kernel of the full 1D
+    periodic weak gradient (dimension 1 for even N, 2 for odd N)."""
+    for nc in (1, 2, 5, 8):
+        Z = null_basis_1d(nc, N) if nc > 1 else null_basis_1d(3, N)[: N + 1] * np.sqrt(3)
+        if nc == 1:
+            Z, _ = np.linalg.qr(Z)
+        T = null_basis_tiled(nc, N)
+        assert T.shape == Z.shape
+        assert np.abs(T.T @ T - np.eye(T.shape[1])).max() <= 1e-12
+        assert np.abs(T @ T.T - Z @ Z.T).max() <= 1e-10
+        assert T.shape[1] == (1 if N % 2 == 0 else 2)
 
 
 @pytest.mark.parametrize("N,order", [(1, 0.7), (2, 2.7), (3, 2.7), (4, 4.7)])
