@@ -12,7 +12,20 @@ under "fp32_refine64". The roofline object covers the fused CG operator-apply ke
 duration is measured with HIP events around every launch inside the timed pressure solves.
 The CPU baseline is the oracle's assembled-CSR CG timed in a 1-thread subprocess.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rand2d_256_N6|rand3d_64_N4]
+Workload batch2d_64 (separate invocation): 64 independent 2D periodic pressure problems, sides
+and degrees drawn uniformly from 32..256 and 2..8 (seed 4), each with a standard-normal RHS scaled
+to unit norm. One "step" is one batched solve of all problems to relative residual 1e-10 (FP32
+iterations with FP64 residual replacement; FP64 CG timed beside it). value = sum over problems of
+DoFs x iterations / wall time of the solve.
+
+Workload adjoint3d_48_N3 (separate invocation): 3D periodic 48^3 cells, N = 3, 20 steps (dt 1e-3,
+nu 1e-2, theta 0.6) from a seeded smoothed random velocity; one "step" is one gradient of the final
+kinetic energy with respect to the initial velocity (checkpoints every 5 steps, solves to 1e-13),
+followed by the central finite-difference check on 16 directions. value = pressure DoFs x
+pressure-CG iterations (forward, recomputed and adjoint solves) / wall time of the gradients.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload rand2d_256_N6|rand3d_64_N4|batch2d_64|adjoint3d_48_N3]
 """
 import argparse
 import json
@@ -117,6 +130,165 @@ print(json.dumps(dict(value=g.ndof * {iters} / dt, seconds=dt, cores=len(os.sche
                       f"{r['cores']} cores available)"}
 
 
+def bench_batch(args, pd, torch):
+    """Batched workload: one step = one pd_batch_cg_solve of every problem from x = 0."""
+    import numpy as np
+    import synthetic
+    cfg = dict(synthetic.CONFIGS[args.workload])
+    specs = synthetic.batch_problems(seed=cfg["seed"], count=cfg["count"],
+                                     side_range=cfg["side_range"], N_range=cfg["N_range"])
+    B = pd.pd_batch_setup([(p["side"], p["side"]) for p in specs], [(1.0, 1.0)] * len(specs),
+                          [p["N"] for p in specs], cfg["dt"],
+                          pd.PD_BATCH_AUTOTUNE if args.autotune else 0)
+    parts = []
+    for p in specs:
+        r = synthetic.random_rhs(p["seed"], p["side"] ** 2 * (p["N"] + 1) ** 2)
+        parts.append(r / np.linalg.norm(r))
+    b = torch.tensor(np.concatenate(parts), dtype=torch.float64, device="cuda")
+    del parts
+    ndofs = [B.offsets[j + 1] - B.offsets[j] for j in range(B.count)]
+    res = {}
+    for name, prec in (("fp32_refine64", pd.PD_FP32_REFINE64), ("fp64", pd.PD_FP64)):
+        x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            pd.pd_batch_cg_solve(B, prec, b, x, cfg["rtol"], cfg["maxit"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        work, infos = 0, None
+        for _ in range(args.steps):
+            rc, infos = pd.pd_batch_cg_solve(B, prec, b, x, cfg["rtol"], cfg["maxit"])
+            if rc != pd.PD_OK:
+                raise RuntimeError(f"batched solve failed ({name}): rc {rc}")
+            work += sum(n * i["iters"] for n, i in zip(ndofs, infos))
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        bytes_it = 40.0 if prec == pd.PD_FP32_REFINE64 else 80.0
+        res[name] = dict(seconds=secs, work=work, infos=infos, bytes_it=bytes_it)
+        del x
+    r32, r64 = res["fp32_refine64"], res["fp64"]
+    value = r32["work"] / r32["seconds"]
+    falls = [j for j, i in enumerate(r32["infos"]) if i["fallback_iter"] >= 0]
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DoF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r32["seconds"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "problems": B.count, "total_dofs": B.total,
+                   "sides": [p["side"] for p in specs], "N": [p["N"] for p in specs],
+                   "rtol": cfg["rtol"], "dt": cfg["dt"], "autotune": bool(args.autotune)},
+        "solve_ms": 1e3 * r32["seconds"] / args.steps,
+        "max_iters": max(i["iters"] for i in r32["infos"]),
+        "fp64_fallback_problems": falls,
+        "algorithmic_gbs_cg": r32["work"] * r32["bytes_it"] / r32["seconds"] / 1e9,
+        "rel_res_true_max": max(i["rel_res_true"] for i in r32["infos"]),
+        "fp64": {"value": r64["work"] / r64["seconds"], "unit": "DoF-iterations/s",
+                 "solve_ms": 1e3 * r64["seconds"] / args.steps,
+                 "max_iters": max(i["iters"] for i in r64["infos"]),
+                 "algorithmic_gbs_cg": r64["work"] * r64["bytes_it"] / r64["seconds"] / 1e9,
+                 "rel_res_true_max": max(i["rel_res_true"] for i in r64["infos"])},
+        "speedup_solve_vs_fp64": r64["seconds"] / r32["seconds"],
+        "per_problem": [{"side": p["side"], "N": p["N"], "iters_refine": i["iters"],
+                         "fp64_from": i["fallback_iter"], "iters_fp64": k["iters"]}
+                        for p, i, k in zip(specs, r32["infos"], r64["infos"])],
+    }
+    B.close()
+    print(json.dumps(line))
+
+
+def bench_adjoint(args, pd, torch):
+    """Adjoint workload: one step = one gradient of the final kinetic energy with respect to the
+    initial velocity (forward rollout with checkpoints, backward with segment recomputation and
+    pd_step_adjoint), solves to 1e-13; then the central finite-difference check."""
+    import synthetic
+    from paper_1602_05806_amd import autograd as ag
+    cfg = dict(synthetic.CONFIGS[args.workload])
+    cells, N = cfg["cells"], cfg["N"]
+    ctx = pd.pd_setup(3, cells, cfg["lengths"], N, cfg["dt"], cfg["theta"], cfg["nu"])
+    pd.pd_configure(ctx, pd.PD_CFG_P_RTOL, 1e-13)
+    pd.pd_configure(ctx, pd.PD_CFG_V_RTOL, 1e-13)
+    xi, _ = pd.pd_nodes(ctx)
+    field = synthetic.FourierField(cfg["seed"], 3, cfg["kmax"], cfg["lengths"])
+    field.normalise(cfg["vmax"])
+    U = field.eval(synthetic.staggered_coords(cells, cfg["lengths"], xi))
+    u0 = [torch.tensor(synthetic.tensor_to_blocked(x, cells, N + 1), device="cuda") for x in U]
+    W = ag.quadrature_weights(ctx)
+    steps, every = cfg["steps"], cfg["checkpoint"]
+
+    def gradient():
+        ur = [x.clone().requires_grad_(True) for x in u0]
+        loss = ag.kinetic_energy(ctx, ag.Rollout.apply(ctx, steps, every, *ur), W)
+        loss.backward()
+        return float(loss.detach()), [x.grad for x in ur]
+
+    for _ in range(args.warmup):
+        gradient()
+    for k in ag.stats:
+        ag.stats[k] = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, grad = gradient()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    st = dict(ag.stats)
+    fd = []
+    unorm = float(torch.sqrt(sum((x * x).sum() for x in u0)))
+    coords = synthetic.staggered_coords(cells, cfg["lengths"], xi)
+    for k in range(args.fd_dirs):
+        fk = synthetic.FourierField(5000 + k, 3, cfg["kmax"], cfg["lengths"])
+        fk.normalise(1.0)
+        v = [torch.tensor(synthetic.tensor_to_blocked(x, cells, N + 1), device="cuda")
+             for x in fk.eval(coords)]
+        eps = 1e-6 * unorm / float(torch.sqrt(sum((x * x).sum() for x in v)))
+        with torch.no_grad():
+            fp = float(ag.kinetic_energy(ctx, ag.Rollout.apply(
+                ctx, steps, every, *[a + eps * b for a, b in zip(u0, v)]), W))
+            fm = float(ag.kinetic_energy(ctx, ag.Rollout.apply(
+                ctx, steps, every, *[a - eps * b for a, b in zip(u0, v)]), W))
+        f = (fp - fm) / (2 * eps)
+        gv = float(sum((a * b).sum() for a, b in zip(grad, v)))
+        fd.append(abs(gv - f) / abs(f))
+    ndof = ctx.ndof
+    value = ndof * st["pressure_iters"] / secs
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DoF-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * secs / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": list(cells), "N": N,
+                   "dofs_per_component": ndof, "time_steps": steps, "checkpoint_every": every,
+                   "dt": cfg["dt"], "nu": cfg["nu"], "theta": cfg["theta"], "rtol": 1e-13,
+                   "step": "gradient of the final kinetic energy (forward + adjoint)"},
+        "loss": loss,
+        "forward_steps_per_gradient": st["steps"] / args.steps,
+        "adjoint_steps_per_gradient": st["adjoint_steps"] / args.steps,
+        "pressure_iters_per_gradient": st["pressure_iters"] / args.steps,
+        "viscous_iters_per_gradient": st["viscous_iters"] / args.steps,
+        "fd_check": {"directions": args.fd_dirs, "max_rel_err": max(fd) if fd else None,
+                     "rel_errs": fd, "eps": "1e-6 ||U0|| / ||v||",
+                     "direction_kind": "smooth random Fourier fields, wavenumbers <= 6",
+                     "seeds": "5000 + k"},
+    }
+    ctx.close()
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,6 +298,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch2d_64: pick tile shapes with the autotuner (PD_AUTOTUNE_CACHE)")
+    ap.add_argument("--fd-dirs", type=int, default=16,
+                    help="adjoint3d_48_N3: finite-difference directions checked after timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the pressure path is measured on one "
@@ -143,6 +319,12 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload.startswith("batch"):
+        bench_batch(args, pd, torch)
+        return
+    if args.workload.startswith("adjoint"):
+        bench_adjoint(args, pd, torch)
+        return
     cfg = dict(synthetic.CONFIGS[args.workload])
     cfg.setdefault("steps", 1)
     dim = len(cfg["cells"])

@@ -152,6 +152,40 @@ int pd_convect(pd_ctx* ctx, void* const um[3], void* hip_stream);
  * Solver settings come from pd_configure. */
 int pd_step(pd_ctx* ctx, void* const u[3], void* p, pd_solve_info info[4], void* hip_stream);
 
+/* ---- Adjoint (transposed linearisation) of the fractional step --------------------------------
+ * The step maps the dual velocity U^n to U^{n+1} (P^n does not enter U^{n+1}). Its adjoint maps
+ * a cotangent Ubar of U^{n+1} to the cotangent of U^n, in reverse order of the step: the velocity
+ * update and pressure solve (q = A_p^+ b is symmetric, so the adjoint pressure solve is a second
+ * CG solve on A_p from zero with the same settings), B_d^T, pi_{#->*}^T, the viscous solve
+ * (A_v symmetric: a CG solve with A_v, then the mass matrix), the transposed linearisation of the
+ * explicit TVD-RK3 convection at the forward stages (Rusanov speed differentiated on the branch of
+ * the forward state), and pi_{*->#}^T. All arrays FP64; solver settings come from pd_configure.
+ * Transposes of the single operators are exposed for testing and custom adjoints. */
+
+/* out = pi^T in along direction d: dir 0 transposes pi_{*->#} (in: main layout, out: dual),
+ * dir 1 transposes pi_{#->*} (in: dual, out: main). in and out must not alias. */
+int pd_l2_project_adjoint(pd_ctx* ctx, int d, int dir, const void* in, void* out,
+                          void* hip_stream);
+
+/* ubar[d] = B_d^T bbar for every direction d (bbar: main layout; ubar[d]: dual layout of
+ * component d), B_d the divergence map of pd_rhs_div. Overwrites ubar. */
+int pd_rhs_div_adjoint(pd_ctx* ctx, const void* bbar, void* const ubar[3], void* hip_stream);
+
+/* qbar = -sum_d G_d^T ubar[d]: transpose of the velocity update of pd_project_velocity with
+ * respect to q (G_d = dt h_d^-1 M_d^-1 D_d). Overwrites qbar (main layout). */
+int pd_project_velocity_adjoint(pd_ctx* ctx, void* const ubar[3], void* qbar, void* hip_stream);
+
+/* Adjoint of pd_convect (one TVD-RK3 step of the explicit convection on the main grid) at the
+ * state um (the input of that pd_convect call, unchanged): ubar holds the cotangent of the output
+ * on entry and the cotangent of the input on return. um and ubar must not alias. */
+int pd_convect_adjoint(pd_ctx* ctx, void* const um[3], void* const ubar[3], void* hip_stream);
+
+/* Adjoint of pd_step at U^n: u holds U^n (dual components, unchanged), ubar holds the cotangent of
+ * U^{n+1} on entry and that of U^n on return. info[0..dim-1] report the adjoint viscous solves,
+ * info[3] the adjoint pressure solve (info may be NULL). Synchronises. */
+int pd_step_adjoint(pd_ctx* ctx, void* const u[3], void* const ubar[3], pd_solve_info info[4],
+                    void* hip_stream);
+
 /* Settings used by pd_step and the timing hooks (key, value):
  *   PD_CFG_STEP_PREC     PD_FP64 (default) or PD_FP32_REFINE64 for the step's solves
  *   PD_CFG_P_RTOL        pressure tolerance in pd_step (default 1e-10)

@@ -37,6 +37,8 @@ PD_TAB_NODES, PD_TAB_WEIGHTS, PD_TAB_L, PD_TAB_C, PD_TAB_R, PD_TAB_PNULL = range
 EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "pd_table_1d", "pd_apply",
             "pd_cg_solve", "pd_rhs_div", "pd_project_velocity", "pd_project_null",
             "pd_l2_project", "pd_convect", "pd_step", "pd_configure", "pd_timing",
+            "pd_l2_project_adjoint", "pd_rhs_div_adjoint", "pd_project_velocity_adjoint",
+            "pd_convect_adjoint", "pd_step_adjoint",
             "pd_batch_setup", "pd_batch_destroy", "pd_batch_last_error", "pd_batch_layout",
             "pd_batch_variants", "pd_batch_configure", "pd_batch_cg_solve"]
 
@@ -76,6 +78,12 @@ _lib.pd_configure.argtypes = [_vp, ctypes.c_int, ctypes.c_double]
 _lib.pd_timing.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                            ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_double),
                            ctypes.c_int]
+_lib.pd_l2_project_adjoint.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+_lib.pd_rhs_div_adjoint.argtypes = [_vp, _vp, ctypes.POINTER(_vp), _vp]
+_lib.pd_project_velocity_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _vp]
+_lib.pd_convect_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]
+_lib.pd_step_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                 ctypes.POINTER(pd_solve_info), _vp]
 _lib.pd_batch_setup.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                 ctypes.c_double, ctypes.c_uint, _vp]
@@ -253,6 +261,42 @@ def pd_step(ctx, u, p, stream=None):
     info = (pd_solve_info * 4)()
     rc = _lib.pd_step(ctx.handle, _vec3(ctx, u), _ptr(p, ctx.ndof, torch.float64), info,
                       ctypes.c_void_p(_stream(stream)))
+    _check(ctx, rc, allow=(PD_ENOCONV, PD_EBREAKDOWN))
+    return [i.as_dict() for i in info]
+
+
+def pd_l2_project_adjoint(ctx, d, direction, src, dst, stream=None):
+    import torch
+    _check(ctx, _lib.pd_l2_project_adjoint(ctx.handle, d, direction,
+                                           _ptr(src, ctx.ndof, torch.float64),
+                                           _ptr(dst, ctx.ndof, torch.float64),
+                                           ctypes.c_void_p(_stream(stream))))
+
+
+def pd_rhs_div_adjoint(ctx, bbar, ubar, stream=None):
+    import torch
+    _check(ctx, _lib.pd_rhs_div_adjoint(ctx.handle, _ptr(bbar, ctx.ndof, torch.float64),
+                                        _vec3(ctx, ubar), ctypes.c_void_p(_stream(stream))))
+
+
+def pd_project_velocity_adjoint(ctx, ubar, qbar, stream=None):
+    import torch
+    _check(ctx, _lib.pd_project_velocity_adjoint(ctx.handle, _vec3(ctx, ubar),
+                                                 _ptr(qbar, ctx.ndof, torch.float64),
+                                                 ctypes.c_void_p(_stream(stream))))
+
+
+def pd_convect_adjoint(ctx, um, ubar, stream=None):
+    _check(ctx, _lib.pd_convect_adjoint(ctx.handle, _vec3(ctx, um), _vec3(ctx, ubar),
+                                        ctypes.c_void_p(_stream(stream))))
+
+
+def pd_step_adjoint(ctx, u, ubar, stream=None):
+    """Adjoint of pd_step at U^n = u (unchanged): ubar in = cotangent of U^{n+1}, out = that of
+    U^n. Returns 4 solve-info dicts (adjoint viscous x, y, z; adjoint pressure)."""
+    info = (pd_solve_info * 4)()
+    rc = _lib.pd_step_adjoint(ctx.handle, _vec3(ctx, u), _vec3(ctx, ubar), info,
+                              ctypes.c_void_p(_stream(stream)))
     _check(ctx, rc, allow=(PD_ENOCONV, PD_EBREAKDOWN))
     return [i.as_dict() for i in info]
 

@@ -46,6 +46,9 @@ struct pd_ctx {
   double* s1[3] = {nullptr, nullptr, nullptr};
   double* s2[3] = {nullptr, nullptr, nullptr};
   double* qbuf = nullptr;
+  double* at[4][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
+                      {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};   // adjoint work
+  double* abar = nullptr;                             // adjoint pressure right-hand side
   CgState* hst = nullptr;      // pinned host mirror, 2 slots
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -185,16 +188,17 @@ int cg_launch(pd_ctx* c, CgRun* R) {
   L.pold = buf[k & 1];
   L.pnew = buf[(k + 1) & 1];
   L.y = R->B.q;
+  L.ev_start = L.ev_stop = nullptr;
   if (R->timed) {
     while (c->tev.size() < 2 * (size_t)(k + 1)) {
       hipEvent_t e;
       PD_HIP(c, hipEventCreate(&e));
       c->tev.push_back(e);
     }
-    PD_HIP(c, hipEventRecord(c->tev[2 * k], R->s));
+    L.ev_start = c->tev[2 * k];
+    L.ev_stop = c->tev[2 * k + 1];
   }
   PD_HIP(c, pdk::launch_apply(L, R->s));
-  if (R->timed) PD_HIP(c, hipEventRecord(c->tev[2 * k + 1], R->s));
   PD_HIP(c, pdk::launch_cg_update(R->fp32, R->x, buf[(k + 1) & 1], R->B.q, R->B.r, c->ndof, R->st,
                                   k, c->sigpart, R->nsig, R->rho[(k + 1) & 1], R->s));
   ++R->k;
@@ -544,6 +548,96 @@ int project_velocity(pd_ctx* c, const double* q, void* const u[3], hipStream_t s
   return PD_OK;
 }
 
+// Transpose of a two-cell line operator out_i = A0 in_{i+o0} + A1 in_{i+o1} (times coef and the
+// transverse weights, both diagonal): out_j = A0^T in_{j-o0} + A1^T in_{j-o1}.
+void transpose_line(pdk::LineLaunch* L) {
+  const int n = L->N + 1;
+  double t0[81], t1[81];
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      t0[q * n + p] = L->A0[p * n + q];
+      t1[q * n + p] = L->A1[p * n + q];
+    }
+  for (int i = 0; i < n * n; ++i) {
+    L->A0[i] = t0[i];
+    L->A1[i] = t1[i];
+  }
+  L->o0 = -L->o0;
+  L->o1 = -L->o1;
+}
+
+// Transpose of pi_{*->#} (dir 0) or pi_{#->*} (dir 1) along d.
+int l2_project_T(pd_ctx* c, int d, int dir, const double* in, double* out, hipStream_t s) {
+  pdk::LineLaunch L;
+  fill_line_common(c, &L);
+  const int n = c->n;
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      L.A0[p * n + q] = c->tab.ML[p * n + q] / c->tab.w[p];
+      L.A1[p * n + q] = c->tab.MR[p * n + q] / c->tab.w[p];
+    }
+  L.d = d;
+  L.o0 = dir == 0 ? -1 : 0;
+  L.o1 = dir == 0 ? 0 : 1;
+  L.coef = 1.0;
+  transpose_line(&L);
+  L.in = in;
+  L.out = out;
+  PD_HIP(c, pdk::launch_line(L, s));
+  return PD_OK;
+}
+
+// ubar_d = accum ubar_d + B_d^T bbar (B_d^T = h_d^-1 W_perp D_d: main -> dual of direction d)
+int rhs_div_T(pd_ctx* c, const double* bbar, void* const ubar[3], double accum, hipStream_t s) {
+  const int n = c->n;
+  for (int d = 0; d < c->dim; ++d) {
+    if (!ubar[d]) return fail(c, PD_EINVAL, "null velocity component");
+    pdk::LineLaunch L;
+    fill_line_common(c, &L);
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q) {
+        L.A0[p * n + q] = c->tab.Rt[q * n + p];
+        L.A1[p * n + q] = -c->tab.Lt[q * n + p];
+      }
+    L.d = d;
+    L.o0 = -1;
+    L.o1 = 0;
+    L.coef = 1.0 / c->h[d];
+    L.wperp = 1;
+    transpose_line(&L);
+    L.accum = accum;
+    L.in = bbar;
+    L.out = (double*)ubar[d];
+    PD_HIP(c, pdk::launch_line(L, s));
+  }
+  return PD_OK;
+}
+
+// qbar = -sum_d G_d^T ubar_d (G_d = dt h_d^-1 M_d^-1 D_d: the velocity update's gradient)
+int project_velocity_T(pd_ctx* c, void* const ubar[3], double* qbar, hipStream_t s) {
+  const int n = c->n;
+  for (int d = 0; d < c->dim; ++d) {
+    if (!ubar[d]) return fail(c, PD_EINVAL, "null velocity component");
+    pdk::LineLaunch L;
+    fill_line_common(c, &L);
+    for (int p = 0; p < n; ++p)
+      for (int r = 0; r < n; ++r) {
+        L.A0[p * n + r] = c->tab.Rt[p * n + r] / c->tab.w[p];
+        L.A1[p * n + r] = -c->tab.Lt[p * n + r] / c->tab.w[p];
+      }
+    L.d = d;
+    L.o0 = 1;
+    L.o1 = 0;
+    L.coef = -c->dt / c->h[d];
+    transpose_line(&L);
+    L.accum = d == 0 ? 0.0 : 1.0;
+    L.in = (const double*)ubar[d];
+    L.out = qbar;
+    PD_HIP(c, pdk::launch_line(L, s));
+  }
+  return PD_OK;
+}
+
 int ensure_step_buffers(pd_ctx* c) {
   const size_t n = (size_t)c->ndof;
   for (int d = 0; d < c->dim; ++d) {
@@ -555,46 +649,128 @@ int ensure_step_buffers(pd_ctx* c) {
   return dev_alloc(c, &c->qbuf, n);
 }
 
-int convect(pd_ctx* c, double* const um[3], hipStream_t s) {
+int ensure_adjoint_buffers(pd_ctx* c) {
+  int rc = ensure_step_buffers(c);
+  if (rc) return rc;
+  const size_t n = (size_t)c->ndof;
+  for (int k = 0; k < 4; ++k)
+    for (int d = 0; d < c->dim; ++d)
+      if ((rc = dev_alloc(c, &c->at[k][d], n))) return rc;
+  return dev_alloc(c, &c->abar, n);
+}
+
+void fill_conv_common(const pd_ctx* c, pdk::ConvLaunch* L) {
+  L->dim = c->dim;
+  L->N = c->N;
+  for (int d = 0; d < 3; ++d) {
+    L->nc[d] = c->nc[d];
+    L->h[d] = c->h[d];
+  }
+  const int n = c->n;
+  for (int i = 0; i < 9; ++i) {
+    L->w[i] = i < n ? c->tab.w[i] : 0;
+    L->phi0[i] = i < n ? c->tab.phi0[i] : 0;
+    L->phi1[i] = i < n ? c->tab.phi1[i] : 0;
+  }
+  for (int i = 0; i < 81; ++i) L->Kv[i] = i < n * n ? c->tab.Kv[i] : 0;
+  L->dt = c->dt;
+}
+
+// The first two Shu-Osher stages: s1 = U + dt L(U); s2 = 3/4 U + 1/4 (s1 + dt L(s1)).
+int rk_stages12(pd_ctx* c, double* const um[3], double* const s1[3], double* const s2[3],
+                hipStream_t s) {
   pdk::ConvLaunch L;
+  fill_conv_common(c, &L);
+  for (int d = 0; d < c->dim; ++d) {
+    L.ucur[d] = um[d];
+    L.u0[d] = um[d];
+    L.out[d] = s1[d];
+  }
+  L.a = 0.0;
+  L.b = 1.0;
+  PD_HIP(c, pdk::launch_convect_stage(L, s));
+  for (int d = 0; d < c->dim; ++d) {
+    L.ucur[d] = s1[d];
+    L.out[d] = s2[d];
+  }
+  L.a = 0.75;
+  L.b = 0.25;
+  PD_HIP(c, pdk::launch_convect_stage(L, s));
+  return PD_OK;
+}
+
+int convect(pd_ctx* c, double* const um[3], hipStream_t s) {
+  // Shu-Osher TVD RK3: U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
+  //                    U  = 1/3 U + 2/3 (U2 + dt L(U2))
+  int rc = rk_stages12(c, um, c->s1, c->s2, s);
+  if (rc) return rc;
+  pdk::ConvLaunch L;
+  fill_conv_common(c, &L);
+  for (int d = 0; d < c->dim; ++d) {
+    L.ucur[d] = c->s2[d];
+    L.u0[d] = um[d];
+    L.out[d] = um[d];
+  }
+  L.a = 1.0 / 3.0;
+  L.b = 2.0 / 3.0;
+  PD_HIP(c, pdk::launch_convect_stage(L, s));
+  return PD_OK;
+}
+
+// Adjoint of the three RK stages at the forward states U (um), U1 (s1), U2 (s2): given the
+// cotangent fbar of the RK3 result, write the cotangent of U into out. Work vectors: wa, wb
+// (fbar, wa, wb and out distinct). In reverse stage order:
+//   U2bar = 2/3 (fbar + dt J(U2)^T fbar),        Ubar  = 1/3 fbar
+//   U1bar = 1/4 (U2bar + dt J(U1)^T U2bar),      Ubar += 3/4 U2bar
+//   Ubar += U1bar + dt J(U)^T U1bar
+int convect_adjoint(pd_ctx* c, double* const um[3], double* const s1[3], double* const s2[3],
+                    double* const fbar[3], double* const wa[3], double* const wb[3],
+                    double* const out[3], hipStream_t s) {
+  const long long n = c->ndof;
+  pdk::ConvAdjLaunch L;
   L.dim = c->dim;
   L.N = c->N;
   for (int d = 0; d < 3; ++d) {
     L.nc[d] = c->nc[d];
     L.h[d] = c->h[d];
   }
-  const int n = c->n;
+  const int nn = c->n;
   for (int i = 0; i < 9; ++i) {
-    L.w[i] = i < n ? c->tab.w[i] : 0;
-    L.phi0[i] = i < n ? c->tab.phi0[i] : 0;
-    L.phi1[i] = i < n ? c->tab.phi1[i] : 0;
+    L.w[i] = i < nn ? c->tab.w[i] : 0;
+    L.phi0[i] = i < nn ? c->tab.phi0[i] : 0;
+    L.phi1[i] = i < nn ? c->tab.phi1[i] : 0;
   }
-  for (int i = 0; i < 81; ++i) L.Kv[i] = i < n * n ? c->tab.Kv[i] : 0;
+  for (int i = 0; i < 81; ++i) L.Kv[i] = i < nn * nn ? c->tab.Kv[i] : 0;
   L.dt = c->dt;
-  // Shu-Osher TVD RK3: U1 = U + dt L(U); U2 = 3/4 U + 1/4 (U1 + dt L(U1));
-  //                    U  = 1/3 U + 2/3 (U2 + dt L(U2))
   for (int d = 0; d < c->dim; ++d) {
-    L.ucur[d] = um[d];
-    L.u0[d] = um[d];
-    L.out[d] = c->s1[d];
+    L.state[d] = s2[d];
+    L.obar[d] = fbar[d];
+    L.acc[d] = nullptr;
+    L.out[d] = wa[d];
   }
-  L.a = 0.0;
-  L.b = 1.0;
-  PD_HIP(c, pdk::launch_convect_stage(L, s));
-  for (int d = 0; d < c->dim; ++d) {
-    L.ucur[d] = c->s1[d];
-    L.out[d] = c->s2[d];
-  }
-  L.a = 0.75;
-  L.b = 0.25;
-  PD_HIP(c, pdk::launch_convect_stage(L, s));
-  for (int d = 0; d < c->dim; ++d) {
-    L.ucur[d] = c->s2[d];
-    L.out[d] = um[d];
-  }
-  L.a = 1.0 / 3.0;
+  L.acc_coef = 0.0;
   L.b = 2.0 / 3.0;
-  PD_HIP(c, pdk::launch_convect_stage(L, s));
+  PD_HIP(c, pdk::launch_convect_adj_stage(L, s));
+  for (int d = 0; d < c->dim; ++d)
+    PD_HIP(c, pdk::launch_axpby(1.0 / 3.0, fbar[d], 0.0, out[d], n, s));
+  for (int d = 0; d < c->dim; ++d) {
+    L.state[d] = s1[d];
+    L.obar[d] = wa[d];
+    L.out[d] = wb[d];
+  }
+  L.b = 0.25;
+  PD_HIP(c, pdk::launch_convect_adj_stage(L, s));
+  for (int d = 0; d < c->dim; ++d)
+    PD_HIP(c, pdk::launch_axpby(0.75, wa[d], 1.0, out[d], n, s));
+  for (int d = 0; d < c->dim; ++d) {
+    L.state[d] = um[d];
+    L.obar[d] = wb[d];
+    L.acc[d] = out[d];
+    L.out[d] = out[d];
+  }
+  L.acc_coef = 1.0;
+  L.b = 1.0;
+  PD_HIP(c, pdk::launch_convect_adj_stage(L, s));
   return PD_OK;
 }
 
@@ -698,7 +874,10 @@ void pd_destroy(pd_ctx* c) {
     if (c->um[d]) (void)hipFree(c->um[d]);
     if (c->s1[d]) (void)hipFree(c->s1[d]);
     if (c->s2[d]) (void)hipFree(c->s2[d]);
+    for (int k = 0; k < 4; ++k)
+      if (c->at[k][d]) (void)hipFree(c->at[k][d]);
   }
+  if (c->abar) (void)hipFree(c->abar);
   if (c->hst) (void)hipHostFree(c->hst);
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -846,6 +1025,117 @@ int pd_step(pd_ctx* c, void* const u[3], void* p, pd_solve_info info[4], void* h
   // 6. velocity update, 7. P^{n+1} = (q - (1-theta) P^n) / theta
   if ((rc = project_velocity(c, c->qbuf, u, s))) return rc;
   PD_HIP(c, pdk::launch_axpby(1.0 / c->theta, c->qbuf, -(1.0 - c->theta) / c->theta, (double*)p, n, s));
+  PD_HIP(c, hipStreamSynchronize(s));
+  return PD_OK;
+}
+
+int pd_l2_project_adjoint(pd_ctx* c, int d, int dir, const void* in, void* out,
+                          void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (d < 0 || d >= c->dim || (dir != 0 && dir != 1)) return fail(c, PD_EINVAL, "bad direction");
+  if (!in || !out || in == out) return fail(c, PD_EINVAL, "null or aliased array");
+  c->last_stream = S(hip_stream);
+  return l2_project_T(c, d, dir, (const double*)in, (double*)out, S(hip_stream));
+}
+
+int pd_rhs_div_adjoint(pd_ctx* c, const void* bbar, void* const ubar[3], void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!bbar || !ubar) return fail(c, PD_EINVAL, "null array");
+  c->last_stream = S(hip_stream);
+  return rhs_div_T(c, (const double*)bbar, ubar, 0.0, S(hip_stream));
+}
+
+int pd_project_velocity_adjoint(pd_ctx* c, void* const ubar[3], void* qbar, void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!ubar || !qbar) return fail(c, PD_EINVAL, "null array");
+  c->last_stream = S(hip_stream);
+  return project_velocity_T(c, ubar, (double*)qbar, S(hip_stream));
+}
+
+int pd_convect_adjoint(pd_ctx* c, void* const um[3], void* const ubar[3], void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!um || !ubar) return fail(c, PD_EINVAL, "null array");
+  for (int d = 0; d < c->dim; ++d)
+    if (!um[d] || !ubar[d] || um[d] == ubar[d]) return fail(c, PD_EINVAL, "null or aliased component");
+  int rc = ensure_adjoint_buffers(c);
+  if (rc) return rc;
+  hipStream_t s = S(hip_stream);
+  c->last_stream = s;
+  const long long n = c->ndof;
+  double* u0[3] = {(double*)um[0], (double*)um[1], c->dim == 3 ? (double*)um[2] : nullptr};
+  if ((rc = rk_stages12(c, u0, c->s1, c->s2, s))) return rc;
+  // the cotangent is read from ubar into a work vector, the result written back into ubar
+  for (int d = 0; d < c->dim; ++d)
+    PD_HIP(c, pdk::launch_axpby(1.0, (const double*)ubar[d], 0.0, c->at[0][d], n, s));
+  double* out[3] = {(double*)ubar[0], (double*)ubar[1], c->dim == 3 ? (double*)ubar[2] : nullptr};
+  return convect_adjoint(c, u0, c->s1, c->s2, c->at[0], c->at[1], c->at[2], out, s);
+}
+
+int pd_step_adjoint(pd_ctx* c, void* const u[3], void* const ubar[3], pd_solve_info info[4],
+                    void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!u || !ubar) return fail(c, PD_EINVAL, "null array");
+  for (int d = 0; d < c->dim; ++d)
+    if (!u[d] || !ubar[d] || u[d] == ubar[d]) return fail(c, PD_EINVAL, "null or aliased component");
+  int rc = ensure_adjoint_buffers(c);
+  if (rc) return rc;
+  hipStream_t s = S(hip_stream);
+  c->last_stream = s;
+  const long long n = c->ndof;
+  pd_solve_info loc[4];
+  std::memset(loc, 0, sizeof(loc));
+  for (int d = 0; d < 4; ++d) loc[d].fallback_iter = -1;
+  double* T1[3] = {c->at[0][0], c->at[0][1], c->at[0][2]};
+  double* T2[3] = {c->at[1][0], c->at[1][1], c->at[1][2]};
+  double* T3[3] = {c->at[2][0], c->at[2][1], c->at[2][2]};
+  double* T4[3] = {c->at[3][0], c->at[3][1], c->at[3][2]};
+  // forward states of the step's convection: U = pi_{*->#} U^n, and the RK stage inputs
+  for (int d = 0; d < c->dim; ++d)
+    if ((rc = l2_project(c, d, 0, (const double*)u[d], c->um[d], s))) return rc;
+  if (c->convection)
+    if ((rc = rk_stages12(c, c->um, c->s1, c->s2, s))) return rc;
+  // 6: U^{n+1}_d = U*_d - G_d q  ->  qbar = -sum_d G_d^T ubar_d
+  if ((rc = project_velocity_T(c, ubar, c->qbuf, s))) return rc;
+  // 5: q = A_p^+ b (symmetric)  ->  bbar = A_p^+ qbar
+  PD_HIP(c, pdk::launch_zero(false, c->abar, n, s));
+  rc = solve(c, PD_OP_PRESSURE, c->step_prec, c->qbuf, c->abar, c->p_rtol, c->maxit, &loc[3], s);
+  if (rc != PD_OK) {
+    if (info) std::memcpy(info, loc, sizeof(loc));
+    return rc;
+  }
+  // b = sum_d B_d U*_d  ->  U*bar_d = ubar_d + B_d^T bbar
+  for (int d = 0; d < c->dim; ++d)
+    PD_HIP(c, pdk::launch_axpby(1.0, (const double*)ubar[d], 0.0, T1[d], n, s));
+  void* t1v[3] = {T1[0], T1[1], T1[2]};
+  if ((rc = rhs_div_T(c, c->abar, t1v, 1.0, s))) return rc;
+  // 4: U*_d = pi_{#->*} U#_d
+  for (int d = 0; d < c->dim; ++d)
+    if ((rc = l2_project_T(c, d, 1, T1[d], T2[d], s))) return rc;
+  // 3: U#_d = A_v^-1 M F_d  ->  Fbar_d = M A_v^-1 U#bar_d (A_v symmetric, M diagonal)
+  double** fbar = T2;
+  if (c->nu > 0.0) {
+    for (int d = 0; d < c->dim; ++d) {
+      PD_HIP(c, pdk::launch_zero(false, T3[d], n, s));
+      rc = solve(c, PD_OP_VISCOUS, c->step_prec, T2[d], T3[d], c->v_rtol, c->maxit, &loc[d], s);
+      if (rc != PD_OK) {
+        if (info) std::memcpy(info, loc, sizeof(loc));
+        return rc;
+      }
+      PD_HIP(c, pdk::launch_mass(c->dim, c->N, c->tab.w, T3[d], T1[d], c->ncells, s));
+    }
+    fbar = T1;
+  }
+  // 2: F = RK3(U)  ->  Ubar = RK3 adjoint at the forward stages (um, s1, s2)
+  double** ubm = fbar;
+  if (c->convection) {
+    double** wa = fbar == T1 ? T2 : T1;
+    if ((rc = convect_adjoint(c, c->um, c->s1, c->s2, fbar, wa, T3, T4, s))) return rc;
+    ubm = T4;
+  }
+  // 1: U_d = pi_{*->#} U^n_d  ->  ubar_d = pi_{*->#}^T Ubar_d
+  for (int d = 0; d < c->dim; ++d)
+    if ((rc = l2_project_T(c, d, 0, ubm[d], (double*)ubar[d], s))) return rc;
+  if (info) std::memcpy(info, loc, sizeof(loc));
   PD_HIP(c, hipStreamSynchronize(s));
   return PD_OK;
 }

@@ -15,6 +15,8 @@
 // FUSE = 1 is the CG form: the search direction p = r + beta p_old is formed while loading
 // (beta read from the device-resident CG state), stored for the owned cells, and the block sums of
 // <p, A p> feed the grid reduction that sets alpha = rho / <p, A p>.
+#include <hip/hip_ext.h>
+
 #include "pd_apply2d.h"
 #include "pd_device.h"
 #include "pd_launch.h"
@@ -341,13 +343,16 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   if (g.blocks > (unsigned long long)kMaxPartials) return hipErrorInvalidValue;
   const unsigned G = (unsigned)g.blocks;
   const bool pf = L.prefetch != 0;
+  // extended launch: the optional start/stop events are taken from the dispatch itself (no
+  // separate marker packets around the kernel)
+  hipEvent_t e0 = L.ev_start, e1 = L.ev_stop;
   if (L.dim == 2) {
 #define PD_A2D(VV)                                                                              \
   if (L.fuse) {                                                                                 \
-    if (pf) hipLaunchKernelGGL((k_apply2d<T, N, VV, 1, 1>), dim3(G), dim3(256), 0, s, a, B);    \
-    else hipLaunchKernelGGL((k_apply2d<T, N, VV, 1, 0>), dim3(G), dim3(256), 0, s, a, B);       \
+    if (pf) hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 1, 1>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B); \
+    else hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 1, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);   \
   } else {                                                                                      \
-    hipLaunchKernelGGL((k_apply2d<T, N, VV, 0, 0>), dim3(G), dim3(256), 0, s, a, B);           \
+    hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 0, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);       \
   }
     if (L.tile_variant == 1) { PD_A2D(1) }
     else if (L.tile_variant == 2) { PD_A2D(2) }
@@ -356,10 +361,10 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   } else {
     constexpr int NTH = Tile3D<N>::NTH;
     if (L.fuse) {
-      if (pf) hipLaunchKernelGGL((k_apply3d<T, N, 1, 1>), dim3(G), dim3(NTH), 0, s, a, B);
-      else hipLaunchKernelGGL((k_apply3d<T, N, 1, 0>), dim3(G), dim3(NTH), 0, s, a, B);
+      if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 1>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+      else hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     } else {
-      hipLaunchKernelGGL((k_apply3d<T, N, 0, 0>), dim3(G), dim3(NTH), 0, s, a, B);
+      hipExtLaunchKernelGGL((k_apply3d<T, N, 0, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     }
   }
   return hipGetLastError();

@@ -33,6 +33,8 @@ struct ApplyLaunch {
   int prefetch = 1;          // prefetch the next tile (2D) / next plane's halo (3D) into registers
   int tile_variant = 0;      // 2D tile shape (0 = largest fitting, 1 / 2 = one / two sizes smaller)
   const OpTables* tab = nullptr;
+  hipEvent_t ev_start = nullptr;   // optional events stamped at the kernel's start and end
+  hipEvent_t ev_stop = nullptr;
 };
 
 hipError_t launch_apply(const ApplyLaunch& L, hipStream_t s);
@@ -105,6 +107,22 @@ struct ConvLaunch {
   double a = 0.0, b = 1.0, dt = 0.0;                     // out = a u0 + b (ucur + dt L(ucur))
 };
 hipError_t launch_convect_stage(const ConvLaunch& L, hipStream_t s);
+
+// Adjoint of one RK stage out = a u0 + b (ucur + dt L(ucur)): with obar the cotangent of out,
+// out_adj = acc_coef acc + b (obar + dt J(state)^T obar) is the cotangent reaching ucur = state
+// (plus acc); the a u0 part is a plain scaling done by the caller.
+struct ConvAdjLaunch {
+  int dim = 2, N = 0;
+  int nc[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  double w[9], phi0[9], phi1[9], Kv[81];
+  const double* state[3] = {nullptr, nullptr, nullptr};
+  const double* obar[3] = {nullptr, nullptr, nullptr};
+  const double* acc[3] = {nullptr, nullptr, nullptr};
+  double* out[3] = {nullptr, nullptr, nullptr};
+  double acc_coef = 0.0, b = 1.0, dt = 0.0;
+};
+hipError_t launch_convect_adj_stage(const ConvAdjLaunch& L, hipStream_t s);
 
 // ---- batched 2D solves (pd_batch.hip)
 constexpr int kMaxNC2D = 81;      // (N+1)^2 for N = 8

@@ -28,7 +28,7 @@ CONFIGS = {
                          theta=0.6, nu=1e-3, field="fourier", kmax=6, seed=3, vmax=0.1,
                          rtol=1e-10),
     "batch2d_64": dict(dim=2, count=64, side_range=(32, 256), N_range=(2, 8), seed=4,
-                       dt=5e-4, rtol=1e-10),
+                       dt=5e-4, rtol=1e-10, maxit=400000),
     "adjoint3d_48_N3": dict(dim=3, cells=(48, 48, 48), lengths=(1.0, 1.0, 1.0), N=3, dt=1e-3,
                             theta=0.6, nu=1e-2, field="fourier", kmax=6, seed=5, vmax=0.1,
                             steps=20, checkpoint=5, fd_dirs=16),
