@@ -194,8 +194,10 @@ int pd_step_adjoint(pd_ctx* ctx, void* const u[3], void* const ubar[3], pd_solve
  *   PD_CFG_CONVECTION    1 (default) = explicit convection on, 0 = off (unsteady Stokes step)
  *   PD_CFG_RU_FACTOR     PD_FP32_REFINE64: the FP32 residual is replaced by the FP64 residual
  *                        b - A x each time it has dropped by this factor (default 0.1)
- *   PD_CFG_TIMING        1 = record HIP events around every launch of the operator kernel
- *                        inside solves (see pd_timing), 0 (default) = off
+ *   PD_CFG_TIMING        s >= 1: the dispatch of every s-th launch of the operator kernel
+ *                        inside solves carries start/stop HIP events (see pd_timing; 1 = every
+ *                        launch; events add a few microseconds per timed launch), 0 (default) =
+ *                        off
  *   PD_CFG_CHECK_EVERY   convergence poll interval of the solve loop in iterations (default 32)
  *   PD_CFG_KZ            3D operator kernel: planes per column segment (0 = automatic)
  *   PD_CFG_TILES_PER_WG  2D operator kernel: tiles per persistent workgroup (0 = automatic)
@@ -214,10 +216,11 @@ int pd_configure(pd_ctx* ctx, int key, double value);
 
 /* Timing hook: total milliseconds and launch count of the fused CG operator-apply kernel of
  * precision prec (PD_FP64: FP64 solves; PD_FP32: inner solves of PD_FP32_REFINE64) launched inside
- * pressure solves since the last reset (reset != 0 clears after reading). Each launch is
- * bracketed by HIP events on the solve's stream; launches after convergence (early exits) are
- * not counted. Requires PD_CFG_TIMING = 1. bytes_per_launch: algorithmic bytes of one launch
- * (reads r and p_old, writes p and A p: 4 words per DoF). Synchronises with the last stream. */
+ * pressure solves since the last reset (reset != 0 clears after reading). The sampled launches
+ * (every PD_CFG_TIMING-th; requires PD_CFG_TIMING >= 1) carry start/stop HIP events in their
+ * dispatch on the solve's stream; launches after convergence (early exits) are not counted.
+ * bytes_per_launch: algorithmic bytes of one launch (reads r, p_old and x, writes p, A p and x:
+ * 6 words per DoF). Synchronises with the last stream. */
 int pd_timing(pd_ctx* ctx, int prec, double* total_ms, long long* launches,
               double* bytes_per_launch, int reset);
 

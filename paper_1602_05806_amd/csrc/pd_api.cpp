@@ -144,9 +144,12 @@ struct CgBuffers {
 };
 
 // A chunked conjugate-gradient run on the device, FP64 or FP32 vectors (FP64 scalars).
-// Iteration k = apply kernel (p_k = r_k + beta_k p_{k-1}, q = A p_k, partials of <p_k, q>) +
-// update kernel (x += alpha p_k, r -= alpha q, partials of <r_{k+1}, r_{k+1}>). The run can be
-// stopped by a host predicate on the polled state and resumed at the exact iteration.
+// Iteration k = apply kernel (x += alpha_{k-1} p_{k-1}, p_k = r_k + beta_k p_{k-1}, q = A p_k,
+// partials of <p_k, q>) + update kernel (r -= alpha_k q, partials of <r_{k+1}, r_{k+1}>): the
+// x update rides on the apply, which reads p_{k-1} anyway (9 vector words per DoF and
+// iteration instead of 10); the one still pending when the run stops is flushed at the end.
+// The run can be stopped by a host predicate on the polled state and resumed at the exact
+// iteration.
 struct CgRun {
   int op = 0;
   bool fp32 = false;
@@ -168,7 +171,8 @@ int cg_prepare(pd_ctx* c, CgRun* R) {
   R->rho[0] = c->rhopart;
   R->rho[1] = c->rhopart + pdk::kMaxStreamPartials;
   R->L = base_launch(c, R->op, R->fp32);
-  R->L.fuse = 1;
+  R->L.fuse = 2;
+  R->L.xsol = R->x;
   R->L.st = R->st;
   R->L.nrho = R->nrho;
   R->L.sigpart = c->sigpart;
@@ -189,25 +193,27 @@ int cg_launch(pd_ctx* c, CgRun* R) {
   L.pnew = buf[(k + 1) & 1];
   L.y = R->B.q;
   L.ev_start = L.ev_stop = nullptr;
-  if (R->timed) {
-    while (c->tev.size() < 2 * (size_t)(k + 1)) {
+  if (R->timed && k % c->timing == 0) {       // every timing-th launch carries events
+    const size_t j = (size_t)(k / c->timing);
+    while (c->tev.size() < 2 * (j + 1)) {
       hipEvent_t e;
       PD_HIP(c, hipEventCreate(&e));
       c->tev.push_back(e);
     }
-    L.ev_start = c->tev[2 * k];
-    L.ev_stop = c->tev[2 * k + 1];
+    L.ev_start = c->tev[2 * j];
+    L.ev_stop = c->tev[2 * j + 1];
   }
   PD_HIP(c, pdk::launch_apply(L, R->s));
-  PD_HIP(c, pdk::launch_cg_update(R->fp32, R->x, buf[(k + 1) & 1], R->B.q, R->B.r, c->ndof, R->st,
-                                  k, c->sigpart, R->nsig, R->rho[(k + 1) & 1], R->s));
+  PD_HIP(c, pdk::launch_cg_update(R->fp32, R->B.q, R->B.r, c->ndof, R->st, k, c->sigpart,
+                                  R->nsig, R->rho[(k + 1) & 1], R->s));
   ++R->k;
   return PD_OK;
 }
 
 // Launch iterations in chunks until the device reports done or stop(polled state) is true; the
 // next chunk is already queued while a chunk's state is inspected. On return the stream is
-// synchronised, *fin holds the final state and R->k the number of completed iterations.
+// synchronised, x holds the iterate of the last completed iteration, *fin the final state and
+// R->k the number of completed iterations.
 template <typename Pred>
 int cg_run_until(pd_ctx* c, CgRun* R, int maxit, Pred stop, CgState* fin) {
   const int chunk = c->check_every > 0 ? c->check_every : 32;
@@ -231,6 +237,7 @@ int cg_run_until(pd_ctx* c, CgRun* R, int maxit, Pred stop, CgState* fin) {
     slot ^= 1;
     if (R->k > maxit + 2 * chunk) finished = true;
   }
+  PD_HIP(c, pdk::launch_x_flush(R->fp32, R->x, R->B.pa, R->B.pb, c->ndof, R->st, R->s));
   int rc = read_state(c, R->st, fin, R->s);
   if (rc) return rc;
   if (fin->done) R->k = fin->iter;
@@ -240,9 +247,12 @@ int cg_run_until(pd_ctx* c, CgRun* R, int maxit, Pred stop, CgState* fin) {
 void cg_collect_timing(pd_ctx* c, const CgRun& R) {
   if (!R.timed) return;
   const int tslot = R.fp32 ? 1 : 0;
-  for (int i = 0; i < R.k && 2 * (size_t)i + 1 < c->tev.size(); ++i) {
+  // sampled launches of the completed iterations (launches queued after the stop exit at once)
+  for (int k = 0; k < R.k; k += c->timing) {
+    const size_t j = (size_t)(k / c->timing);
+    if (2 * j + 1 >= c->tev.size()) break;
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, c->tev[2 * i], c->tev[2 * i + 1]) == hipSuccess) {
+    if (hipEventElapsedTime(&ms, c->tev[2 * j], c->tev[2 * j + 1]) == hipSuccess) {
       c->t_ms[tslot] += ms;
       c->t_cnt[tslot] += 1;
     }
@@ -1167,7 +1177,8 @@ int pd_configure(pd_ctx* c, int key, double v) {
       c->ru_factor = v;
       break;
     case PD_CFG_TIMING:
-      c->timing = v != 0.0;
+      if (!(v >= 0.0 && v <= 1e6)) return fail(c, PD_EINVAL, "PD_CFG_TIMING must be in [0, 1e6]");
+      c->timing = (int)v;
       break;
     case PD_CFG_CHECK_EVERY:
       if (!(v >= 1)) return fail(c, PD_EINVAL, "check interval must be >= 1");
@@ -1202,8 +1213,8 @@ int pd_timing(pd_ctx* c, int prec, double* total_ms, long long* launches,
   const int k = prec == PD_FP32 ? 1 : 0;
   if (total_ms) *total_ms = c->t_ms[k];
   if (launches) *launches = c->t_cnt[k];
-  // fused CG apply: reads r and p_old, writes p and A p (4 words per DoF)
-  if (bytes_per_launch) *bytes_per_launch = 4.0 * (double)c->ndof * (k ? 4.0 : 8.0);
+  // fused CG apply: reads r, p_old and x, writes p, A p and x (6 words per DoF)
+  if (bytes_per_launch) *bytes_per_launch = 6.0 * (double)c->ndof * (k ? 4.0 : 8.0);
   if (reset) {
     c->t_ms[k] = 0;
     c->t_cnt[k] = 0;

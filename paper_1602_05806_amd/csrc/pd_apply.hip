@@ -84,6 +84,8 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   const int gi = wrapi(ui, a.nx), gj = wrapi(uj, a.ny);
   const size_t plane = (size_t)a.nx * a.ny;
   T beta = T(0);
+  bool xupd = false;   // FUSE = 2: x += xalpha p_old on the owned z-line
+  T xalpha = T(0);
 
   auto zbase = [&](int k) -> size_t {
     return (((size_t)wrap_small(k, a.nz) * a.ny + gj) * a.nx + gi) * NC + lp;
@@ -92,7 +94,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   {
     // first two planes of this thread's z-line; the CG scalars are reduced while they load
     const size_t bp = zbase(k0 - 1), bc = zbase(k0);
-    T pp[n], pc[n];
+    T pp[n], pc[n], xc[FUSE == 2 ? n : 1];
 #pragma unroll
     for (int l3 = 0; l3 < n; ++l3) {
       zp[l3] = xg[bp + l3 * NP];
@@ -101,17 +103,26 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
         pp[l3] = pg[bp + l3 * NP];
         pc[l3] = pg[bc + l3 * NP];
       }
+      if (FUSE == 2) xc[l3] = a.xsol[bc + l3 * NP];
     }
     if (FUSE) {
-      const IterScalars sc = iteration_scalars<NTH>(a.st, a.kbase ? *a.kbase + a.k : a.k,
-                                                    a.rho_cur, a.nrho, blockIdx.x == 0);
+      const int k = a.kbase ? *a.kbase + a.k : a.k;
+      const IterScalars sc = iteration_scalars<NTH>(a.st, k, a.rho_cur, a.nrho, blockIdx.x == 0);
       if (sc.stop) return;
       beta = (T)sc.beta;
+      if (FUSE == 2) {
+        xupd = k >= 1 && a.st->xk == k - 1;
+        xalpha = (T)a.st->alpha;
+        if (xupd && blockIdx.x == 0 && threadIdx.x == 0) a.st->xused = k - 1;
+      }
 #pragma unroll
       for (int l3 = 0; l3 < n; ++l3) {
         zp[l3] = zp[l3] + beta * pp[l3];
         zc[l3] = zc[l3] + beta * pc[l3];
-        if (valid) png[bc + l3 * NP] = zc[l3];
+        if (valid) {
+          png[bc + l3 * NP] = zc[l3];
+          if (FUSE == 2 && xupd) a.xsol[bc + l3 * NP] = xc[l3] + xalpha * pc[l3];
+        }
       }
     }
   }
@@ -193,11 +204,13 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     __syncthreads();
     // plane k+1: own z-line and (prefetch) halo, in flight during the x/y phases
     const size_t bn = zbase(k + 1);
-    T pn[n];
+    const bool own_next = valid && (k + 1 < k1);
+    T pn[n], xn[FUSE == 2 ? n : 1];
 #pragma unroll
     for (int l3 = 0; l3 < n; ++l3) {
       zn[l3] = xg[bn + l3 * NP];
       if (FUSE) pn[l3] = pg[bn + l3 * NP];
+      if (FUSE == 2 && xupd && own_next) xn[l3] = a.xsol[bn + l3 * NP];
     }
     if constexpr (PREF) {
       if (k + 1 < k1) halo_load(k + 1);
@@ -226,11 +239,13 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     }
     __syncthreads();
     if (FUSE) {
-      const bool own_next = valid && (k + 1 < k1);
 #pragma unroll
       for (int l3 = 0; l3 < n; ++l3) {
         zn[l3] = zn[l3] + beta * pn[l3];
-        if (own_next) png[bn + l3 * NP] = zn[l3];
+        if (own_next) {
+          png[bn + l3 * NP] = zn[l3];
+          if (FUSE == 2 && xupd) a.xsol[bn + l3 * NP] = xn[l3] + xalpha * pn[l3];
+        }
       }
     }
     {  // own z-line (l1, l2) from registers; final values
@@ -334,6 +349,7 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   a.rho_cur = L.rho_cur;
   a.nrho = L.nrho;
   a.sigpart = L.sigpart;
+  a.xsol = (T*)L.xsol;
   const Blk<T, N> B = make_blk<T, N>(*L.tab);
   const Geom g = geometry<T, N>(L);
   a.ntx = g.ntx;
@@ -349,8 +365,8 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   if (L.dim == 2) {
 #define PD_A2D(VV)                                                                              \
   if (L.fuse) {                                                                                 \
-    if (pf) hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 1, 1>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B); \
-    else hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 1, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);   \
+    if (pf) hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 2, 1>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B); \
+    else hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 2, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);   \
   } else {                                                                                      \
     hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 0, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);       \
   }
@@ -361,8 +377,8 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   } else {
     constexpr int NTH = Tile3D<N>::NTH;
     if (L.fuse) {
-      if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 1>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
-      else hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+      if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 2, 1>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+      else hipExtLaunchKernelGGL((k_apply3d<T, N, 2, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     } else {
       hipExtLaunchKernelGGL((k_apply3d<T, N, 0, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     }

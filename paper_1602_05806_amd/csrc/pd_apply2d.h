@@ -24,6 +24,7 @@ struct ApplyArgs {
   const double* rho_cur;
   int nrho;
   double* sigpart;
+  T* xsol;            // FUSE = 2: CG iterate, x += alpha_{k-1} p_old on owned cells
 };
 
 __device__ __forceinline__ int wrapi(int i, int m) {
@@ -119,6 +120,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
   T* __restrict__ yg = a.y;
   const int tid = threadIdx.x;
   T rvi[TY][JI], pvi[TY][JI], rvh[2][JH], pvh[2][JH];
+  T xvi[FUSE == 2 ? TY : 1][FUSE == 2 ? JI : 1];   // FUSE = 2: x of the owned cells
 
   // global element index of box element e of box row bj (bj in 0..TY+1) of the tile at (tx0, ty0)
   auto gindex = [&](int tx0, int ty0, int bj, int e) -> size_t {
@@ -149,6 +151,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
           } else if (j < JI) {
             rvi[bj - 1][j] = rv;
             pvi[bj - 1][j] = pv;
+            if (FUSE == 2 && e >= NC && e < (TX + 1) * NC) xvi[bj - 1][j] = a.xsol[g];
           }
         }
       }
@@ -157,11 +160,18 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
 
   if (t_begin < t_end) stage_load(t_begin);
   T beta = T(0);
+  bool xupd = false;   // FUSE = 2: x += xalpha p_old on the owned cells
+  T xalpha = T(0);
   if (FUSE) {
-    const IterScalars sc = iteration_scalars<256>(a.st, a.kbase ? *a.kbase + a.k : a.k,
-                                                  a.rho_cur, a.nrho, t_begin == 0);
+    const int k = a.kbase ? *a.kbase + a.k : a.k;
+    const IterScalars sc = iteration_scalars<256>(a.st, k, a.rho_cur, a.nrho, t_begin == 0);
     if (sc.stop) return;
     beta = (T)sc.beta;
+    if (FUSE == 2) {
+      xupd = k >= 1 && a.st->xk == k - 1;
+      xalpha = (T)a.st->alpha;
+      if (xupd && t_begin == 0 && threadIdx.x == 0) a.st->xused = k - 1;
+    }
   }
   double dot = 0.0;
   for (int tile = t_begin; tile < t_end; ++tile) {
@@ -182,8 +192,11 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
             if (!halo) {
               const int bi = e / NC;                 // box column: own cells are 1..TX
               const int ui = tx0 + bi - 1, uj = ty0 + bj - 1;
-              if (bi >= 1 && bi <= TX && ui < a.nx && uj < a.ny)
-                png[((size_t)uj * a.nx + ui) * NC + (e - bi * NC)] = v;
+              if (bi >= 1 && bi <= TX && ui < a.nx && uj < a.ny) {
+                const size_t g = ((size_t)uj * a.nx + ui) * NC + (e - bi * NC);
+                png[g] = v;
+                if (FUSE == 2 && xupd) a.xsol[g] = xvi[bj - 1][j] + xalpha * pvi[bj - 1][j];
+              }
             }
           }
           xs[(bj * BX + (halo ? 1 : 0)) * NC + e] = v;

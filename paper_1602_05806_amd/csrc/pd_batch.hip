@@ -143,6 +143,7 @@ __global__ __launch_bounds__(256) void k_apply2d_batch(BatchIter it, const int* 
   a.rho_cur = rho_slot(it, j, it.koff);
   a.nrho = P.nupd;
   a.sigpart = it.sig + P.sig_off;
+  a.xsol = nullptr;
   const int tile = b - toff[g];
   apply2d_body<T, N, V, FUSE, 0>(a, B, tile, tile + 1, tile);
 }
@@ -418,7 +419,8 @@ __global__ void k_state_init_batch(CgState* st, int count, int maxit, double tol
     s.switched = 0;
     s.stall = 0;
     s.fallback_k = -1;
-    s.pad = 0;
+    s.xk = -1;
+    s.xused = -1;
   }
 }
 

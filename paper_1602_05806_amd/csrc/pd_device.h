@@ -52,7 +52,13 @@ struct CgState {
   int switched;      // batched: set when the problem has just switched to FP64 iterations
   int stall;         // batched refinement: replacements in a row without a new best residual
   int fallback_k;    // batched refinement: iteration of the switch to FP64, -1 = none
-  int pad;
+  // Single-problem runs fold x += alpha_k p_k into the apply kernel of iteration k + 1, which
+  // reads p_k anyway: xk = iteration whose alpha (above) awaits that update, -1 = none; xused =
+  // the last such iteration an apply kernel has applied (block 0 records it; no block of the
+  // same launch reads it). After a run stops, x is complete once xk == xused or after one
+  // flush kernel.
+  int xk;
+  int xused;
 };
 
 // Finalizers of the stand-alone reductions (dot kernel + single-block finalize kernel).

@@ -44,10 +44,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 }
 
 // CG iteration k, second half: alpha_k = rho_k / <p_k, A p_k> (sigma re-summed from the apply
-// kernel's block partials), x += alpha p; r -= alpha q; block partials of <r_{k+1}, r_{k+1}>.
+// kernel's block partials), r -= alpha q, block partials of <r_{k+1}, r_{k+1}>. The matching
+// x += alpha_k p_k is left to the apply kernel of iteration k + 1 (which reads p_k anyway) or,
+// when the run stops first, to k_x_flush: block 0 publishes alpha_k with xk = k.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T* __restrict__ p,
-                                                      const T* __restrict__ q, T* __restrict__ r,
+__global__ __launch_bounds__(kBlock) void k_cg_update(const T* __restrict__ q, T* __restrict__ r,
                                                       long long n, CgState* st, int k,
                                                       const double* __restrict__ sigpart, int nsig,
                                                       double* __restrict__ rho_next) {
@@ -56,13 +57,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T
   constexpr int J = 4;
   const long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x;
   const long long stride = (long long)gridDim.x * kBlock;
-  T xv[J], pv[J], qv[J], rv[J];
+  T qv[J], rv[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const long long i = i0 + j * stride;
     if (i < n) {
-      xv[j] = x[i];
-      pv[j] = p[i];
       qv[j] = q[i];
       rv[j] = r[i];
     }
@@ -81,6 +80,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->sigma = sigma;
     st->alpha = alpha;
+    st->xk = k;
   }
   const T a = (T)alpha;
   double s = 0.0;
@@ -88,20 +88,33 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T
   for (int j = 0; j < J; ++j) {
     const long long i = i0 + j * stride;
     if (i < n) {
-      x[i] = xv[j] + a * pv[j];
       const T rn = rv[j] - a * qv[j];
       r[i] = rn;
       s += (double)rn * (double)rn;
     }
   }
   for (long long i = i0 + J * stride; i < n; i += stride) {
-    x[i] = x[i] + a * p[i];
     const T rn = r[i] - a * q[i];
     r[i] = rn;
     s += (double)rn * (double)rn;
   }
   s = block_sum_all<kBlock>(s);
   if (threadIdx.x == 0) rho_next[blockIdx.x] = s;
+}
+
+// After a run has stopped: the pending x += alpha_xk p_xk (p_k is in buf[(k + 1) % 2]) unless an
+// apply kernel already made it. Called once per stop; the next state reset clears xk.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_x_flush(T* __restrict__ x, const T* __restrict__ pa,
+                                                    const T* __restrict__ pb, long long n,
+                                                    const CgState* st) {
+  const int xk = st->xk;
+  if (xk < 0 || st->xused == xk) return;
+  const T a = (T)st->alpha;
+  const T* __restrict__ p = ((xk + 1) & 1) ? pb : pa;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock)
+    x[i] = x[i] + a * p[i];
 }
 
 // r = b - q (q may be null: r = b), with block partials of <r, r>.
@@ -151,6 +164,8 @@ __global__ void k_state_init(CgState* st, int maxit, double rtol) {
     st->even_stop = 0;
     st->fresh = 0;
     st->scale = 1.0;
+    st->xk = -1;
+    st->xused = -1;
   }
 }
 
@@ -164,6 +179,8 @@ __global__ void k_state_set(CgState* st, int maxit, double tol2) {
     st->restart_k = -1;
     st->even_stop = 0;
     st->fresh = 0;
+    st->xk = -1;
+    st->xused = -1;
   }
 }
 
@@ -291,18 +308,27 @@ hipError_t launch_finalize(const double* partials, int nparts, CgState* st, int 
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(bool fp32, void* x, const void* p, const void* q, void* r,
-                            long long n, CgState* st, int k, const double* sigpart, int nsig,
-                            double* rho_next, hipStream_t s) {
+hipError_t launch_cg_update(bool fp32, const void* q, void* r, long long n, CgState* st, int k,
+                            const double* sigpart, int nsig, double* rho_next, hipStream_t s) {
   const unsigned G = stream_blocks(n, 4);
   if (fp32)
-    hipLaunchKernelGGL(k_cg_update<float>, dim3(G), dim3(kBlock), 0, s, (float*)x,
-                       (const float*)p, (const float*)q, (float*)r, n, st, k, sigpart, nsig,
-                       rho_next);
+    hipLaunchKernelGGL(k_cg_update<float>, dim3(G), dim3(kBlock), 0, s, (const float*)q,
+                       (float*)r, n, st, k, sigpart, nsig, rho_next);
   else
-    hipLaunchKernelGGL(k_cg_update<double>, dim3(G), dim3(kBlock), 0, s, (double*)x,
-                       (const double*)p, (const double*)q, (double*)r, n, st, k, sigpart, nsig,
-                       rho_next);
+    hipLaunchKernelGGL(k_cg_update<double>, dim3(G), dim3(kBlock), 0, s, (const double*)q,
+                       (double*)r, n, st, k, sigpart, nsig, rho_next);
+  return hipGetLastError();
+}
+
+hipError_t launch_x_flush(bool fp32, void* x, const void* pa, const void* pb, long long n,
+                          const CgState* st, hipStream_t s) {
+  const unsigned G = stream_blocks(n, 4);
+  if (fp32)
+    hipLaunchKernelGGL(k_x_flush<float>, dim3(G), dim3(kBlock), 0, s, (float*)x,
+                       (const float*)pa, (const float*)pb, n, st);
+  else
+    hipLaunchKernelGGL(k_x_flush<double>, dim3(G), dim3(kBlock), 0, s, (double*)x,
+                       (const double*)pa, (const double*)pb, n, st);
   return hipGetLastError();
 }
 
