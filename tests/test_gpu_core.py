@@ -6,8 +6,8 @@ import pytest
 
 from oracle import layout
 from oracle.operators import (Grid, pressure_operator, viscous_operator, div_rhs, grad_update,
-                              apply_at)
-from oracle.solvers import FastDiag
+                              apply_at, null_basis_tiled, project_null)
+from oracle.solvers import FastDiag, cg
 from oracle.step import dual_to_main, main_to_dual, rk3, StepOracle
 import synthetic
 
@@ -99,6 +99,52 @@ def test_pressure_solve_matches_min_norm(pd, dim, cells, N, prec):
     assert info["status"] == pd.PD_OK
     assert info["rel_res_true"] <= 2e-12
     assert err <= 1e-9
+
+
+@pytest.mark.parametrize("dim,cells,N,m", [(2, (9, 7), 4, 1), (2, (9, 7), 4, 2), (2, (12, 10), 6, 37),
+                                           (3, (4, 5, 3), 3, 23), (2, (6, 5), 0, 9)])
+def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m):
+    """After exactly m FP64 iterations from x0 = 0 (maxit = m) the GPU iterate equals the oracle's
+    plain CG iterate x_m on the assembled matrix. Pins the iteration bookkeeping of the device
+    loop, including the x update of the last iteration, which the apply kernel of the next
+    iteration would have made and the stop leaves to the flush kernel. (The oracle's own x_m
+    moves by ~1e-15 relative under 1e-15 perturbations of b for these cases.)"""
+    import torch
+    print(f"cg iterates dim={dim} cells={cells} N={N} m={m}", flush=True)
+    L = (1.0,) * dim
+    dt = 5e-4
+    g = Grid(cells, L, N)
+    A = pressure_operator(g, dt)
+    bt = layout.blocked_to_tensor(synthetic.random_rhs(21 + m, g.ndof), cells, g.n)
+    bt = project_null(g, bt, [null_basis_tiled(c, N) for c in cells])   # b in range(A_p)
+    x_ref, it, _ = cg(A, bt.reshape(-1), 1e-30, m)
+    assert it == m
+    ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, 1e-2)
+    x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(layout.tensor_to_blocked(bt, cells, g.n)), x,
+                          1e-30, m)
+    ctx.close()
+    assert info["status"] == pd.PD_ENOCONV and info["iters"] == m
+    got = layout.blocked_to_tensor(host(x), cells, g.n).reshape(-1)
+    assert np.linalg.norm(got - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
+
+
+def test_timing_samples_every_sth_launch(pd):
+    """PD_CFG_TIMING = s times every s-th operator launch of a pressure solve (iterations
+    0, s, 2s, ... below the final count) and reports the 6-word algorithmic bytes per launch."""
+    import torch
+    cells, N, m, s = (10, 8), 3, 37, 4
+    g = Grid(cells, (1.0, 1.0), N)
+    ctx = pd.pd_setup(2, cells, (1.0, 1.0), N, 5e-4, 0.6, 1e-2)
+    pd.pd_configure(ctx, pd.PD_CFG_TIMING, s)
+    pd.pd_timing(ctx, pd.PD_FP64, reset=True)
+    x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(synthetic.random_rhs(5, g.ndof)), x, 1e-30, m)
+    t = pd.pd_timing(ctx, pd.PD_FP64, reset=True)
+    ctx.close()
+    assert info["iters"] == m
+    assert t["launches"] == (m + s - 1) // s and t["total_ms"] > 0.0
+    assert t["bytes_per_launch"] == 6.0 * g.ndof * 8.0
 
 
 @pytest.mark.parametrize("prec", [0, 2])
