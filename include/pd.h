@@ -205,12 +205,16 @@ int pd_step_adjoint(pd_ctx* ctx, void* const u[3], void* const ubar[3], pd_solve
  *                        next plane's halo (3D) into registers during compute, 0 = no prefetch
  *   PD_CFG_TILE_VARIANT  2D operator kernel tile shape: 0 (default) = the largest tile of cells
  *                        whose LDS box fits, 1 / 2 = one / two sizes smaller (more workgroups)
- * The last four only change the launch shape; results are identical up to the block order of
- * the dot-product partial sums. */
+ *   PD_CFG_DEFER_X       where CG iteration k's x += alpha_k p_k is made: 1 (default) = in the
+ *                        operator kernel of iteration k + 1 (it reads p_k anyway; 9 instead of
+ *                        10 vector words per DoF and iteration), 0 = in the update kernel
+ * The last five only change the launch shape; results are identical up to the block order of
+ * the dot-product partial sums (and, for PD_CFG_DEFER_X, the rounding of x). */
 enum {
   PD_CFG_STEP_PREC = 0, PD_CFG_P_RTOL = 1, PD_CFG_V_RTOL = 2, PD_CFG_MAXIT = 3,
   PD_CFG_CONVECTION = 4, PD_CFG_RU_FACTOR = 5, PD_CFG_TIMING = 6, PD_CFG_CHECK_EVERY = 7,
-  PD_CFG_KZ = 8, PD_CFG_TILES_PER_WG = 9, PD_CFG_PREFETCH = 10, PD_CFG_TILE_VARIANT = 11
+  PD_CFG_KZ = 8, PD_CFG_TILES_PER_WG = 9, PD_CFG_PREFETCH = 10, PD_CFG_TILE_VARIANT = 11,
+  PD_CFG_DEFER_X = 12
 };
 int pd_configure(pd_ctx* ctx, int key, double value);
 
@@ -219,8 +223,9 @@ int pd_configure(pd_ctx* ctx, int key, double value);
  * pressure solves since the last reset (reset != 0 clears after reading). The sampled launches
  * (every PD_CFG_TIMING-th; requires PD_CFG_TIMING >= 1) carry start/stop HIP events in their
  * dispatch on the solve's stream; launches after convergence (early exits) are not counted.
- * bytes_per_launch: algorithmic bytes of one launch (reads r, p_old and x, writes p, A p and x:
- * 6 words per DoF). Synchronises with the last stream. */
+ * bytes_per_launch: algorithmic bytes of one launch of the last timed solve (reads r and p_old,
+ * writes p and A p, and with the deferred x update also reads and writes x: 6 words per DoF,
+ * else 4). Synchronises with the last stream. */
 int pd_timing(pd_ctx* ctx, int prec, double* total_ms, long long* launches,
               double* bytes_per_launch, int reset);
 

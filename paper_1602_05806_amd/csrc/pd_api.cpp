@@ -32,6 +32,7 @@ struct pd_ctx {
   int maxit = 100000, convection = 1, timing = 0, check_every = 32;
   int kz = 0, tiles_per_wg = 0, prefetch = 1;   // operator-kernel launch shape
   int tile_variant = 0;                          // 2D tile shape (0 = largest fitting)
+  int defer_x = 1;         // 1: x update made by the next apply kernel, 0: by the update kernel
   // device workspace
   CgState* st = nullptr;       // CG state of the (inner) solve
   CgState* st2 = nullptr;      // outer refinement / residual norms
@@ -55,6 +56,7 @@ struct pd_ctx {
   std::vector<hipEvent_t> tev;
   double t_ms[2] = {0, 0};
   long long t_cnt[2] = {0, 0};
+  double t_words[2] = {6, 6};  // vector words per DoF of the timed launches (6 or 4)
   hipStream_t last_stream = nullptr;
 };
 
@@ -144,10 +146,12 @@ struct CgBuffers {
 };
 
 // A chunked conjugate-gradient run on the device, FP64 or FP32 vectors (FP64 scalars).
-// Iteration k = apply kernel (x += alpha_{k-1} p_{k-1}, p_k = r_k + beta_k p_{k-1}, q = A p_k,
-// partials of <p_k, q>) + update kernel (r -= alpha_k q, partials of <r_{k+1}, r_{k+1}>): the
-// x update rides on the apply, which reads p_{k-1} anyway (9 vector words per DoF and
-// iteration instead of 10); the one still pending when the run stops is flushed at the end.
+// Iteration k = apply kernel (p_k = r_k + beta_k p_{k-1}, q = A p_k, partials of <p_k, q>) +
+// update kernel (x += alpha_k p_k, r -= alpha_k q, partials of <r_{k+1}, r_{k+1}>). Deferred
+// form (default): the x update rides on the apply kernel of iteration k + 1, which reads p_k
+// anyway (9 vector words per DoF and iteration instead of 10; the update still pending when the
+// run stops is flushed at the end). Measured at 256^2 N = 6 and 64^3 N = 4: 0-8 % (2D) and 13 %
+// (3D) less time per FP64 iteration, 9 % less (2D) and 1 % more (3D) per FP32 iteration.
 // The run can be stopped by a host predicate on the polled state and resumed at the exact
 // iteration.
 struct CgRun {
@@ -158,6 +162,7 @@ struct CgRun {
   CgState* st = nullptr;
   hipStream_t s = nullptr;
   bool timed = false;
+  bool defer = true;         // x update made by the next apply kernel (else by the update kernel)
   int k = 0;                 // next iteration to launch / iterations completed after a stop
   int nrho = 0, nsig = 0;
   double* rho[2] = {nullptr, nullptr};
@@ -171,8 +176,9 @@ int cg_prepare(pd_ctx* c, CgRun* R) {
   R->rho[0] = c->rhopart;
   R->rho[1] = c->rhopart + pdk::kMaxStreamPartials;
   R->L = base_launch(c, R->op, R->fp32);
-  R->L.fuse = 2;
-  R->L.xsol = R->x;
+  R->defer = c->defer_x != 0;
+  R->L.fuse = R->defer ? 2 : 1;
+  R->L.xsol = R->defer ? R->x : nullptr;
   R->L.st = R->st;
   R->L.nrho = R->nrho;
   R->L.sigpart = c->sigpart;
@@ -204,8 +210,9 @@ int cg_launch(pd_ctx* c, CgRun* R) {
     L.ev_stop = c->tev[2 * j + 1];
   }
   PD_HIP(c, pdk::launch_apply(L, R->s));
-  PD_HIP(c, pdk::launch_cg_update(R->fp32, R->B.q, R->B.r, c->ndof, R->st, k, c->sigpart,
-                                  R->nsig, R->rho[(k + 1) & 1], R->s));
+  PD_HIP(c, pdk::launch_cg_update(R->fp32, R->defer ? nullptr : R->x,
+                                  R->defer ? nullptr : buf[(k + 1) & 1], R->B.q, R->B.r, c->ndof,
+                                  R->st, k, c->sigpart, R->nsig, R->rho[(k + 1) & 1], R->s));
   ++R->k;
   return PD_OK;
 }
@@ -247,6 +254,7 @@ int cg_run_until(pd_ctx* c, CgRun* R, int maxit, Pred stop, CgState* fin) {
 void cg_collect_timing(pd_ctx* c, const CgRun& R) {
   if (!R.timed) return;
   const int tslot = R.fp32 ? 1 : 0;
+  c->t_words[tslot] = R.defer ? 6.0 : 4.0;
   // sampled launches of the completed iterations (launches queued after the stop exit at once)
   for (int k = 0; k < R.k; k += c->timing) {
     const size_t j = (size_t)(k / c->timing);
@@ -1199,6 +1207,10 @@ int pd_configure(pd_ctx* c, int key, double v) {
       if (!(v == 0 || v == 1 || v == 2)) return fail(c, PD_EINVAL, "tile variant must be 0, 1 or 2");
       c->tile_variant = (int)v;
       break;
+    case PD_CFG_DEFER_X:
+      if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_DEFER_X must be 0 or 1");
+      c->defer_x = (int)v;
+      break;
     default:
       return fail(c, PD_EINVAL, "unknown configuration key");
   }
@@ -1213,8 +1225,9 @@ int pd_timing(pd_ctx* c, int prec, double* total_ms, long long* launches,
   const int k = prec == PD_FP32 ? 1 : 0;
   if (total_ms) *total_ms = c->t_ms[k];
   if (launches) *launches = c->t_cnt[k];
-  // fused CG apply: reads r, p_old and x, writes p, A p and x (6 words per DoF)
-  if (bytes_per_launch) *bytes_per_launch = 6.0 * (double)c->ndof * (k ? 4.0 : 8.0);
+  // fused CG apply: reads r and p_old, writes p and A p; with the deferred x update it also reads
+  // and writes x (6 words per DoF, else 4)
+  if (bytes_per_launch) *bytes_per_launch = c->t_words[k] * (double)c->ndof * (k ? 4.0 : 8.0);
   if (reset) {
     c->t_ms[k] = 0;
     c->t_cnt[k] = 0;

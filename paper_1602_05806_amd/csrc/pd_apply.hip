@@ -398,9 +398,12 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   hipEvent_t e0 = L.ev_start, e1 = L.ev_stop;
   if (L.dim == 2) {
 #define PD_A2D(VV)                                                                              \
-  if (L.fuse) {                                                                                 \
+  if (L.fuse == 2) {                                                                            \
     if (pf) hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 2, 1>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B); \
     else hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 2, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);   \
+  } else if (L.fuse) {                                                                          \
+    if (pf) hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 1, 1>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B); \
+    else hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 1, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);   \
   } else {                                                                                      \
     hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 0, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);       \
   }
@@ -410,9 +413,12 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
 #undef PD_A2D
   } else {
     constexpr int NTH = Tile3D<N>::NTH;
-    if (L.fuse) {
+    if (L.fuse == 2) {
       if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 2, 1>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
       else hipExtLaunchKernelGGL((k_apply3d<T, N, 2, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+    } else if (L.fuse) {
+      if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 1>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+      else hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     } else {
       hipExtLaunchKernelGGL((k_apply3d<T, N, 0, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     }

@@ -16,7 +16,7 @@ struct ApplyLaunch {
   int nc[3] = {1, 1, 1};
   bool fp32 = false;
   int fuse = 0;              // 1: CG iteration form (p = r + beta p_old; sigma partials)
-                             // 2: the same plus the pending x += alpha_{k-1} p_old into xsol
+                             // 2: the same plus the deferred x += alpha_{k-1} p_old into xsol
   const void* x = nullptr;   // operand (fuse = 0) or r (fuse = 1, 2)
   const void* pold = nullptr;
   void* pnew = nullptr;
@@ -50,9 +50,11 @@ hipError_t launch_dot(bool fp32, const void* a, const void* b, long long n, doub
                       hipStream_t s);
 hipError_t launch_finalize(const double* partials, int nparts, CgState* st, int fin,
                            hipStream_t s);
-// CG iteration k, second half (see k_cg_update): r -= alpha_k q, partials of rho_{k+1}
-hipError_t launch_cg_update(bool fp32, const void* q, void* r, long long n, CgState* st, int k,
-                            const double* sigpart, int nsig, double* rho_next, hipStream_t s);
+// CG iteration k, second half (see k_cg_update): r -= alpha_k q, partials of rho_{k+1}; with
+// x (and p) non-null also x += alpha_k p, else the x update is deferred (fused apply form 2)
+hipError_t launch_cg_update(bool fp32, void* x, const void* p, const void* q, void* r,
+                            long long n, CgState* st, int k, const double* sigpart, int nsig,
+                            double* rho_next, hipStream_t s);
 // the x update still pending when a run stopped (see k_x_flush)
 hipError_t launch_x_flush(bool fp32, void* x, const void* pa, const void* pb, long long n,
                           const CgState* st, hipStream_t s);

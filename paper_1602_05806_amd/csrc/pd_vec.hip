@@ -44,11 +44,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double* __restrict__ 
 }
 
 // CG iteration k, second half: alpha_k = rho_k / <p_k, A p_k> (sigma re-summed from the apply
-// kernel's block partials), r -= alpha q, block partials of <r_{k+1}, r_{k+1}>. The matching
-// x += alpha_k p_k is left to the apply kernel of iteration k + 1 (which reads p_k anyway) or,
-// when the run stops first, to k_x_flush: block 0 publishes alpha_k with xk = k.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(const T* __restrict__ q, T* __restrict__ r,
+// kernel's block partials), r -= alpha q, block partials of <r_{k+1}, r_{k+1}>. XU = 1: also
+// x += alpha p here (6 vector words per DoF). XU = 0: the x update is left to the apply kernel of
+// iteration k + 1 (which reads p_k anyway) or, when the run stops first, to k_x_flush; block 0
+// publishes alpha_k with xk = k (3 words per DoF).
+template <typename T, int XU>
+__global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T* __restrict__ p,
+                                                      const T* __restrict__ q, T* __restrict__ r,
                                                       long long n, CgState* st, int k,
                                                       const double* __restrict__ sigpart, int nsig,
                                                       double* __restrict__ rho_next) {
@@ -57,11 +59,15 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const T* __restrict__ q, T
   constexpr int J = 4;
   const long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x;
   const long long stride = (long long)gridDim.x * kBlock;
-  T qv[J], rv[J];
+  T xv[XU ? J : 1], pv[XU ? J : 1], qv[J], rv[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const long long i = i0 + j * stride;
     if (i < n) {
+      if (XU) {
+        xv[j] = x[i];
+        pv[j] = p[i];
+      }
       qv[j] = q[i];
       rv[j] = r[i];
     }
@@ -80,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const T* __restrict__ q, T
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->sigma = sigma;
     st->alpha = alpha;
-    st->xk = k;
+    if (!XU) st->xk = k;
   }
   const T a = (T)alpha;
   double s = 0.0;
@@ -88,12 +94,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(const T* __restrict__ q, T
   for (int j = 0; j < J; ++j) {
     const long long i = i0 + j * stride;
     if (i < n) {
+      if (XU) x[i] = xv[j] + a * pv[j];
       const T rn = rv[j] - a * qv[j];
       r[i] = rn;
       s += (double)rn * (double)rn;
     }
   }
   for (long long i = i0 + J * stride; i < n; i += stride) {
+    if (XU) x[i] = x[i] + a * p[i];
     const T rn = r[i] - a * q[i];
     r[i] = rn;
     s += (double)rn * (double)rn;
@@ -308,15 +316,27 @@ hipError_t launch_finalize(const double* partials, int nparts, CgState* st, int 
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(bool fp32, const void* q, void* r, long long n, CgState* st, int k,
-                            const double* sigpart, int nsig, double* rho_next, hipStream_t s) {
+hipError_t launch_cg_update(bool fp32, void* x, const void* p, const void* q, void* r,
+                            long long n, CgState* st, int k, const double* sigpart, int nsig,
+                            double* rho_next, hipStream_t s) {
   const unsigned G = stream_blocks(n, 4);
-  if (fp32)
-    hipLaunchKernelGGL(k_cg_update<float>, dim3(G), dim3(kBlock), 0, s, (const float*)q,
-                       (float*)r, n, st, k, sigpart, nsig, rho_next);
-  else
-    hipLaunchKernelGGL(k_cg_update<double>, dim3(G), dim3(kBlock), 0, s, (const double*)q,
-                       (double*)r, n, st, k, sigpart, nsig, rho_next);
+  if (fp32) {
+    if (x)
+      hipLaunchKernelGGL((k_cg_update<float, 1>), dim3(G), dim3(kBlock), 0, s, (float*)x,
+                         (const float*)p, (const float*)q, (float*)r, n, st, k, sigpart, nsig,
+                         rho_next);
+    else
+      hipLaunchKernelGGL((k_cg_update<float, 0>), dim3(G), dim3(kBlock), 0, s, nullptr, nullptr,
+                         (const float*)q, (float*)r, n, st, k, sigpart, nsig, rho_next);
+  } else {
+    if (x)
+      hipLaunchKernelGGL((k_cg_update<double, 1>), dim3(G), dim3(kBlock), 0, s, (double*)x,
+                         (const double*)p, (const double*)q, (double*)r, n, st, k, sigpart, nsig,
+                         rho_next);
+    else
+      hipLaunchKernelGGL((k_cg_update<double, 0>), dim3(G), dim3(kBlock), 0, s, nullptr, nullptr,
+                         (const double*)q, (double*)r, n, st, k, sigpart, nsig, rho_next);
+  }
   return hipGetLastError();
 }
 

@@ -26,6 +26,16 @@ def test_library_exports_every_declared_symbol(pd):
     assert sorted(pd.EXPORTED) == declared_symbols()
 
 
+def test_binding_constants_match_header(pd):
+    """Every enumerator of include/pd.h (PD_... = value) has the same value in the binding."""
+    src = open(os.path.join(ROOT, "include", "pd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    consts = dict((k, int(v)) for k, v in re.findall(r"\b(PD_[A-Z0-9_]+)\s*=\s*(-?\d+)", src))
+    assert "PD_CFG_DEFER_X" in consts and "PD_BCFG_CHUNK" in consts
+    wrong = {k: (v, getattr(pd, k, None)) for k, v in consts.items() if getattr(pd, k, None) != v}
+    assert not wrong, wrong
+
+
 def test_setup_rejects_bad_arguments_without_touching_the_device(pd):
     import pytest
     for args in [(4, (4, 4), (1.0, 1.0), 2, 1e-3, 0.6, 0.0),      # dim

@@ -101,16 +101,18 @@ def test_pressure_solve_matches_min_norm(pd, dim, cells, N, prec):
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("defer", [1, 0])
 @pytest.mark.parametrize("dim,cells,N,m", [(2, (9, 7), 4, 1), (2, (9, 7), 4, 2), (2, (12, 10), 6, 37),
                                            (3, (4, 5, 3), 3, 23), (2, (6, 5), 0, 9)])
-def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m):
+def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m, defer):
     """After exactly m FP64 iterations from x0 = 0 (maxit = m) the GPU iterate equals the oracle's
     plain CG iterate x_m on the assembled matrix. Pins the iteration bookkeeping of the device
     loop, including the x update of the last iteration, which the apply kernel of the next
-    iteration would have made and the stop leaves to the flush kernel. (The oracle's own x_m
-    moves by ~1e-15 relative under 1e-15 perturbations of b for these cases.)"""
+    iteration would have made and the stop leaves to the flush kernel (PD_CFG_DEFER_X = 1), and
+    the plain form with x updated in the update kernel (0). (The oracle's own x_m moves by
+    ~1e-15 relative under 1e-15 perturbations of b for these cases.)"""
     import torch
-    print(f"cg iterates dim={dim} cells={cells} N={N} m={m}", flush=True)
+    print(f"cg iterates dim={dim} cells={cells} N={N} m={m} defer={defer}", flush=True)
     L = (1.0,) * dim
     dt = 5e-4
     g = Grid(cells, L, N)
@@ -120,6 +122,7 @@ def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m):
     x_ref, it, _ = cg(A, bt.reshape(-1), 1e-30, m)
     assert it == m
     ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, 1e-2)
+    pd.pd_configure(ctx, pd.PD_CFG_DEFER_X, defer)
     x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
     info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(layout.tensor_to_blocked(bt, cells, g.n)), x,
                           1e-30, m)
