@@ -320,6 +320,29 @@ static long long resident_2d(int v, int pf) {
   return cache[dev][v][pf];
 }
 
+// Workgroups of the 3D kernel (fused form 0, 1 or 2; prefetch pf) the device holds at once.
+template <typename T, int N>
+static long long resident_3d(int fuse, int pf) {
+  constexpr int kDev = 16;
+  static int cache[kDev][3][2];
+  static bool init[kDev][3][2];
+  int dev = 0;
+  if (fuse < 0 || fuse > 2 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) return 0;
+  if (fuse == 0) pf = 0;
+  if (!init[dev][fuse][pf]) {
+    const void* f = fuse == 2 ? (pf ? (const void*)k_apply3d<T, N, 2, 1> : (const void*)k_apply3d<T, N, 2, 0>)
+                  : fuse == 1 ? (pf ? (const void*)k_apply3d<T, N, 1, 1> : (const void*)k_apply3d<T, N, 1, 0>)
+                              : (const void*)k_apply3d<T, N, 0, 0>;
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, Tile3D<N>::NTH, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    cache[dev][fuse][pf] = per_cu * cus;
+    init[dev][fuse][pf] = true;
+  }
+  return cache[dev][fuse][pf];
+}
+
 template <typename T, int N>
 static Geom geometry(const ApplyLaunch& L) {
   Geom g;
@@ -351,8 +374,13 @@ static Geom geometry(const ApplyLaunch& L) {
     g.ntx = (nx + TL::TX - 1) / TL::TX;
     g.nty = (ny + TL::TY - 1) / TL::TY;
     const long long cols = (long long)g.ntx * g.nty;
-    // planes per segment: about 1024 workgroups, segments of at least 4 planes (64^3 N=4: 16)
-    int kz = (int)((cols * nz) / 1024);
+    // planes per segment: as many workgroups as the device holds at once (one wave of
+    // workgroups; each segment re-reads two boundary planes), segments of at least 4 planes.
+    // 64^3 N = 4: FP64 one workgroup per CU -> 64 planes, FP32 two -> 32; measured 6 % faster
+    // than 16 planes in FP64 and equal in FP32.
+    const long long res = resident_3d<T, N>(L.fuse, L.prefetch != 0);
+    int kz = res > 0 ? (int)std::min<long long>(nz, (cols * nz + res - 1) / res)
+                     : (int)((cols * nz) / 1024);
     if (kz < 4) kz = 4;
     if (kz > nz) kz = nz;
     if (L.kz_override > 0) kz = L.kz_override < nz ? L.kz_override : nz;
