@@ -62,7 +62,9 @@ enum { PD_FP64 = 0, PD_FP32 = 1, PD_FP32_REFINE64 = 2 };
 enum { PD_OP_PRESSURE = 0, PD_OP_VISCOUS = 1 };
 
 /* Per-solve report. iters: CG iterations (FP32 plus FP64 ones for PD_FP32_REFINE64);
- * outer_iters: FP64 residual recomputations of the refinement (1 for PD_FP64); restarts:
+ * outer_iters: FP64 residual recomputations (refinement: one per replacement; PD_FP64: the
+ * CG runs, 1 plus the replacements made when the recurrence met rtol but the recomputed residual
+ * b - A x did not); restarts:
  * refinement replacements that also restarted the search direction; fallback_iter: for
  * PD_FP32_REFINE64, the iteration at which the solve continued in FP64 because the FP64
  * residual had stopped decreasing under FP32 iterations (FP32 rounding of A p dominates the
@@ -116,8 +118,13 @@ int pd_apply(pd_ctx* ctx, int op, int prec, const void* x, void* y, void* hip_st
  * Section 2.1). b, x: ndof FP64 arrays. x holds the initial guess on entry (set it to zero for
  * the paper's choice) and the solution on exit. For PD_OP_PRESSURE, b is first projected onto
  * range(A_p) (orthogonal complement of the null space of the weak gradient) and x is projected
- * at exit, so the result is the minimum-norm solution. Stops when ||r||_2 <= rtol ||b||_2.
- * prec: PD_FP64 or PD_FP32_REFINE64. Synchronises with the stream at exit; info may be NULL.
+ * at exit, so the result is the minimum-norm solution. PD_FP64 stops when the CG recurrence
+ * residual <= rtol ||b||_2 and the recomputed FP64 residual ||b - A x||_2 is too: when the latter
+ * is above but within 16x, it replaces the recurrence residual and the iterations continue (up
+ * to 8 times, while each replacement at least halves it; a larger gap is the FP64 rounding
+ * floor of b - A x and ends the solve with PD_OK, rel_res_true reporting it).
+ * PD_FP32_REFINE64 stops on the recomputed FP64 residual. Synchronises with the stream at exit;
+ * info may be NULL.
  * Returns PD_OK, PD_ENOCONV (maxit reached) or PD_EBREAKDOWN. */
 int pd_cg_solve(pd_ctx* ctx, int op, int prec, const void* b, void* x, double rtol, int maxit,
                 pd_solve_info* info, void* hip_stream);

@@ -56,6 +56,10 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   __shared__ T xs[NS * NC];
   __shared__ T ys[NT * NC];
   __shared__ int hbase[NS];     // in-plane cell index (j*nx + i, wrapped) of every halo slot
+  // launches queued after the run stopped exit before loading anything
+  if (FUSE) {
+    if (a.st->done) return;
+  }
   const T* __restrict__ xg = a.x;
   const T* __restrict__ pg = a.pold;
   T* __restrict__ png = a.pnew;
@@ -105,7 +109,6 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
       if (FUSE == 2) xc[l3] = a.xsol[bc + l3 * NP];
     }
     if (FUSE) {
-      if (a.st->done) return;   // loads above are harmless once the run has stopped
       const int k = a.kbase ? *a.kbase + a.k : a.k;
       const IterScalars sc = iteration_scalars<NTH>(a.st, k, a.rho_cur, a.nrho, blockIdx.x == 0);
       if (sc.stop) return;

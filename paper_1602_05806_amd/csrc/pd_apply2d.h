@@ -111,6 +111,10 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
   constexpr int JI = (RI + 255) / 256, JH = (RH + 255) / 256;
   __shared__ T xs[(TY + 2) * BX * NC];
   __shared__ T ys[NT * NC];
+  // launches queued after the run stopped exit before loading anything
+  if (FUSE) {
+    if (a.st->done) return;
+  }
   const T* __restrict__ xg = a.x;
   const T* __restrict__ pg = a.pold;
   T* __restrict__ png = a.pnew;
@@ -155,14 +159,11 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
     }
   };
 
-  // the first tile's loads are issued before the state is read (reading r and p_old is harmless
-  // once the run has stopped; nothing is written then)
   if (t_begin < t_end) stage_load(t_begin);
   T beta = T(0);
   bool xupd = false;   // FUSE = 2: x += xalpha p_old on the owned cells
   T xalpha = T(0);
   if (FUSE) {
-    if (a.st->done) return;
     const int k = a.kbase ? *a.kbase + a.k : a.k;
     const IterScalars sc = iteration_scalars<256>(a.st, k, a.rho_cur, a.nrho, t_begin == 0);
     if (sc.stop) return;

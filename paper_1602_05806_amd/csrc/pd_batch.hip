@@ -57,17 +57,33 @@ __device__ __forceinline__ double* rho_slot(const BatchIter& it, int j, int pari
   return it.rho + (size_t)j * 2 * kMaxStreamPartials + (size_t)(parity & 1) * kMaxStreamPartials;
 }
 
-// ---- CG update: x += alpha_j p; r -= alpha_j q; partials of <r, r> (next iteration's slot)
+// ---- CG update: r -= alpha_j q; partials of <r, r> (next iteration's slot). The matching
+// x += alpha_j p_k is deferred: the apply kernel of iteration k + 1 makes it, or k_xflush_batch at
+// the end of the chunk when the problem has stopped iterating; block 0 of the problem publishes
+// alpha_j with xk = k. The first J elements of each thread are loaded before sigma is reduced.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update_batch(BatchIter it, T* __restrict__ x,
-                                                         const T* __restrict__ pbuf,
-                                                         const T* __restrict__ q,
+__global__ __launch_bounds__(kBlock) void k_update_batch(BatchIter it, const T* __restrict__ q,
                                                          T* __restrict__ r) {
   const Slot sl = slot_of(it, it.upd_off, blockIdx.x);
   const BProb& P = it.probs[sl.j];
   CgState* st = it.st + sl.j;
   if (!iterates(it, st)) return;
   const int k = *it.kbase + it.koff;
+  const long long n = P.ndof;
+  const long long stride = (long long)P.nupd * kBlock;
+  const long long i0 = (long long)sl.lb * kBlock + threadIdx.x;
+  T* rj = r + P.dof_off;
+  const T* qj = q + P.dof_off;
+  constexpr int J = 8;
+  T qv[J], rv[J];
+#pragma unroll
+  for (int jj = 0; jj < J; ++jj) {
+    const long long i = i0 + jj * stride;
+    if (i < n) {
+      qv[jj] = qj[i];
+      rv[jj] = rj[i];
+    }
+  }
   const double sigma = sum_partials<kBlock>(it.sig + P.sig_off, P.nsig);
   const double alpha = st->rho / sigma;
   if (!(sigma > 0.0) || !isfinite(alpha)) {
@@ -79,16 +95,18 @@ __global__ __launch_bounds__(kBlock) void k_update_batch(BatchIter it, T* __rest
     }
     return;
   }
-  const long long n = P.ndof;
-  const long long stride = (long long)P.nupd * kBlock;
   const T a = (T)alpha;
-  T* xj = x + P.dof_off;
-  T* rj = r + P.dof_off;
-  const T* pj = pbuf + P.dof_off;
-  const T* qj = q + P.dof_off;
   double s = 0.0;
-  for (long long i = (long long)sl.lb * kBlock + threadIdx.x; i < n; i += stride) {
-    xj[i] = xj[i] + a * pj[i];
+#pragma unroll
+  for (int jj = 0; jj < J; ++jj) {
+    const long long i = i0 + jj * stride;
+    if (i < n) {
+      const T rn = rv[jj] - a * qv[jj];
+      rj[i] = rn;
+      s += (double)rn * (double)rn;
+    }
+  }
+  for (long long i = i0 + J * stride; i < n; i += stride) {
     const T rn = rj[i] - a * qj[i];
     rj[i] = rn;
     s += (double)rn * (double)rn;
@@ -96,9 +114,44 @@ __global__ __launch_bounds__(kBlock) void k_update_batch(BatchIter it, T* __rest
   s = block_sum_all<kBlock>(s);
   if (threadIdx.x == 0) {
     rho_slot(it, sl.j, it.koff + 1)[sl.lb] = s;
-    // the direction of this iteration now exists: later iterations may build on it (no reader
-    // of this flag runs during this kernel)
-    if (sl.lb == 0) st->fresh = 0;
+    if (sl.lb == 0) {
+      st->alpha = alpha;
+      st->xk = k;
+      // the direction of this iteration now exists: later iterations may build on it (no reader
+      // of this flag runs during this kernel)
+      st->fresh = 0;
+    }
+  }
+}
+
+// ---- chunk end, every listed problem: the deferred x += alpha p_xk still pending (the problem
+// stopped iterating before the apply kernel of the next iteration made it). FP64-mode problems
+// update x64 with the FP64 direction, FP32-mode problems the FP32 correction d32 with the FP32
+// direction; p_k sits in buffer (k + 1) % 2 of its precision. The next finalize clears xk.
+__global__ __launch_bounds__(kBlock) void k_xflush_batch(BatchIter it, double* __restrict__ x64,
+                                                         float* __restrict__ d32,
+                                                         const double* __restrict__ pa64,
+                                                         const double* __restrict__ pb64,
+                                                         const float* __restrict__ pa32,
+                                                         const float* __restrict__ pb32) {
+  const Slot sl = slot_of(it, it.upd_off, blockIdx.x);
+  const BProb& P = it.probs[sl.j];
+  const CgState* st = it.st + sl.j;
+  const int xk = st->xk;
+  if (xk < 0 || st->xused == xk) return;
+  const long long n = P.ndof;
+  const long long stride = (long long)P.nupd * kBlock;
+  const long long o = P.dof_off;
+  if (st->mode64) {
+    const double a = st->alpha;
+    const double* __restrict__ p = ((xk + 1) & 1) ? pb64 : pa64;
+    for (long long i = (long long)sl.lb * kBlock + threadIdx.x; i < n; i += stride)
+      x64[o + i] += a * p[o + i];
+  } else {
+    const float a = (float)st->alpha;
+    const float* __restrict__ p = ((xk + 1) & 1) ? pb32 : pa32;
+    for (long long i = (long long)sl.lb * kBlock + threadIdx.x; i < n; i += stride)
+      d32[o + i] += a * p[o + i];
   }
 }
 
@@ -110,7 +163,7 @@ __global__ __launch_bounds__(256) void k_apply2d_batch(BatchIter it, const int* 
                                                        const T* __restrict__ x,
                                                        const T* __restrict__ pold,
                                                        T* __restrict__ pnew, T* __restrict__ y,
-                                                       Blk<T, N> B) {
+                                                       T* __restrict__ xsol, Blk<T, N> B) {
   const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int g = find_prob(toff, ng, b);
   const int j = grp[g];
@@ -143,7 +196,7 @@ __global__ __launch_bounds__(256) void k_apply2d_batch(BatchIter it, const int* 
   a.rho_cur = rho_slot(it, j, it.koff);
   a.nrho = P.nupd;
   a.sigpart = it.sig + P.sig_off;
-  a.xsol = nullptr;
+  a.xsol = FUSE == 2 ? xsol + P.dof_off : nullptr;
   const int tile = b - toff[g];
   apply2d_body<T, N, V, FUSE, 0>(a, B, tile, tile + 1, tile);
 }
@@ -229,6 +282,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
   const int j = it.list[blockIdx.x];
   const BProb& P = it.probs[j];
   CgState* st = it.st + j;
+  if (WHAT == 3 && threadIdx.x == 0) st->xk = -1;   // the deferred x update was flushed before
   if (WHAT == 3 && st->fin) return;
   const double s = sum_partials<kBlock>(it.tmp + (size_t)j * kMaxStreamPartials, P.nupd);
   const double rec = WHAT == 3 ? sum_partials<kBlock>(rho_slot(it, j, it.koff), P.nupd) : 0.0;
@@ -426,7 +480,7 @@ __global__ void k_state_init_batch(CgState* st, int count, int maxit, double tol
 
 template <typename T, int N, int V>
 hipError_t launch_group_N(const BatchIter& it, const BatchGroup& g, bool fuse, const void* x,
-                          const void* pold, void* pnew, void* y, const OpTables& tb,
+                          const void* pold, void* pnew, void* y, void* xsol, const OpTables& tb,
                           hipStream_t s) {
   Blk<T, N> B;
   constexpr int n = N + 1;
@@ -437,39 +491,41 @@ hipError_t launch_group_N(const BatchIter& it, const BatchGroup& g, bool fuse, c
   }
   for (int i = 0; i < n; ++i) B.w[i] = (T)tb.w[i];
   if (fuse)
-    hipLaunchKernelGGL((k_apply2d_batch<T, N, V, 1>), dim3(g.blocks), dim3(256), 0, s, it,
-                       g.grp, g.toff, g.ng, (const T*)x, (const T*)pold, (T*)pnew, (T*)y, B);
+    hipLaunchKernelGGL((k_apply2d_batch<T, N, V, 2>), dim3(g.blocks), dim3(256), 0, s, it,
+                       g.grp, g.toff, g.ng, (const T*)x, (const T*)pold, (T*)pnew, (T*)y,
+                       (T*)xsol, B);
   else
     hipLaunchKernelGGL((k_apply2d_batch<T, N, V, 0>), dim3(g.blocks), dim3(256), 0, s, it,
-                       g.grp, g.toff, g.ng, (const T*)x, (const T*)pold, (T*)pnew, (T*)y, B);
+                       g.grp, g.toff, g.ng, (const T*)x, (const T*)pold, (T*)pnew, (T*)y,
+                       (T*)nullptr, B);
   return hipGetLastError();
 }
 
 template <typename T, int N>
 hipError_t launch_group_V(const BatchIter& it, const BatchGroup& g, bool fuse, const void* x,
-                          const void* pold, void* pnew, void* y, const OpTables& tb,
+                          const void* pold, void* pnew, void* y, void* xsol, const OpTables& tb,
                           hipStream_t s) {
   switch (g.variant) {
-    case 1: return launch_group_N<T, N, 1>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 2: return launch_group_N<T, N, 2>(it, g, fuse, x, pold, pnew, y, tb, s);
-    default: return launch_group_N<T, N, 0>(it, g, fuse, x, pold, pnew, y, tb, s);
+    case 1: return launch_group_N<T, N, 1>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 2: return launch_group_N<T, N, 2>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    default: return launch_group_N<T, N, 0>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
   }
 }
 
 template <typename T>
 hipError_t launch_group_T(const BatchIter& it, const BatchGroup& g, bool fuse, const void* x,
-                          const void* pold, void* pnew, void* y, const OpTables& tb,
+                          const void* pold, void* pnew, void* y, void* xsol, const OpTables& tb,
                           hipStream_t s) {
   switch (g.N) {
-    case 0: return launch_group_V<T, 0>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 1: return launch_group_V<T, 1>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 2: return launch_group_V<T, 2>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 3: return launch_group_V<T, 3>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 4: return launch_group_V<T, 4>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 5: return launch_group_V<T, 5>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 6: return launch_group_V<T, 6>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 7: return launch_group_V<T, 7>(it, g, fuse, x, pold, pnew, y, tb, s);
-    case 8: return launch_group_V<T, 8>(it, g, fuse, x, pold, pnew, y, tb, s);
+    case 0: return launch_group_V<T, 0>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 1: return launch_group_V<T, 1>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 2: return launch_group_V<T, 2>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 3: return launch_group_V<T, 3>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 4: return launch_group_V<T, 4>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 5: return launch_group_V<T, 5>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 6: return launch_group_V<T, 6>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 7: return launch_group_V<T, 7>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
+    case 8: return launch_group_V<T, 8>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -477,22 +533,31 @@ hipError_t launch_group_T(const BatchIter& it, const BatchGroup& g, bool fuse, c
 }  // namespace
 
 hipError_t launch_apply_batch(const BatchIter& it, const BatchGroup& g, bool fp32, bool fuse,
-                              const void* x, const void* pold, void* pnew, void* y,
+                              const void* x, const void* pold, void* pnew, void* y, void* xsol,
                               const OpTables& tb, hipStream_t s) {
   if (g.blocks == 0) return hipSuccess;
-  return fp32 ? launch_group_T<float>(it, g, fuse, x, pold, pnew, y, tb, s)
-              : launch_group_T<double>(it, g, fuse, x, pold, pnew, y, tb, s);
+  return fp32 ? launch_group_T<float>(it, g, fuse, x, pold, pnew, y, xsol, tb, s)
+              : launch_group_T<double>(it, g, fuse, x, pold, pnew, y, xsol, tb, s);
 }
 
-hipError_t launch_update_batch(const BatchIter& it, bool fp32, void* x, const void* p,
-                               const void* q, void* r, hipStream_t s) {
+hipError_t launch_update_batch(const BatchIter& it, bool fp32, const void* q, void* r,
+                               hipStream_t s) {
   if (it.count == 0) return hipSuccess;
   if (fp32)
     hipLaunchKernelGGL(k_update_batch<float>, dim3(it.upd_blocks), dim3(kBlock), 0, s, it,
-                       (float*)x, (const float*)p, (const float*)q, (float*)r);
+                       (const float*)q, (float*)r);
   else
     hipLaunchKernelGGL(k_update_batch<double>, dim3(it.upd_blocks), dim3(kBlock), 0, s, it,
-                       (double*)x, (const double*)p, (const double*)q, (double*)r);
+                       (const double*)q, (double*)r);
+  return hipGetLastError();
+}
+
+hipError_t launch_xflush_batch(const BatchIter& it, double* x64, float* d32, const double* pa64,
+                               const double* pb64, const float* pa32, const float* pb32,
+                               hipStream_t s) {
+  if (it.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_xflush_batch, dim3(it.upd_blocks), dim3(kBlock), 0, s, it, x64, d32, pa64,
+                     pb64, pa32, pb32);
   return hipGetLastError();
 }
 

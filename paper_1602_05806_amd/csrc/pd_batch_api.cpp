@@ -367,6 +367,7 @@ int autotune(pd_batch* b, int pi, unsigned flags, std::map<std::string, int>* ca
     void* pa = fp32 ? (void*)b->pa32 : (void*)b->pa64;
     void* pb = fp32 ? (void*)b->pb32 : (void*)b->pb64;
     void* q = fp32 ? (void*)b->q32 : (void*)b->q64;
+    void* xs = fp32 ? (void*)b->d32 : (void*)b->x64;   // untouched: xk = -1 in every state
     BHIP(b, pdk::launch_zero_all(fp32, r, b->total, s));
     BHIP(b, pdk::launch_zero_all(fp32, pa, b->total, s));
     BHIP(b, pdk::launch_zero_all(false, b->rho, (long long)count * 2 * pdk::kMaxStreamPartials, s));
@@ -389,12 +390,12 @@ int autotune(pd_batch* b, int pi, unsigned flags, std::map<std::string, int>* ca
         for (int w = 0; w < 3 && e == hipSuccess; ++w)
           for (const BatchGroup& g : gs)
             if (e == hipSuccess)
-              e = pdk::launch_apply_batch(it, g, fp32, true, r, pa, pb, q, b->tabs[g.N], s);
+              e = pdk::launch_apply_batch(it, g, fp32, true, r, pa, pb, q, xs, b->tabs[g.N], s);
         if (e == hipSuccess) e = hipEventRecord(b->t0, s);
         for (int w = 0; w < reps && e == hipSuccess; ++w)
           for (const BatchGroup& g : gs)
             if (e == hipSuccess)
-              e = pdk::launch_apply_batch(it, g, fp32, true, r, pa, pb, q, b->tabs[g.N], s);
+              e = pdk::launch_apply_batch(it, g, fp32, true, r, pa, pb, q, xs, b->tabs[g.N], s);
         if (e == hipSuccess) e = hipEventRecord(b->t1, s);
         if (e == hipSuccess) e = hipEventSynchronize(b->t1);
         float ms = 0.f;
@@ -429,14 +430,20 @@ int enqueue_chunk(pd_batch* b, const Plan& pl, hipStream_t s) {
     const BatchIter i64 = make_iter(b, 0, pl.l64, i, 1, 0);
     for (const BatchGroup& g : pl.g32)
       BHIP(b, pdk::launch_apply_batch(i32, g, true, true, b->r32, p32[i & 1], p32[(i + 1) & 1],
-                                      b->q32, b->tabs[g.N], s));
+                                      b->q32, b->d32, b->tabs[g.N], s));
     for (const BatchGroup& g : pl.g64)
       BHIP(b, pdk::launch_apply_batch(i64, g, false, true, b->r64, p64[i & 1], p64[(i + 1) & 1],
-                                      b->q64, b->tabs[g.N], s));
-    BHIP(b, pdk::launch_update_batch(i32, true, b->d32, p32[(i + 1) & 1], b->q32, b->r32, s));
-    BHIP(b, pdk::launch_update_batch(i64, false, b->x64, p64[(i + 1) & 1], b->q64, b->r64, s));
+                                      b->q64, b->x64, b->tabs[g.N], s));
+    BHIP(b, pdk::launch_update_batch(i32, true, b->q32, b->r32, s));
+    BHIP(b, pdk::launch_update_batch(i64, false, b->q64, b->r64, s));
   }
   const int K = b->chunk;
+  // the deferred x updates of the problems that stopped inside the chunk (and of those still
+  // running, whose next apply would have made it): x is complete before anything below reads
+  // it; the chunk-end finalize clears xk
+  BHIP(b, pdk::launch_xflush_batch(make_iter(b, 0, pl.lall, K, -1, 0), b->x64, b->d32,
+                                   (const double*)p64[0], (const double*)p64[1],
+                                   (const float*)p32[0], (const float*)p32[1], s));
   // FP64 residual of the unfinished FP32-mode problems and of fallen-back FP64-mode problems
   // whose recurrence has met the tolerance
   const BatchIter chk = make_iter(b, 0, pl.lall, K, -2, 1);
@@ -446,7 +453,7 @@ int enqueue_chunk(pd_batch* b, const Plan& pl, hipStream_t s) {
                                      nullptr, b->x64, b->d32, s));
     for (const BatchGroup& g : pl.gallr)
       BHIP(b, pdk::launch_apply_batch(chk, g, false, false, b->x64, nullptr, nullptr, b->q64,
-                                      b->tabs[g.N], s));
+                                      nullptr, b->tabs[g.N], s));
     BHIP(b, pdk::launch_stream_batch(0, chk, b->b64, b->q64, b->r64, nullptr, nullptr, s));
     BHIP(b, pdk::launch_project_null_batch(chk, b->r64, s));
     BHIP(b, pdk::launch_stream_batch(3, chk, nullptr, nullptr, b->r64, nullptr, nullptr, s));
@@ -840,7 +847,7 @@ int pd_batch_cg_solve(pd_batch* b, int prec, const void* bvec, void* xvec, doubl
   BHIP(b, pdk::launch_project_null_batch(all, b->x64, s));
   for (const BatchGroup& g : b->g64_all)
     BHIP(b, pdk::launch_apply_batch(all, g, false, false, b->x64, nullptr, nullptr, b->q64,
-                                    b->tabs[g.N], s));
+                                    nullptr, b->tabs[g.N], s));
   BHIP(b, pdk::launch_stream_batch(0, all, b->b64, b->q64, b->r64, nullptr, nullptr, s));
   BHIP(b, pdk::launch_finalize_batch(0, all, s));
   BHIP(b, hipMemcpyAsync(xvec, b->x64, n * sizeof(double), hipMemcpyDeviceToDevice, s));

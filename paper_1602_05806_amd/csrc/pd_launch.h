@@ -181,12 +181,19 @@ struct BatchGroup {
 };
 
 // fuse: CG iteration form (skips problems whose done flag is set or whose mode differs from
-// it.want); else y = A x for the group's problems that are not finished.
+// it.want), including the deferred x += alpha_{k-1} p_old into xsol (the iterate of this
+// precision: FP32 correction or FP64 x); else y = A x for the group's problems that are not
+// finished (xsol unused).
 hipError_t launch_apply_batch(const BatchIter& it, const BatchGroup& g, bool fp32, bool fuse,
-                              const void* x, const void* pold, void* pnew, void* y,
+                              const void* x, const void* pold, void* pnew, void* y, void* xsol,
                               const OpTables& tb, hipStream_t s);
-hipError_t launch_update_batch(const BatchIter& it, bool fp32, void* x, const void* p,
-                               const void* q, void* r, hipStream_t s);
+// r -= alpha q with partials of <r, r>; publishes alpha and xk for the deferred x update
+hipError_t launch_update_batch(const BatchIter& it, bool fp32, const void* q, void* r,
+                               hipStream_t s);
+// chunk end: the deferred x update of every listed problem that stopped before making it
+hipError_t launch_xflush_batch(const BatchIter& it, double* x64, float* d32, const double* pa64,
+                               const double* pb64, const float* pa32, const float* pb32,
+                               hipStream_t s);
 // Streaming passes over the list (problems with fin set are skipped except by mode 1):
 // 0: r64 = b - q64 (partials of <r64, r64> into tmp); 1: x64 += scale d32, d32 = 0;
 // 2: r32 = r64 / scale (partials into the rho slot koff & 1), problems in FP32 mode;
