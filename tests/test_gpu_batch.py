@@ -114,8 +114,13 @@ def test_batch_matches_direct_and_single(pd, prec):
         assert mass_norm(g, got - alone) <= 2e-10 * mass_norm(g, ref)
         if prec == pd.PD_FP64:
             # the recurrence is the same CG in the same precision: the iteration counts agree up
-            # to the rounding of the dot products (different partial-sum order)
-            assert abs(info["iters"] - infos[j]["iters"]) <= max(3, info["iters"] // 50)
+            # to the rounding of the dot products (different partial-sum order) until the single
+            # solve's first stop; the single solve then continues while its recomputed residual
+            # is above rtol (the batched FP64 solve stops on the recurrence)
+            if info["outer_iters"] == 1:
+                assert abs(info["iters"] - infos[j]["iters"]) <= max(3, info["iters"] // 50)
+            else:
+                assert info["iters"] >= infos[j]["iters"] - max(3, info["iters"] // 50)
         ctx.close()
     B.close()
 
