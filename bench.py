@@ -103,6 +103,25 @@ def run_steps(pd, ctx, u, p, nsteps, torch):
     return time.perf_counter() - t0, iters, solves
 
 
+def device_copy_gbs(torch, mib=512, reps=10):
+    """Measured HBM bandwidth of a plain device copy (torch copy_ of `mib` MiB, twice the size of
+    the 256 MB Infinity Cache): read + write bytes / time, best of `reps`."""
+    n = mib * 1024 * 1024 // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2.0 * n * 8 / best / 1e9
+
+
 def cpu_baseline(cfg, iters=40):
     """Time the oracle (assembled CSR + plain CG loop) at the full workload size for a fixed number
     of iterations in a subprocess limited to one thread."""
@@ -364,6 +383,7 @@ def main():
 
     r64, r32 = results["fp64"], results["fp32_refine64"]
     ndof = ctx.ndof
+    copy_gbs = device_copy_gbs(torch)     # after the timed steps; reference for the roofline
     value = ndof * r64["iters"] / r64["seconds"]
     kt = r64["kernel"]
     avg_ms = kt["total_ms"] / max(kt["launches"], 1)
@@ -399,7 +419,9 @@ def main():
                      "traffic": measured_traffic(args.workload, "fp64"),
                      "kernel": "k_apply (fused CG form, FP64)",
                      "avg_launch_us": 1e3 * avg_ms, "launches": kt["launches"],
-                     "bytes_per_launch": kt["bytes_per_launch"]},
+                     "bytes_per_launch": kt["bytes_per_launch"],
+                     "copy_gbs": copy_gbs,
+                     "frac_of_copy": (achieved / copy_gbs) if achieved else None},
         "fp32_refine64": {
             "value": ndof * r32["iters"] / r32["seconds"], "unit": "DoF-iterations/s",
             "ms_per_step": 1e3 * r32["seconds"] / args.steps,
