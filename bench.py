@@ -185,7 +185,7 @@ def bench_batch(args, pd, torch):
             work += sum(n * i["iters"] for n, i in zip(ndofs, infos))
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
-        bytes_it = 40.0 if prec == pd.PD_FP32_REFINE64 else 80.0
+        bytes_it = 36.0 if prec == pd.PD_FP32_REFINE64 else 72.0   # 9 vector words per DoF
         res[name] = dict(seconds=secs, work=work, infos=infos, bytes_it=bytes_it)
         del x
     r32, r64 = res["fp32_refine64"], res["fp64"]
