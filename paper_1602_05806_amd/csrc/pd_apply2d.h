@@ -131,11 +131,13 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
     const int gj = wrap_small(ty0 + bj - 1, a.ny);
     return ((size_t)gj * a.nx + gi) * NC + l;
   };
-  auto stage_load = [&](int tile) {
+  // box rows [bj_lo, bj_hi) of a tile into registers
+  auto stage_load = [&](int tile, int bj_lo, int bj_hi) {
     const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
     const bool flat = tx0 >= 1 && tx0 + TX + 1 <= a.nx;        // no row crosses the x seam
 #pragma unroll
     for (int bj = 0; bj < TY + 2; ++bj) {
+      if (bj < bj_lo || bj >= bj_hi) continue;
       const bool halo = bj == 0 || bj == TY + 1;
       const int gj = wrap_small(ty0 + bj - 1, a.ny);
       const size_t row0 = ((size_t)gj * a.nx + (halo ? tx0 : tx0 - 1)) * NC;
@@ -159,7 +161,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
     }
   };
 
-  if (t_begin < t_end) stage_load(t_begin);
+  if (t_begin < t_end) stage_load(t_begin, 0, TY + 2);
   T beta = T(0);
   bool xupd = false;   // FUSE = 2: x += xalpha p_old on the owned cells
   T xalpha = T(0);
@@ -205,7 +207,11 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
       }
     }
     __syncthreads();
-    if (PF && tile + 1 < t_end) stage_load(tile + 1);   // in flight during the compute below
+    // the next tile's loads, in flight during the compute below: half of the box rows before the
+    // x-lines, half before the y-lines (issuing all at once stalls this wave's x-lines while the
+    // memory pipeline drains)
+    constexpr int HALF = (TY + 2) / 2;
+    if (PF && tile + 1 < t_end) stage_load(tile + 1, 0, HALF);
 
     // x-lines: (cell c, l2); nodes l1 = 0..N
     for (int L = tid; L < NT * n; L += 256) {
@@ -223,6 +229,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
       line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + l2 * n + l1] = wgt * v; });
     }
     __syncthreads();
+    if (PF && tile + 1 < t_end) stage_load(tile + 1, HALF, TY + 2);
 
     // y-lines: (cell c, l1); nodes l2 = 0..N; final values are stored here
     for (int L = tid; L < NT * n; L += 256) {
@@ -251,7 +258,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
       });
     }
     __syncthreads();
-    if (!PF && tile + 1 < t_end) stage_load(tile + 1);
+    if (!PF && tile + 1 < t_end) stage_load(tile + 1, 0, TY + 2);
   }
   if (FUSE) {
     const double s = block_sum_all<256>(dot);
