@@ -393,26 +393,23 @@ __global__ __launch_bounds__(kBlock) void k_node_sums_batch(BatchIter it, const 
   const long long c0 = (long long)sl.lb * per;
   const long long c1 = c0 + per < P.ncells ? c0 + per : P.ncells;
   const int NC = P.NC;
-  for (int l = threadIdx.x; l < NC; l += kBlock) {
-    double s = 0.0;
-    for (long long c = c0; c < c1; ++c) s += v[P.dof_off + c * NC + l];
-    it.nsp[((size_t)sl.j * kNsBlocksBatch + sl.lb) * kMaxNC2D + l] = s;
-  }
+  __shared__ double acc[kBlock];
+  __shared__ double out[kMaxNC2D];
+  column_sums<double>(v + P.dof_off, NC, c0, c1, NC, acc, out);
+  for (int l = threadIdx.x; l < NC; l += kBlock)
+    it.nsp[((size_t)sl.j * kNsBlocksBatch + sl.lb) * kMaxNC2D + l] = out[l];
 }
 
 __global__ __launch_bounds__(kBlock) void k_null_finalize_batch(BatchIter it) {
   const int j = it.list[blockIdx.x];
   const BProb& P = it.probs[j];
   if (!serves(it, it.st + j)) return;
-  __shared__ double S[kMaxNC2D], U[kMaxNC2D];
+  __shared__ double S[kMaxNC2D], U[kMaxNC2D], acc[kBlock];
   const int nb = P.nns;
   const int n = P.N + 1, NC = P.NC;
   const double* Pn = it.pnull + P.N * 81;
-  for (int l = threadIdx.x; l < NC; l += kBlock) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += it.nsp[((size_t)j * kNsBlocksBatch + b) * kMaxNC2D + l];
-    S[l] = s / (double)P.ncells;
-  }
+  column_sums<double>(it.nsp + (size_t)j * kNsBlocksBatch * kMaxNC2D, kMaxNC2D, 0, nb, NC, acc, S);
+  for (int l = threadIdx.x; l < NC; l += kBlock) S[l] = S[l] / (double)P.ncells;
   __syncthreads();
   for (int d = 0; d < 2; ++d) {
     const int stride = d == 0 ? 1 : n;

@@ -93,6 +93,45 @@ __device__ __forceinline__ double block_sum_all(double v) {
   return tot;
 }
 
+// Sums over rows [r0, r1) of the row-major array a (row stride ld, NC columns), one per column,
+// returned in out[0..NC) of every block (shared; acc: kBlock shared doubles of scratch). Every thread works: thread t takes column t % NC of the rows
+// r0 + t / NC, r0 + t / NC + G, ... (G = kBlock / NC row groups, four independent accumulators),
+// and the G partial sums of a column are added in group order. NC > kBlock: one thread per column.
+template <typename T>
+__device__ __forceinline__ void column_sums(const T* __restrict__ a, int ld, long long r0,
+                                            long long r1, int NC, double* __restrict__ acc,
+                                            double* __restrict__ out) {
+  if (NC <= kBlock) {
+    const int G = kBlock / NC;
+    const int g = threadIdx.x / NC, l = threadIdx.x - g * NC;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (g < G) {
+      long long r = r0 + g;
+      for (; r + 3LL * G < r1; r += 4LL * G) {
+        s0 += (double)a[r * ld + l];
+        s1 += (double)a[(r + G) * ld + l];
+        s2 += (double)a[(r + 2LL * G) * ld + l];
+        s3 += (double)a[(r + 3LL * G) * ld + l];
+      }
+      for (; r < r1; r += G) s0 += (double)a[r * ld + l];
+    }
+    acc[threadIdx.x] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    for (int c = threadIdx.x; c < NC; c += kBlock) {
+      double t = 0.0;
+      for (int q = 0; q < G; ++q) t += acc[q * NC + c];
+      out[c] = t;
+    }
+  } else {
+    for (int c = threadIdx.x; c < NC; c += kBlock) {
+      double t = 0.0;
+      for (long long r = r0; r < r1; ++r) t += (double)a[r * ld + c];
+      out[c] = t;
+    }
+  }
+  __syncthreads();
+}
+
 // Fixed-order sum of `n` partials written by a previous kernel; result in every thread.
 template <int NT>
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n) {

@@ -244,17 +244,17 @@ struct P81 {
   double P[81];
 };
 
+// part[b][l] = sum over the cells of block b of v(cell, l)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_node_sums(const T* __restrict__ v, long long ncells,
                                                       int NC, double* __restrict__ part) {
+  __shared__ double acc[kBlock];
+  __shared__ double out[kMaxNC];
   const long long per = (ncells + gridDim.x - 1) / gridDim.x;
   const long long c0 = (long long)blockIdx.x * per;
   const long long c1 = c0 + per < ncells ? c0 + per : ncells;
-  for (int l = threadIdx.x; l < NC; l += kBlock) {
-    double s = 0.0;
-    for (long long c = c0; c < c1; ++c) s += (double)v[c * NC + l];
-    part[(size_t)blockIdx.x * NC + l] = s;
-  }
+  column_sums<T>(v, NC, c0, c1, NC, acc, out);
+  for (int l = threadIdx.x; l < NC; l += kBlock) part[(size_t)blockIdx.x * NC + l] = out[l];
 }
 
 // corr = (P (x) ... (x) P) (sum of the node partials) / ncells  (single block)
@@ -262,12 +262,9 @@ __global__ __launch_bounds__(kBlock) void k_null_finalize(const double* __restri
                                                           int nblk, long long ncells, int NC,
                                                           int dim, int n, P81 P,
                                                           double* __restrict__ corr) {
-  __shared__ double S[kMaxNC], U[kMaxNC];
-  for (int l = threadIdx.x; l < NC; l += kBlock) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * NC + l];
-    S[l] = s / (double)ncells;
-  }
+  __shared__ double S[kMaxNC], U[kMaxNC], acc[kBlock];
+  column_sums<double>(part, NC, 0, nblk, NC, acc, S);
+  for (int l = threadIdx.x; l < NC; l += kBlock) S[l] = S[l] / (double)ncells;
   __syncthreads();
   for (int d = 0; d < dim; ++d) {
     int stride = 1;
