@@ -14,7 +14,9 @@
 //       LDS with the plane's x/y face halos.
 // FUSE = 1 is the CG form: the search direction p = r + beta p_old is formed while loading
 // (beta read from the device-resident CG state), stored for the owned cells, and the block sums of
-// <p, A p> feed the grid reduction that sets alpha = rho / <p, A p>.
+// <p, A p> feed the grid reduction that sets alpha = rho / <p, A p>. FUSE = 2 adds the deferred x
+// update of the previous iteration, x += alpha_{k-1} p_old, on the owned cells (p_old is loaded
+// anyway).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
