@@ -6,7 +6,7 @@ import pytest
 
 from oracle import layout
 from oracle.operators import (Grid, pressure_operator, viscous_operator, div_rhs, grad_update,
-                              apply_at, null_basis_tiled, project_null)
+                              apply_at, apply_operator, null_basis_tiled, project_null)
 from oracle.solvers import FastDiag, cg
 from oracle.step import dual_to_main, main_to_dual, rk3, StepOracle
 import synthetic
@@ -298,3 +298,32 @@ def test_full_size_apply_sampled(pd):
         got = yt[tuple(idx.T)]
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
         ctx.close()
+
+
+@pytest.mark.parametrize("dim,cells,N,dt,m", [(2, (256, 256), 6, 5e-4, 4), (3, (64, 64, 64), 4, 1e-3, 2)])
+def test_full_size_cg_iterates_in_bench_configuration(pd, dim, cells, N, dt, m):
+    """The fused CG kernels at full size in the launch configuration the benchmark times (256^2
+    N = 6: three tiles per workgroup with the next tile's loads in flight; 64^3 N = 4: whole-column
+    z segments), with the deferred x update: after m FP64 iterations from x0 = 0 the iterate
+    equals the oracle's plain CG iterate computed with the matrix-free oracle operator."""
+    import torch
+    from scipy.sparse.linalg import LinearOperator
+    print(f"full-size CG iterates dim={dim} cells={cells} N={N} m={m}", flush=True)
+    L = (1.0,) * dim
+    g = Grid(cells, L, N)
+    rng = np.random.default_rng(81)
+    bt = project_null(g, rng.standard_normal(g.shape()), [null_basis_tiled(c, N) for c in cells])
+    A = LinearOperator((g.ndof, g.ndof), dtype=np.float64,
+                       matvec=lambda v: apply_operator(g, v, 0.0, dt).reshape(-1))
+    x_ref, it, _ = cg(A, bt.reshape(-1), 1e-30, m)
+    assert it == m
+    ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, 1e-3)
+    x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(layout.tensor_to_blocked(bt, cells, g.n)), x,
+                          1e-30, m)
+    ctx.close()
+    assert info["status"] == pd.PD_ENOCONV and info["iters"] == m
+    got = layout.blocked_to_tensor(host(x), cells, g.n).reshape(-1)
+    rel = np.linalg.norm(got - x_ref) / np.linalg.norm(x_ref)
+    print(f"  relative difference {rel:.2e}", flush=True)
+    assert rel <= 1e-12
