@@ -379,13 +379,25 @@ static Geom geometry(const ApplyLaunch& L) {
     g.ntx = (nx + TL::TX - 1) / TL::TX;
     g.nty = (ny + TL::TY - 1) / TL::TY;
     const long long cols = (long long)g.ntx * g.nty;
-    // planes per segment: as many workgroups as the device holds at once (one wave of
-    // workgroups; each segment re-reads two boundary planes), segments of at least 4 planes.
-    // 64^3 N = 4: FP64 one workgroup per CU -> 64 planes, FP32 two -> 32; measured 6 % faster
-    // than 16 planes in FP64 and equal in FP32.
+    // planes per segment: the workgroups run in waves of `res` (what the device holds at once)
+    // and a segment of kz planes costs about kz + 2 plane steps (two boundary planes re-read),
+    // so kz minimises waves * (kz + 2), ties to the longer segment; at least 4 planes.
+    // 64^3 N = 4: FP64 (one workgroup per CU) 64 planes, FP32 32 (6 % faster than 16 in FP64);
+    // 48^3 N = 3 FP64 (144 columns): 85 us per apply against 101 us with one wave of 27-plane
+    // segments (the second wave held 32 workgroups).
     const long long res = resident_3d<T, N>(L.fuse, L.prefetch != 0);
-    int kz = res > 0 ? (int)std::min<long long>(nz, (cols * nz + res - 1) / res)
-                     : (int)((cols * nz) / 1024);
+    int kz = (int)((cols * nz) / 1024);
+    if (res > 0) {
+      long long best = -1;
+      for (int z = std::min(4, nz); z <= nz; ++z) {
+        const long long waves = (cols * ((nz + z - 1) / z) + res - 1) / res;
+        const long long cost = waves * (z + 2);
+        if (best < 0 || cost <= best) {
+          best = cost;
+          kz = z;
+        }
+      }
+    }
     if (kz < 4) kz = 4;
     if (kz > nz) kz = nz;
     if (L.kz_override > 0) kz = L.kz_override < nz ? L.kz_override : nz;
