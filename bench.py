@@ -388,6 +388,10 @@ def main():
     kt = r64["kernel"]
     avg_ms = kt["total_ms"] / max(kt["launches"], 1)
     achieved = kt["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9 if kt["launches"] else None
+    # vector words per DoF and CG iteration: the one-kernel 2D form moves 8 in its operator
+    # kernel; the two-kernel form 6 there plus 3 in the update kernel
+    apply_words = kt["bytes_per_launch"] / (8.0 * ndof) if kt["launches"] else 6.0
+    cg_words = 8.0 if apply_words > 7.0 else apply_words + 3.0
     kt32 = r32["kernel"]
     avg32 = kt32["total_ms"] / max(kt32["launches"], 1)
     ach32 = kt32["bytes_per_launch"] / (avg32 * 1e-3) / 1e9 if kt32["launches"] else None
@@ -412,7 +416,8 @@ def main():
         "pressure_iters_per_step": r64["iters"] / args.steps,
         "pressure_solve_ms_per_step": r64["psolve_ms"] / args.steps,
         "pressure_dof_it_per_s_solve_only": ndof * r64["iters"] / (r64["psolve_ms"] * 1e-3),
-        "algorithmic_gbs_cg": ndof * r64["iters"] * 72.0 / (r64["psolve_ms"] * 1e-3) / 1e9,
+        "cg_words_per_dof_it": cg_words,
+        "algorithmic_gbs_cg": ndof * r64["iters"] * 8.0 * cg_words / (r64["psolve_ms"] * 1e-3) / 1e9,
         "rel_res_true_max": r64["rel_res_true"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,

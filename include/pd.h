@@ -215,13 +215,21 @@ int pd_step_adjoint(pd_ctx* ctx, void* const u[3], void* const ubar[3], pd_solve
  *   PD_CFG_DEFER_X       where CG iteration k's x += alpha_k p_k is made: 1 (default) = in the
  *                        operator kernel of iteration k + 1 (it reads p_k anyway; 9 instead of
  *                        10 vector words per DoF and iteration), 0 = in the update kernel
- * The last five only change the launch shape; results are identical up to the block order of
- * the dot-product partial sums (and, for PD_CFG_DEFER_X, the rounding of x). */
+ *   PD_CFG_ONE_KERNEL    2D only: 1 = one kernel per CG iteration: the operator kernel of
+ *                        iteration k also makes the residual update of iteration k - 1,
+ *                        r_k = r_{k-1} - alpha_{k-1} q_{k-1}, and its x update (8 vector words
+ *                        per DoF and iteration instead of 9, one launch instead of two), with
+ *                        rho_k = |r_k|^2 expanded from <r_{k-1}, q_{k-1}> and <q_{k-1}, q_{k-1}>;
+ *                        0 (default) = operator kernel + update kernel (measured as fast or
+ *                        faster on gfx950). 3D solves always use two kernels.
+ * The last six only change the launch shape; results are identical up to the block order of
+ * the dot-product partial sums (for PD_CFG_DEFER_X also the rounding of x, for
+ * PD_CFG_ONE_KERNEL the rounding of rho_k). */
 enum {
   PD_CFG_STEP_PREC = 0, PD_CFG_P_RTOL = 1, PD_CFG_V_RTOL = 2, PD_CFG_MAXIT = 3,
   PD_CFG_CONVECTION = 4, PD_CFG_RU_FACTOR = 5, PD_CFG_TIMING = 6, PD_CFG_CHECK_EVERY = 7,
   PD_CFG_KZ = 8, PD_CFG_TILES_PER_WG = 9, PD_CFG_PREFETCH = 10, PD_CFG_TILE_VARIANT = 11,
-  PD_CFG_DEFER_X = 12
+  PD_CFG_DEFER_X = 12, PD_CFG_ONE_KERNEL = 13
 };
 int pd_configure(pd_ctx* ctx, int key, double value);
 
@@ -232,7 +240,8 @@ int pd_configure(pd_ctx* ctx, int key, double value);
  * dispatch on the solve's stream; launches after convergence (early exits) are not counted.
  * bytes_per_launch: algorithmic bytes of one launch of the last timed solve (reads r and p_old,
  * writes p and A p, and with the deferred x update also reads and writes x: 6 words per DoF,
- * else 4). Synchronises with the last stream. */
+ * else 4; the one-kernel 2D form also reads A p_{k-1} and writes r: 8 words). Synchronises with
+ * the last stream. */
 int pd_timing(pd_ctx* ctx, int prec, double* total_ms, long long* launches,
               double* bytes_per_launch, int reset);
 

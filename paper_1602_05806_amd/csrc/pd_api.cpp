@@ -33,6 +33,7 @@ struct pd_ctx {
   int kz = 0, tiles_per_wg = 0, prefetch = 1;   // operator-kernel launch shape
   int tile_variant = 0;                          // 2D tile shape (0 = largest fitting)
   int defer_x = 1;         // 1: x update made by the next apply kernel, 0: by the update kernel
+  int one_kernel = 0;      // 2D: one kernel per CG iteration (residual update folded in)
   // device workspace
   CgState* st = nullptr;       // CG state of the (inner) solve
   CgState* st2 = nullptr;      // outer refinement / residual norms
@@ -43,6 +44,9 @@ struct pd_ctx {
   double* null_corr = nullptr;
   double *r64 = nullptr, *pa64 = nullptr, *pb64 = nullptr, *q64 = nullptr, *bw64 = nullptr;
   float *r32 = nullptr, *pa32 = nullptr, *pb32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+  // 2D one-kernel CG iterations: second residual and A p buffers, 2 x 4-tuple partials
+  double *r64b = nullptr, *q64b = nullptr, *fpart = nullptr;
+  float *r32b = nullptr, *q32b = nullptr;
   double* um[3] = {nullptr, nullptr, nullptr};
   double* s1[3] = {nullptr, nullptr, nullptr};
   double* s2[3] = {nullptr, nullptr, nullptr};
@@ -56,7 +60,7 @@ struct pd_ctx {
   std::vector<hipEvent_t> tev;
   double t_ms[2] = {0, 0};
   long long t_cnt[2] = {0, 0};
-  double t_words[2] = {6, 6};  // vector words per DoF of the timed launches (6 or 4)
+  double t_words[2] = {6, 6};  // vector words per DoF of the timed launches (8, 6 or 4)
   hipStream_t last_stream = nullptr;
 };
 
@@ -140,12 +144,23 @@ int read_state(pd_ctx* c, const CgState* dev, CgState* host, hipStream_t s) {
 }
 
 // Device buffers of one CG run: residual r, the two search-direction buffers (iteration k reads
-// buf[k % 2] and writes buf[(k + 1) % 2]) and q = A p.
+// buf[k % 2] and writes buf[(k + 1) % 2]) and q = A p. The one-kernel form also double-buffers
+// r and q: iteration k reads r_{k-1} and q_{k-1} from {r, rb}[(k + 1) % 2], {q, qb}[(k + 1) % 2]
+// and writes r_k, q_k to {r, rb}[k % 2], {q, qb}[k % 2]; a run (re)started at iteration k takes
+// r_k from {r, rb}[k % 2].
 struct CgBuffers {
   void *r, *pa, *pb, *q;
+  void *rb = nullptr, *qb = nullptr;
 };
 
 // A chunked conjugate-gradient run on the device, FP64 or FP32 vectors (FP64 scalars).
+// One-kernel form (2D, opt-in): the apply kernel of iteration k also makes the residual update
+// of iteration k - 1 (r_k = r_{k-1} - alpha_{k-1} q_{k-1} while loading r and q for its tile and
+// halo) and the x update, so one iteration is one kernel and 8 vector words per DoF. Measured
+// at 256^2 N = 6 it is not faster: the tile kernel streams at the same rate as with 6 words
+// (about 3.6 TB/s), so the 3 words moved out of the update kernel (5.3 TB/s) cost about what
+// the saved kernel boundary gains (FP64 57 us per iteration kernel against 44 + 15 us; FP32
+// slower).
 // Iteration k = apply kernel (p_k = r_k + beta_k p_{k-1}, q = A p_k, partials of <p_k, q>) +
 // update kernel (x += alpha_k p_k, r -= alpha_k q, partials of <r_{k+1}, r_{k+1}>). Deferred
 // form (default): the x update rides on the apply kernel of iteration k + 1, which reads p_k
@@ -163,6 +178,8 @@ struct CgRun {
   hipStream_t s = nullptr;
   bool timed = false;
   bool defer = true;         // x update made by the next apply kernel (else by the update kernel)
+  bool one = false;          // one kernel per iteration (2D)
+  int kfirst = 0;            // iteration at which the run was (re)started: r_k given, no update
   int k = 0;                 // next iteration to launch / iterations completed after a stop
   int nrho = 0, nsig = 0;
   double* rho[2] = {nullptr, nullptr};
@@ -177,13 +194,16 @@ int cg_prepare(pd_ctx* c, CgRun* R) {
   R->rho[1] = c->rhopart + pdk::kMaxStreamPartials;
   R->L = base_launch(c, R->op, R->fp32);
   R->defer = c->defer_x != 0;
-  R->L.fuse = R->defer ? 2 : 1;
-  R->L.xsol = R->defer ? R->x : nullptr;
+  R->one = c->one_kernel != 0 && c->dim == 2 && R->B.rb && R->B.qb;
+  R->L.fuse = R->one ? 3 : R->defer ? 2 : 1;
+  R->L.xsol = (R->one || R->defer) ? R->x : nullptr;
   R->L.st = R->st;
   R->L.nrho = R->nrho;
   R->L.sigpart = c->sigpart;
   R->nsig = (int)pdk::apply_blocks(R->L);
+  R->L.npart = R->nsig;
   R->k = 0;
+  R->kfirst = 0;
   PD_HIP(c, pdk::launch_zero(R->fp32, R->B.pa, c->ndof, R->s));
   return PD_OK;
 }
@@ -198,6 +218,17 @@ int cg_launch(pd_ctx* c, CgRun* R) {
   L.pold = buf[k & 1];
   L.pnew = buf[(k + 1) & 1];
   L.y = R->B.q;
+  if (R->one) {
+    void* rb[2] = {R->B.r, R->B.rb};
+    void* qb[2] = {R->B.q, R->B.qb};
+    L.first = k == R->kfirst;
+    L.x = L.first ? rb[k & 1] : rb[(k + 1) & 1];
+    L.rout = rb[k & 1];
+    L.qprev = qb[(k + 1) & 1];
+    L.y = qb[k & 1];
+    L.fin = c->fpart + 4 * (size_t)pdk::kMaxPartials * ((k + 1) & 1);
+    L.fout = c->fpart + 4 * (size_t)pdk::kMaxPartials * (k & 1);
+  }
   L.ev_start = L.ev_stop = nullptr;
   if (R->timed && k % c->timing == 0) {       // every timing-th launch carries events
     const size_t j = (size_t)(k / c->timing);
@@ -210,7 +241,8 @@ int cg_launch(pd_ctx* c, CgRun* R) {
     L.ev_stop = c->tev[2 * j + 1];
   }
   PD_HIP(c, pdk::launch_apply(L, R->s));
-  PD_HIP(c, pdk::launch_cg_update(R->fp32, R->defer ? nullptr : R->x,
+  if (!R->one)
+    PD_HIP(c, pdk::launch_cg_update(R->fp32, R->defer ? nullptr : R->x,
                                   R->defer ? nullptr : buf[(k + 1) & 1], R->B.q, R->B.r, c->ndof,
                                   R->st, k, c->sigpart, R->nsig, R->rho[(k + 1) & 1], R->s));
   ++R->k;
@@ -254,7 +286,7 @@ int cg_run_until(pd_ctx* c, CgRun* R, int maxit, Pred stop, CgState* fin) {
 void cg_collect_timing(pd_ctx* c, const CgRun& R) {
   if (!R.timed) return;
   const int tslot = R.fp32 ? 1 : 0;
-  c->t_words[tslot] = R.defer ? 6.0 : 4.0;
+  c->t_words[tslot] = R.one ? 8.0 : R.defer ? 6.0 : 4.0;
   // sampled launches of the completed iterations (launches queued after the stop exit at once)
   for (int k = 0; k < R.k; k += c->timing) {
     const size_t j = (size_t)(k / c->timing);
@@ -298,7 +330,7 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
   R.op = op;
   R.fp32 = false;
   R.x = x;
-  R.B = CgBuffers{c->r64, c->pa64, c->pb64, c->q64};
+  R.B = CgBuffers{c->r64, c->pa64, c->pb64, c->q64, c->r64b, c->q64b};
   R.st = c->st;
   R.s = s;
   R.timed = timed;
@@ -332,6 +364,10 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
     if (res <= goal || res > kTrueGap * goal || (prev_res > 0.0 && res > 0.5 * prev_res)) break;
     prev_res = res;
     PD_HIP(c, pdk::launch_dot(false, c->r64, c->r64, c->ndof, R.rho[R.k & 1], s));
+    if (R.one && (R.k & 1))
+      PD_HIP(c, hipMemcpyAsync(c->r64b, c->r64, c->ndof * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+    R.kfirst = R.k;
     PD_HIP(c, pdk::launch_state_set(c->st, maxit, rtol * rtol * bnorm * bnorm, s));
   }
   cg_collect_timing(c, R);
@@ -377,7 +413,7 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
   R.op = op;
   R.fp32 = true;
   R.x = c->d32;
-  R.B = CgBuffers{c->r32, c->pa32, c->pb32, c->q32};
+  R.B = CgBuffers{c->r32, c->pa32, c->pb32, c->q32, c->r32b, c->q32b};
   R.st = c->st;
   R.s = s;
   R.timed = timed;
@@ -451,7 +487,9 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
       PD_HIP(c, pdk::launch_zero(true, buf[R.k & 1], n, s));
       ++inf->restarts;
     }
-    PD_HIP(c, pdk::launch_to_f32_dot(c->r64, c->r32, n, 1.0 / scale, R.rho[R.k & 1], s));
+    float* r32k = (R.one && (R.k & 1)) ? c->r32b : c->r32;
+    PD_HIP(c, pdk::launch_to_f32_dot(c->r64, r32k, n, 1.0 / scale, R.rho[R.k & 1], s));
+    R.kfirst = R.k;
     ref = res / scale;
     PD_HIP(c, pdk::launch_state_set(c->st, maxit, inner_tol2(ref), s));
   }
@@ -888,6 +926,14 @@ int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int
     pd_destroy(c);
     return rc;
   }
+  if (c->dim == 2 &&
+      ((rc = dev_alloc(c, &c->r64b, n)) || (rc = dev_alloc(c, &c->q64b, n)) ||
+       (rc = dev_alloc(c, &c->r32b, n)) || (rc = dev_alloc(c, &c->q32b, n)) ||
+       (rc = dev_alloc(c, &c->fpart, 8 * (size_t)pdk::kMaxPartials)))) {
+    g_setup_err = c->err;
+    pd_destroy(c);
+    return rc;
+  }
   hipStream_t s = S(hip_stream);
   hipError_t he = hipHostMalloc((void**)&c->hst, 2 * sizeof(CgState), hipHostMallocDefault);
   if (he == hipSuccess) he = hipEventCreate(&c->ev[0]);
@@ -913,7 +959,7 @@ void pd_destroy(pd_ctx* c) {
   (void)hipDeviceSynchronize();
   void* bufs[] = {c->st, c->st2, c->rhopart, c->sigpart, c->tmppart, c->null_part, c->null_corr,
                   c->r64, c->pa64, c->pb64, c->q64, c->bw64, c->r32, c->pa32, c->pb32, c->q32,
-                  c->d32, c->qbuf};
+                  c->d32, c->qbuf, c->r64b, c->q64b, c->fpart, c->r32b, c->q32b};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (int d = 0; d < 3; ++d) {
@@ -1238,6 +1284,10 @@ int pd_configure(pd_ctx* c, int key, double v) {
     case PD_CFG_DEFER_X:
       if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_DEFER_X must be 0 or 1");
       c->defer_x = (int)v;
+      break;
+    case PD_CFG_ONE_KERNEL:
+      if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_ONE_KERNEL must be 0 or 1");
+      c->one_kernel = (int)v;
       break;
     default:
       return fail(c, PD_EINVAL, "unknown configuration key");

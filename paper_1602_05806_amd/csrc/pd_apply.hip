@@ -16,7 +16,11 @@
 // (beta read from the device-resident CG state), stored for the owned cells, and the block sums of
 // <p, A p> feed the grid reduction that sets alpha = rho / <p, A p>. FUSE = 2 adds the deferred x
 // update of the previous iteration, x += alpha_{k-1} p_old, on the owned cells (p_old is loaded
-// anyway).
+// anyway). FUSE = 3 (2D) also makes the residual update of the previous iteration while loading,
+// r_k = r_{k-1} - alpha_{k-1} q_{k-1}, so that one kernel is one CG iteration: 8 vector words
+// per DoF (r, q, p, x read; r, q, p, x written) against 6 + 3 for FUSE = 2 and the update
+// kernel, and one kernel boundary fewer. The scalars come from the expansion of |r_k|^2 with
+// the inner products <r, A p> and <A p, A p> of the previous launch (fused_scalars).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -301,28 +305,35 @@ struct Geom {
 
 // Workgroups of the fused 2D kernel (tile variant v, prefetch pf) the device holds at once:
 // occupancy per CU (registers, LDS) times CUs, queried once per device and shape.
+template <typename T, int N, int F>
+static const void* kernel_2d(int v, int pf) {
+  return pf ? (v == 1 ? (const void*)k_apply2d<T, N, 1, F, 1>
+                      : v == 2 ? (const void*)k_apply2d<T, N, 2, F, 1>
+                               : (const void*)k_apply2d<T, N, 0, F, 1>)
+            : (v == 1 ? (const void*)k_apply2d<T, N, 1, F, 0>
+                      : v == 2 ? (const void*)k_apply2d<T, N, 2, F, 0>
+                               : (const void*)k_apply2d<T, N, 0, F, 0>);
+}
+
+// (fused forms 1, 2 use the form-2 kernel; form 3 its own)
 template <typename T, int N>
-static long long resident_2d(int v, int pf) {
+static long long resident_2d(int fuse, int v, int pf) {
   constexpr int kDev = 16;
-  static int cache[kDev][3][2];
-  static bool init[kDev][3][2];
+  static int cache[kDev][2][3][2];
+  static bool init[kDev][2][3][2];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) return 0;
-  if (!init[dev][v][pf]) {
-    const void* f = pf ? (v == 1 ? (const void*)k_apply2d<T, N, 1, 2, 1>
-                                 : v == 2 ? (const void*)k_apply2d<T, N, 2, 2, 1>
-                                          : (const void*)k_apply2d<T, N, 0, 2, 1>)
-                       : (v == 1 ? (const void*)k_apply2d<T, N, 1, 2, 0>
-                                 : v == 2 ? (const void*)k_apply2d<T, N, 2, 2, 0>
-                                          : (const void*)k_apply2d<T, N, 0, 2, 0>);
+  const int f3 = fuse == 3 ? 1 : 0;
+  if (!init[dev][f3][v][pf]) {
+    const void* f = f3 ? kernel_2d<T, N, 3>(v, pf) : kernel_2d<T, N, 2>(v, pf);
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
-    cache[dev][v][pf] = per_cu * cus;
-    init[dev][v][pf] = true;
+    cache[dev][f3][v][pf] = per_cu * cus;
+    init[dev][f3][v][pf] = true;
   }
-  return cache[dev][v][pf];
+  return cache[dev][f3][v][pf];
 }
 
 // Workgroups of the 3D kernel (fused form 0, 1 or 2; prefetch pf) the device holds at once.
@@ -367,8 +378,10 @@ static Geom geometry(const ApplyLaunch& L) {
     if (L.tiles_per_wg > 0) {
       per = L.tiles_per_wg;
     } else if (L.fuse) {
-      const long long res = resident_2d<T, N>(L.tile_variant, L.prefetch != 0);
-      if (res > 0) per = std::min<long long>(3, std::max<long long>(1, (ntiles + res - 1) / res));
+      const long long res = resident_2d<T, N>(L.fuse, L.tile_variant, L.prefetch != 0);
+      // (the one-kernel form holds fewer workgroups: 4 tiles each at 256^2 N = 6 FP64)
+      const long long cap = L.fuse == 3 ? 4 : 3;
+      if (res > 0) per = std::min<long long>(cap, std::max<long long>(1, (ntiles + res - 1) / res));
     }
     g.kz = (int)per;
     g.ntz = 1;
@@ -429,6 +442,13 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   a.nrho = L.nrho;
   a.sigpart = L.sigpart;
   a.xsol = (T*)L.xsol;
+  a.qprev = (const T*)L.qprev;
+  a.rout = (T*)L.rout;
+  a.fin = L.fin;
+  a.fout = L.fout;
+  a.npart = L.npart;
+  a.first = L.first;
+  if (L.fuse == 3 && L.dim != 2) return hipErrorInvalidValue;
   const Blk<T, N> B = make_blk<T, N>(*L.tab);
   const Geom g = geometry<T, N>(L);
   a.ntx = g.ntx;
@@ -443,7 +463,10 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   hipEvent_t e0 = L.ev_start, e1 = L.ev_stop;
   if (L.dim == 2) {
 #define PD_A2D(VV)                                                                              \
-  if (L.fuse == 2) {                                                                            \
+  if (L.fuse == 3) {                                                                            \
+    if (pf) hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 3, 1>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B); \
+    else hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 3, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);   \
+  } else if (L.fuse == 2) {                                                                     \
     if (pf) hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 2, 1>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B); \
     else hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 2, 0>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B);   \
   } else if (L.fuse) {                                                                          \

@@ -24,7 +24,20 @@ struct ApplyArgs {
   const double* rho_cur;
   int nrho;
   double* sigpart;
-  T* xsol;            // FUSE = 2: CG iterate, x += alpha_{k-1} p_old on owned cells
+  T* xsol;            // FUSE = 2, 3: CG iterate, x += alpha_{k-1} p_old on owned cells
+  // FUSE = 3 (one kernel per CG iteration, 2D): the residual update of iteration k - 1 is made
+  // here, r_k = r_{k-1} - alpha_{k-1} q_{k-1}, from x = r_{k-1} and qprev = q_{k-1} (halo cells
+  // included, so both are double-buffered: rout and y must not alias x and qprev). first = 1:
+  // x already holds r_k (iteration 0, or a run resumed after a residual replacement) with the
+  // partials of <r_k, r_k> in rho_cur; nothing is updated. Each block writes the 4-tuple
+  // (<p, A p>, <r, A p>, <A p, A p>, <r, r>) of its owned cells to fout[4 slot ..], and the
+  // next launch reads the npart tuples of this one from fin.
+  const T* qprev;
+  T* rout;
+  const double* fin;
+  double* fout;
+  int npart;
+  int first;
 };
 
 __device__ __forceinline__ int wrapi(int i, int m) {
@@ -103,6 +116,7 @@ struct Tile2D {
 template <typename T, int N, int V, int FUSE, int PF>
 __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T, N>& B,
                                              int t_begin, int t_end, int slot) {
+  constexpr bool RU = FUSE == 3;                // residual update folded in
   using TL = Tile2D<T, N, V>;
   constexpr int n = N + 1, NC = n * n, TX = TL::TX, TY = TL::TY, NT = TX * TY;
   constexpr int BX = TX + 2;                    // box width in cells
@@ -121,7 +135,10 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
   T* __restrict__ yg = a.y;
   const int tid = threadIdx.x;
   T rvi[TY][JI], pvi[TY][JI], rvh[2][JH], pvh[2][JH];
-  T xvi[FUSE == 2 ? TY : 1][FUSE == 2 ? JI : 1];   // FUSE = 2: x of the owned cells
+  T xvi[FUSE >= 2 ? TY : 1][FUSE >= 2 ? JI : 1];   // FUSE >= 2: x of the owned cells
+  T qvi[RU ? TY : 1][RU ? JI : 1], qvh[RU ? 2 : 1][RU ? JH : 1];   // q_{k-1}
+  T rki[RU ? TY : 1][RU ? JI : 1];              // r_k of the owned cells (for <r_k, A p_k>)
+  const bool rupd = RU && !a.first;
 
   // global element index of box element e of box row bj (bj in 0..TY+1) of the tile at (tx0, ty0)
   auto gindex = [&](int tx0, int ty0, int bj, int e) -> size_t {
@@ -147,14 +164,20 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
         const int e = tid + 256 * j;
         if (e < (halo ? RH : RI)) {
           const size_t g = flat ? row0 + e : gindex(tx0, ty0, bj, e);
-          T rv = xg[g], pv = T(0);
+          T rv = xg[g], pv = T(0), qv = T(0);
           if (FUSE) pv = pg[g];
+          if (rupd) qv = a.qprev[g];
           if (halo) {
-            if (j < JH) { rvh[bj ? 1 : 0][j] = rv; pvh[bj ? 1 : 0][j] = pv; }
+            if (j < JH) {
+              rvh[bj ? 1 : 0][j] = rv;
+              pvh[bj ? 1 : 0][j] = pv;
+              if (RU) qvh[bj ? 1 : 0][j] = qv;
+            }
           } else if (j < JI) {
             rvi[bj - 1][j] = rv;
             pvi[bj - 1][j] = pv;
-            if (FUSE == 2 && e >= NC && e < (TX + 1) * NC) xvi[bj - 1][j] = a.xsol[g];
+            if (RU) qvi[bj - 1][j] = qv;
+            if (FUSE >= 2 && e >= NC && e < (TX + 1) * NC) xvi[bj - 1][j] = a.xsol[g];
           }
         }
       }
@@ -165,7 +188,13 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
   T beta = T(0);
   bool xupd = false;   // FUSE = 2: x += xalpha p_old on the owned cells
   T xalpha = T(0);
-  if (FUSE) {
+  if (rupd) {
+    const FusedScalars sc = fused_scalars<256>(a.st, a.k, a.fin, a.npart, t_begin == 0);
+    if (sc.stop) return;
+    beta = (T)sc.beta;
+    xupd = true;
+    xalpha = (T)sc.alpha;
+  } else if (FUSE) {
     const int k = a.kbase ? *a.kbase + a.k : a.k;
     const IterScalars sc = iteration_scalars<256>(a.st, k, a.rho_cur, a.nrho, t_begin == 0);
     if (sc.stop) return;
@@ -176,7 +205,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
       if (xupd && t_begin == 0 && threadIdx.x == 0) a.st->xused = k - 1;
     }
   }
-  double dot = 0.0;
+  double dot = 0.0, gam = 0.0, nu = 0.0, rr = 0.0;   // RU: <r, A p>, <A p, A p>, <r, r>
   for (int tile = t_begin; tile < t_end; ++tile) {
     const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
     // registers -> LDS (p = r + beta p_old formed here; owned cells also stored to global)
@@ -189,7 +218,9 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
         const int e = tid + 256 * j;
         if (e < (halo ? RH : RI) && (halo ? j < JH : j < JI)) {
           T v = halo ? rvh[bj ? 1 : 0][j] : rvi[bj - 1][j];
+          if (rupd) v = v - xalpha * (halo ? qvh[bj ? 1 : 0][j] : qvi[bj - 1][j]);
           if (FUSE) {
+            const T rk = v;
             // beta = 0 (first iteration, restart) must not read p_old, which may hold anything
             if (beta != T(0)) v = v + beta * (halo ? pvh[bj ? 1 : 0][j] : pvi[bj - 1][j]);
             if (!halo) {
@@ -198,7 +229,12 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
               if (bi >= 1 && bi <= TX && ui < a.nx && uj < a.ny) {
                 const size_t g = ((size_t)uj * a.nx + ui) * NC + (e - bi * NC);
                 png[g] = v;
-                if (FUSE == 2 && xupd) a.xsol[g] = xvi[bj - 1][j] + xalpha * pvi[bj - 1][j];
+                if (FUSE >= 2 && xupd) a.xsol[g] = xvi[bj - 1][j] + xalpha * pvi[bj - 1][j];
+                if (RU) {
+                  if (rupd) a.rout[g] = rk;
+                  rki[bj - 1][j] = rk;
+                  rr += (double)rk * (double)rk;
+                }
               }
             }
           }
@@ -254,13 +290,43 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
         if (valid) {
           yg[base + l2 * n + l1] = val;
           dot += (double)xc * (double)val;
+          if (RU) {
+            nu += (double)val * (double)val;
+            ys[c * NC + l2 * n + l1] = val;     // read back below for <r_k, A p_k>
+          }
         }
       });
     }
     __syncthreads();
+    if (RU) {
+      // <r_k, A p_k> over the owned cells: r_k from registers (staging layout), A p_k from the
+      // accumulator, which the y-lines overwrote with the final values (the next tile's x-lines
+      // write it only after the staging barrier)
+#pragma unroll
+      for (int bj = 1; bj <= TY; ++bj) {
+#pragma unroll
+        for (int j = 0; j < JI; ++j) {
+          const int e = tid + 256 * j;
+          if (e < RI) {
+            const int bi = e / NC;
+            const int ui = tx0 + bi - 1, uj = ty0 + bj - 1;
+            if (bi >= 1 && bi <= TX && ui < a.nx && uj < a.ny)
+              gam += (double)rki[bj - 1][j] * (double)ys[((bj - 1) * TX + bi - 1) * NC + e - bi * NC];
+          }
+        }
+      }
+    }
     if (!PF && tile + 1 < t_end) stage_load(tile + 1, 0, TY + 2);
   }
-  if (FUSE) {
+  if (RU) {
+    double s4[4] = {dot, gam, nu, rr};
+    block_sum4_all<256>(s4);
+    if (threadIdx.x == 0) {
+      double* o = a.fout + 4 * (size_t)slot;
+      *reinterpret_cast<double2*>(o) = make_double2(s4[0], s4[1]);
+      *reinterpret_cast<double2*>(o + 2) = make_double2(s4[2], s4[3]);
+    }
+  } else if (FUSE) {
     const double s = block_sum_all<256>(dot);
     if (threadIdx.x == 0) a.sigpart[slot] = s;
   }

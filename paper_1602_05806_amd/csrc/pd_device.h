@@ -174,6 +174,97 @@ __device__ __forceinline__ IterScalars iteration_scalars(CgState* st, int k,
   return r;
 }
 
+// Four sums over the block in a fixed order, returned to every thread.
+template <int NT>
+__device__ __forceinline__ void block_sum4_all(double (&v)[4]) {
+  __shared__ double red4[(NT + 63) / 64][4];
+  __shared__ double tot4[4];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = wave_sum(v[i]);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red4[wid][i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < (NT + 63) / 64; ++w) s += red4[w][threadIdx.x];
+    tot4[threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = tot4[i];
+}
+
+// Scalars of CG iteration k >= 1 in the one-kernel form, where the apply kernel of iteration k
+// also makes the residual update of iteration k - 1. The previous launch wrote per block the
+// 4-tuple (<p, A p>, <r, A p>, <A p, A p>, <r, r>) of iteration k - 1, so
+//   alpha_{k-1} = rho_{k-1} / sigma_{k-1},
+//   rho_k = |r_{k-1} - alpha_{k-1} q_{k-1}|^2 = rho_{k-1} - 2 alpha gamma + alpha^2 nu
+// (the expansion with the actual inner products, not the exact-arithmetic identity
+// gamma = sigma), beta_k = rho_k / rho_{k-1}, and the stop decision on rho_k.
+struct FusedScalars {
+  double alpha, beta;
+  bool stop;
+};
+
+template <int NT>
+__device__ __forceinline__ FusedScalars fused_scalars(CgState* st, int k,
+                                                      const double* __restrict__ part, int np,
+                                                      bool writer) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < np; i += NT) {
+    const double2 a = *reinterpret_cast<const double2*>(part + 4 * i);
+    const double2 b = *reinterpret_cast<const double2*>(part + 4 * i + 2);
+    s[0] += a.x;
+    s[1] += a.y;
+    s[2] += b.x;
+    s[3] += b.y;
+  }
+  block_sum4_all<NT>(s);
+  const double sigma = s[0], gamma = s[1], nu = s[2], rho_prev = s[3];
+  FusedScalars f;
+  f.alpha = rho_prev / sigma;
+  f.beta = 0.0;
+  if (!(sigma > 0.0) || !isfinite(f.alpha)) {
+    if (threadIdx.x == 0 && writer) {
+      st->sigma = sigma;
+      st->status = -5;
+      st->iter = k - 1;
+      st->done = 1;
+    }
+    f.stop = true;
+    return f;
+  }
+  const double rho = rho_prev - 2.0 * f.alpha * gamma + f.alpha * f.alpha * nu;
+  f.beta = (k != st->restart_k && !st->fresh) ? rho / rho_prev : 0.0;
+  int status = 1;
+  if (!isfinite(rho)) status = -5;
+  else if (rho <= st->tol2 && !(st->even_stop && (k & 1))) status = 0;
+  else if (k >= st->maxit) status = -4;
+  f.stop = status != 1;
+  if (threadIdx.x == 0 && writer) {
+    st->sigma = sigma;
+    st->alpha = f.alpha;
+    st->xk = k - 1;                      // x += alpha_{k-1} p_{k-1}: this launch or a flush
+    st->rho_hist[(k + 1) & 1] = rho_prev;
+    st->rho_hist[k & 1] = rho;
+    st->rho = rho;
+    st->beta = f.beta;
+    st->iter = k;
+    if (f.stop) {
+      st->status = status;
+      st->done = 1;
+    } else {
+      st->xused = k - 1;
+    }
+  }
+  return f;
+}
+
 // Map the hardware block index to a logical tile so that each XCD (blocks are dispatched to
 // the 8 XCDs round-robin) processes one contiguous range of tiles, keeping neighbouring tiles
 // (whose halos overlap) in the same L2.

@@ -17,6 +17,7 @@ struct ApplyLaunch {
   bool fp32 = false;
   int fuse = 0;              // 1: CG iteration form (p = r + beta p_old; sigma partials)
                              // 2: the same plus the deferred x += alpha_{k-1} p_old into xsol
+                             // 3: 2 plus the residual update r -= alpha_{k-1} q_{k-1}
   const void* x = nullptr;   // operand (fuse = 0) or r (fuse = 1, 2)
   const void* pold = nullptr;
   void* pnew = nullptr;
@@ -29,7 +30,17 @@ struct ApplyLaunch {
   const double* rho_cur = nullptr;
   int nrho = 0;
   double* sigpart = nullptr;
-  void* xsol = nullptr;      // fuse = 2: the CG iterate x (updated in place for owned cells)
+  void* xsol = nullptr;      // fuse = 2, 3: the CG iterate x (updated in place for owned cells)
+  // fuse = 3 (2D only): one kernel per CG iteration; the residual update of iteration k - 1 is
+  // made here from x = r_{k-1} and qprev = q_{k-1} into rout (see ApplyArgs); fin / fout: the
+  // 4-tuple partials of the previous / this launch (npart tuples each); first = 1 when x already
+  // holds r_k with the partials of <r_k, r_k> in rho_cur.
+  const void* qprev = nullptr;
+  void* rout = nullptr;
+  const double* fin = nullptr;
+  double* fout = nullptr;
+  int npart = 0;
+  int first = 0;
   int kz_override = 0;       // 3D: planes per column segment (0 = automatic)
   int tiles_per_wg = 0;      // 2D: tiles per persistent workgroup (0 = automatic)
   int prefetch = 1;          // prefetch the next tile (2D) / next plane's halo (3D) into registers

@@ -65,7 +65,7 @@ def test_apply_fp64_fp32(pd, dim, cells, N, op):
     ctx.close()
 
 
-def _solve_case(pd, dim, cells, N, op, prec, project_rhs, rtol, seed):
+def _solve_case(pd, dim, cells, N, op, prec, project_rhs, rtol, seed, one_kernel=None):
     import torch
     print(f"solve dim={dim} cells={cells} N={N} op={op} prec={prec} seed={seed}", flush=True)
     L = (1.0,) * dim
@@ -79,6 +79,8 @@ def _solve_case(pd, dim, cells, N, op, prec, project_rhs, rtol, seed):
     else:
         ref_t = fd.solve(bt, 1.0, nu * dt)
     ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, nu)
+    if one_kernel is not None:
+        pd.pd_configure(ctx, pd.PD_CFG_ONE_KERNEL, one_kernel)
     x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
     info = pd.pd_cg_solve(ctx, op, prec, dev(b), x, rtol, 200000)
     got_t = layout.blocked_to_tensor(host(x), cells, g.n)
@@ -101,18 +103,27 @@ def test_pressure_solve_matches_min_norm(pd, dim, cells, N, prec):
     assert err <= 1e-9
 
 
-@pytest.mark.parametrize("defer", [1, 0])
+# (PD_CFG_ONE_KERNEL, PD_CFG_DEFER_X): one kernel per iteration (2D, opt-in), operator kernel +
+# update kernel with the deferred x update (default), and the plain two-kernel form
+FORMS = {"one": (1, 1), "defer": (0, 1), "plain": (0, 0)}
+
+
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("dim,cells,N,m", [(2, (9, 7), 4, 1), (2, (9, 7), 4, 2), (2, (12, 10), 6, 37),
-                                           (3, (4, 5, 3), 3, 23), (2, (6, 5), 0, 9)])
-def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m, defer):
+                                           (3, (4, 5, 3), 3, 23), (2, (6, 5), 0, 9),
+                                           (2, (17, 11), 3, 3), (2, (17, 11), 3, 50)])
+def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m, form):
     """After exactly m FP64 iterations from x0 = 0 (maxit = m) the GPU iterate equals the oracle's
     plain CG iterate x_m on the assembled matrix. Pins the iteration bookkeeping of the device
-    loop, including the x update of the last iteration, which the apply kernel of the next
-    iteration would have made and the stop leaves to the flush kernel (PD_CFG_DEFER_X = 1), and
-    the plain form with x updated in the update kernel (0). (The oracle's own x_m moves by
-    ~1e-15 relative under 1e-15 perturbations of b for these cases.)"""
+    loop in each form: the x update of the last iteration, which the apply kernel of the next
+    iteration would have made and the stop leaves to the flush kernel (deferred forms), the
+    residual update folded into the next operator kernel with rho_k from the expanded inner
+    products (one-kernel form), and the plain form with x updated in the update kernel. (The
+    oracle's own x_m moves by ~1e-15 relative under 1e-15 perturbations of b for these
+    cases.)"""
     import torch
-    print(f"cg iterates dim={dim} cells={cells} N={N} m={m} defer={defer}", flush=True)
+    one, defer = FORMS[form]
+    print(f"cg iterates dim={dim} cells={cells} N={N} m={m} form={form}", flush=True)
     L = (1.0,) * dim
     dt = 5e-4
     g = Grid(cells, L, N)
@@ -123,6 +134,7 @@ def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m, defer):
     assert it == m
     ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, 1e-2)
     pd.pd_configure(ctx, pd.PD_CFG_DEFER_X, defer)
+    pd.pd_configure(ctx, pd.PD_CFG_ONE_KERNEL, one)
     x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
     info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(layout.tensor_to_blocked(bt, cells, g.n)), x,
                           1e-30, m)
@@ -132,13 +144,16 @@ def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m, defer):
     assert np.linalg.norm(got - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
 
 
-def test_timing_samples_every_sth_launch(pd):
+@pytest.mark.parametrize("one", [1, 0])
+def test_timing_samples_every_sth_launch(pd, one):
     """PD_CFG_TIMING = s times every s-th operator launch of a pressure solve (iterations
-    0, s, 2s, ... below the final count) and reports the 6-word algorithmic bytes per launch."""
+    0, s, 2s, ... below the final count) and reports the algorithmic bytes per launch: 8 words
+    per DoF in the one-kernel form, 6 with the separate update kernel."""
     import torch
     cells, N, m, s = (10, 8), 3, 37, 4
     g = Grid(cells, (1.0, 1.0), N)
     ctx = pd.pd_setup(2, cells, (1.0, 1.0), N, 5e-4, 0.6, 1e-2)
+    pd.pd_configure(ctx, pd.PD_CFG_ONE_KERNEL, one)
     pd.pd_configure(ctx, pd.PD_CFG_TIMING, s)
     pd.pd_timing(ctx, pd.PD_FP64, reset=True)
     x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
@@ -147,7 +162,28 @@ def test_timing_samples_every_sth_launch(pd):
     ctx.close()
     assert info["iters"] == m
     assert t["launches"] == (m + s - 1) // s and t["total_ms"] > 0.0
-    assert t["bytes_per_launch"] == 6.0 * g.ndof * 8.0
+    assert t["bytes_per_launch"] == (8.0 if one else 6.0) * g.ndof * 8.0
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+@pytest.mark.parametrize("cells,N,rtol", [((23, 19), 5, 1e-12), ((40, 33), 3, 1e-11)])
+def test_one_kernel_form_matches_two_kernel_form(pd, cells, N, rtol, prec):
+    """Full solves (FP64 with its true-residual continuation, FP32 with FP64 residual
+    replacements, which restart the run at odd and even iterations and so exercise both
+    residual buffers) in the one-kernel and the two-kernel form: both meet the tolerance on the
+    true residual, reach the minimum-norm solution, and take iteration counts within 2 % of
+    each other (the forms differ only in the rounding of rho_k)."""
+    res = {}
+    for one in (1, 0):
+        print(f"one-kernel form cells={cells} N={N} prec={prec} one={one}", flush=True)
+        info, err = _solve_case(pd, 2, cells, N, 0, prec, True, rtol, 31, one_kernel=one)
+        assert info["status"] == pd.PD_OK
+        assert info["rel_res_true"] <= 1.05 * rtol
+        assert err <= 1e3 * rtol
+        res[one] = info
+    if prec == 2:
+        assert res[1]["outer_iters"] >= 2
+    assert abs(res[1]["iters"] - res[0]["iters"]) <= max(2, 0.02 * res[0]["iters"])
 
 
 @pytest.mark.parametrize("prec", [0, 2])
