@@ -299,12 +299,18 @@ int pd_batch_configure(pd_batch* batch, int key, double value);
 /* Solve every problem of the batch: b = packed FP64 right-hand sides (read only; each problem's
  * part is first projected onto range(A_p) as in pd_cg_solve), x = packed FP64 solutions (out;
  * the initial guess is zero; each problem's result is projected onto range(A_p), the minimum
- * norm solution). prec: PD_FP64 (stop when the recurrence residual <= rtol ||b_j||) or
- * PD_FP32_REFINE64 (stop when the FP64 residual b_j - A x_j recomputed at a chunk end is
- * <= rtol ||b_j||). maxit caps each problem's iterations. info: count entries or NULL; ms is the
- * whole batch's time; rel_res_true is recomputed in FP64 for every problem after the solve;
- * outer_iters counts residual replacements. Synchronises. Returns PD_OK when every problem
- * converged, else PD_EBREAKDOWN if any problem broke down, else PD_ENOCONV. */
+ * norm solution). prec: PD_FP64 (when the recurrence residual meets rtol ||b_j|| at an even
+ * iteration, the FP64 residual b_j - A x_j recomputed at the chunk end decides: above the goal
+ * but within 16x of it, the iterations resume from it with the same direction, at most 8 times,
+ * each halving it; a larger gap is the FP64 rounding floor and ends the problem, as in
+ * pd_cg_solve) or PD_FP32_REFINE64 (stop when the FP64 residual recomputed at a chunk end is
+ * <= rtol ||b_j||). maxit caps each problem's iterations. info: count entries or NULL; iters
+ * counts the iterations a problem ran (a problem stopped inside a chunk waits for the chunk end
+ * without iterating); ms is the whole batch's time; rel_res_true is recomputed in FP64 for every
+ * problem after the solve; outer_iters counts the chunk-end FP64 residual evaluations (at least
+ * 1); fallback_iter: FP32 iterations run before a refinement problem continued in FP64 (-1 =
+ * none). Synchronises. Returns PD_OK when every problem converged, else PD_EBREAKDOWN if any
+ * problem broke down, else PD_ENOCONV. */
 int pd_batch_cg_solve(pd_batch* batch, int prec, const void* b, void* x, double rtol, int maxit,
                       pd_solve_info* info, void* hip_stream);
 

@@ -349,9 +349,11 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
     // The recurrence residual met the tolerance; after thousands of iterations it can sit below
     // the true one, so b - A x decides. If it is above but within kTrueGap of the goal, it
     // replaces r (partials of <r, r> for iteration R.k) and the run continues with the same
-    // direction (a reliable update). A larger gap, or a replacement that did not halve the true
-    // residual, is the FP64 rounding floor of b - A x (about eps cond(A) |b|): the solve ends
-    // there (status PD_OK from the recurrence, the true residual reported).
+    // direction (a reliable update) unless the recurrence had drifted more than 4x below it (then
+    // beta would be huge and the old direction would swamp the new residual: the direction
+    // restarts). A larger gap, or a replacement that did not halve the true residual, is the
+    // FP64 rounding floor of b - A x (about eps cond(A) |b|): the solve ends there (status PD_OK
+    // from the recurrence, the true residual reported).
     if (!(fin.done && fin.status == PD_OK) || R.k >= maxit || inf->outer_iters > kMaxTrueChecks)
       break;
     double res = 0.0;
@@ -363,6 +365,11 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
     const double goal = rtol * bnorm;
     if (res <= goal || res > kTrueGap * goal || (prev_res > 0.0 && res > 0.5 * prev_res)) break;
     prev_res = res;
+    if (!(res <= 4.0 * std::sqrt(fin.rho))) {
+      void* buf[2] = {R.B.pa, R.B.pb};
+      PD_HIP(c, pdk::launch_zero(false, buf[R.k & 1], c->ndof, s));
+      ++inf->restarts;
+    }
     PD_HIP(c, pdk::launch_dot(false, c->r64, c->r64, c->ndof, R.rho[R.k & 1], s));
     if (R.one && (R.k & 1))
       PD_HIP(c, hipMemcpyAsync(c->r64b, c->r64, c->ndof * sizeof(double),

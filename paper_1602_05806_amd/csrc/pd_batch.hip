@@ -48,8 +48,7 @@ __device__ __forceinline__ bool iterates(const BatchIter& it, const CgState* st)
 // recurrence has just met the tolerance (their true residual decides).
 __device__ __forceinline__ bool serves(const BatchIter& it, const CgState* st) {
   if (it.skip_fin && st->fin) return false;
-  if (it.want == -2)
-    return !st->mode64 || (st->fallback_k >= 0 && st->done && st->status == 0);
+  if (it.want == -2) return !st->mode64 || (st->done && st->status == 0);
   return it.want < 0 || st->mode64 == it.want;
 }
 
@@ -254,6 +253,10 @@ __global__ __launch_bounds__(kBlock) void k_stream_batch(BatchIter it, const dou
 // FP32 refinement: replacements in a row without a new smallest FP64 residual after which the
 // problem continues in FP64 (FP32 arithmetic has stopped reducing it)
 constexpr int kStallLimit = 16;
+// FP64 runs: chunk-end checks of the true residual after the recurrence met the tolerance, and
+// the largest true / goal ratio that is iterated away (beyond it: FP64 rounding floor)
+constexpr int kTrueChecks = 8;
+constexpr double kTrueGap = 16.0;
 
 // ---- per-problem finalize (one block per list entry)
 // what 0: aux = sum of the tmp partials (residual norm squared)
@@ -261,9 +264,12 @@ constexpr int kStallLimit = 16;
 //         r / scale); tol2 = the pause threshold max(ru, rtol)^2 of the FP32 iterations (scaled
 //         units); a zero or NaN right-hand side finishes the problem at once
 // what 2: FP64 start: bnorm2 = sum; tol2 = (rtol_j)^2 * sum
-// what 3: chunk end, every unfinished problem. FP64-mode problems finish when their iterations
-//   stopped; for those that fell back from the refinement, a stop on the tolerance is checked
-//   against the recomputed FP64 residual first (resuming from it when it is above). FP32-mode
+// what 3: chunk end, every unfinished problem. FP64-mode problems whose iterations stopped on
+//   the tolerance are checked against the recomputed FP64 residual: finished when it is <= rtol
+//   ||b||; else an FP64 run resumes from it with the same direction (within kTrueGap of the
+//   goal, at most kTrueChecks times, each halving it; else finished at the rounding floor) and
+//   a problem that fell back from the refinement resumes from it with a new direction. Other
+//   stops of FP64-mode problems finish them. FP32-mode
 //   problems decide from the FP64 residual of the replacement
 //   (sum = ||b - A x||^2): finished when it is <= rtol ||b|| (or not finite, or out of
 //   iterations); else, when that residual has grown beyond twice the smallest one so far or has
@@ -308,39 +314,68 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
     st->bnorm2 = s;
     st->tol2 = P.rtol * P.rtol * s;
     st->aux = s;
+    st->ref = 0.0;
+    st->even_stop = 1;
   } else {
     st->switched = 0;
     const int k = *it.kbase + it.koff;
     if (st->mode64) {
       if (!st->done) return;
-      if (st->fallback_k < 0 || st->status != 0) {   // an FP64 run, or out of iterations / broken
+      if (st->status != 0) {           // out of iterations or broken down
         st->fin = 1;
         return;
       }
-      // fallen back from the refinement: the FP64 recurrence met the tolerance; the recomputed
-      // residual decides, else the iterations resume from it with a new direction
+      // the FP64 recurrence met the tolerance: the recomputed residual decides
       st->aux = s;
+      st->outer += 1;
       const double res = sqrt(s);
       const double goal = P.rtol * sqrt(st->bnorm2);
       if (!isfinite(res)) {
         st->fin = 1;
         st->status = -5;
-      } else if (res <= goal) {
+        return;
+      }
+      if (res <= goal) {
         st->fin = 1;
-      } else if (k >= st->maxit) {
-        st->fin = 1;
-        st->status = -4;
+        return;
+      }
+      if (st->fallback_k < 0) {
+        // an FP64 run: the iterations resume from the recomputed residual (with the same
+        // direction: the stop was at an even iteration, so the direction and rho of the
+        // previous iteration sit in the slots the next chunk reads) while it is within
+        // kTrueGap of the goal, at most kTrueChecks times, each halving it; a larger gap is the
+        // FP64 rounding floor of b - A x: finished, the true residual reported
+        if (res > kTrueGap * goal || st->outer > kTrueChecks ||
+            (st->ref > 0.0 && res > 0.5 * st->ref)) {
+          st->fin = 1;
+          return;
+        }
+        st->ref = res;
+        // a recurrence that drifted more than 4x below the true residual would make beta huge
+        // and the old direction swamp the new residual: restart the direction then
+        if (!(res <= 4.0 * sqrt(st->rho))) {
+          st->fresh = 1;
+          st->restarts += 1;
+        }
       } else {
-        st->done = 0;
+        // fallen back from the refinement: resume from it with a new direction
         st->fresh = 1;
-        st->switched = 1;
         st->restarts += 1;
       }
+      if (st->iter - st->idle >= st->maxit) {
+        st->fin = 1;
+        st->status = -4;
+        return;
+      }
+      st->idle += k - st->iter;
+      st->done = 0;
+      st->switched = 1;
       return;
     }
     const bool paused = st->done != 0;
     if (!paused) st->iter = k;         // ran every iteration of the chunk
     st->aux = s;
+    st->outer += 1;
     const double res = sqrt(s);
     const double goal = P.rtol * sqrt(st->bnorm2);
     const double r = res / st->scale;
@@ -350,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
     } else if (res <= goal) {
       st->done = st->fin = 1;
       st->status = 0;
-    } else if ((paused && st->status == -4) || k >= st->maxit) {
+    } else if ((paused && st->status == -4) || st->iter - st->idle >= st->maxit) {
       st->done = st->fin = 1;
       st->status = -4;
     } else {
@@ -360,10 +395,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
       } else {
         st->stall += 1;
       }
+      st->idle += k - st->iter;        // a paused problem resumes at the chunk boundary
       if (r > 2.0 * st->best || st->stall >= kStallLimit) {
         st->mode64 = 1;
         st->switched = 1;
-        st->fallback_k = k;
+        st->fallback_k = k - st->idle;
         st->fresh = 1;
         st->even_stop = 0;
         st->tol2 = goal * goal;
@@ -472,6 +508,8 @@ __global__ void k_state_init_batch(CgState* st, int count, int maxit, double tol
     s.fallback_k = -1;
     s.xk = -1;
     s.xused = -1;
+    s.idle = 0;
+    s.outer = 0;
   }
 }
 

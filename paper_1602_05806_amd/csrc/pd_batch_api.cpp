@@ -444,27 +444,28 @@ int enqueue_chunk(pd_batch* b, const Plan& pl, hipStream_t s) {
   BHIP(b, pdk::launch_xflush_batch(make_iter(b, 0, pl.lall, K, -1, 0), b->x64, b->d32,
                                    (const double*)p64[0], (const double*)p64[1],
                                    (const float*)p32[0], (const float*)p32[1], s));
-  // FP64 residual of the unfinished FP32-mode problems and of fallen-back FP64-mode problems
-  // whose recurrence has met the tolerance
+  // FP64 residual of the unfinished FP32-mode problems and of the FP64-mode problems whose
+  // recurrence has met the tolerance
   const BatchIter chk = make_iter(b, 0, pl.lall, K, -2, 1);
   if (pl.refine) {
     // x64 += scale d32 for every FP32-listed problem (also those that stopped inside the chunk)
     BHIP(b, pdk::launch_stream_batch(1, make_iter(b, 0, pl.l32, K, -1, 0), nullptr, nullptr,
                                      nullptr, b->x64, b->d32, s));
-    for (const BatchGroup& g : pl.gallr)
-      BHIP(b, pdk::launch_apply_batch(chk, g, false, false, b->x64, nullptr, nullptr, b->q64,
-                                      nullptr, b->tabs[g.N], s));
-    BHIP(b, pdk::launch_stream_batch(0, chk, b->b64, b->q64, b->r64, nullptr, nullptr, s));
-    BHIP(b, pdk::launch_project_null_batch(chk, b->r64, s));
-    BHIP(b, pdk::launch_stream_batch(3, chk, nullptr, nullptr, b->r64, nullptr, nullptr, s));
   }
+  for (const BatchGroup& g : pl.gallr)
+    BHIP(b, pdk::launch_apply_batch(chk, g, false, false, b->x64, nullptr, nullptr, b->q64,
+                                    nullptr, b->tabs[g.N], s));
+  BHIP(b, pdk::launch_stream_batch(0, chk, b->b64, b->q64, b->r64, nullptr, nullptr, s));
+  BHIP(b, pdk::launch_project_null_batch(chk, b->r64, s));
+  BHIP(b, pdk::launch_stream_batch(3, chk, nullptr, nullptr, b->r64, nullptr, nullptr, s));
   BHIP(b, pdk::launch_finalize_batch(3, make_iter(b, 0, pl.lall, K, -1, 1), s));
   if (pl.refine) {
     BHIP(b, pdk::launch_stream_batch(2, make_iter(b, 0, pl.l32, K, 0, 1), nullptr, nullptr,
                                      b->r64, nullptr, b->r32, s));
-    BHIP(b, pdk::launch_stream_batch(5, make_iter(b, 0, pl.lall, K, -1, 1), nullptr, nullptr,
-                                     b->r64, nullptr, nullptr, s));
   }
+  // partials of <r, r> of the problems resuming from a recomputed residual
+  BHIP(b, pdk::launch_stream_batch(5, make_iter(b, 0, pl.lall, K, -1, 1), nullptr, nullptr,
+                                   b->r64, nullptr, nullptr, s));
   BHIP(b, pdk::launch_tick(b->d_kbase, b->chunk, s));
   return PD_OK;
 }
@@ -864,9 +865,8 @@ int pd_batch_cg_solve(pd_batch* b, int prec, const void* bvec, void* xvec, doubl
     else if (status != PD_OK) any_noconv = true;
     if (info) {
       pd_solve_info& o = info[j];
-      o.iters = h.iter;
-      const int k32 = h.fallback_k >= 0 ? h.fallback_k : h.iter;
-      o.outer_iters = refine ? k32 / b->chunk : 1;
+      o.iters = h.iter - h.idle;        // iterations run (not the idle ones of a stopped problem)
+      o.outer_iters = h.outer > 1 ? h.outer : 1;
       o.status = status;
       o.restarts = h.restarts;
       o.fallback_iter = refine ? h.fallback_k : -1;

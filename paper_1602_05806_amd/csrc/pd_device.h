@@ -51,7 +51,9 @@ struct CgState {
   int mode64;        // batched: 0 = FP32 iterations with FP64 replacement, 1 = FP64 iterations
   int switched;      // batched: set when the problem has just switched to FP64 iterations
   int stall;         // batched refinement: replacements in a row without a new best residual
-  int fallback_k;    // batched refinement: iteration of the switch to FP64, -1 = none
+  int fallback_k;    // batched refinement: iterations run before the switch to FP64, -1 = none
+  int idle;          // batched: iterations spent stopped inside a chunk before a chunk-end resume
+  int outer;         // batched: chunk-end FP64 residual evaluations of this problem
   // Single-problem runs fold x += alpha_k p_k into the apply kernel of iteration k + 1, which
   // reads p_k anyway: xk = iteration whose alpha (above) awaits that update, -1 = none; xused =
   // the last such iteration an apply kernel has applied (block 0 records it; no block of the
@@ -159,7 +161,7 @@ __device__ __forceinline__ IterScalars iteration_scalars(CgState* st, int k,
   int status = 1;                               // 1 = keep iterating
   if (!isfinite(r.rho)) status = -5;
   else if (r.rho <= st->tol2 && !(st->even_stop && (k & 1))) status = 0;
-  else if (k >= st->maxit) status = -4;
+  else if (k - st->idle >= st->maxit) status = -4;   // iterations run (batched: idle excluded)
   r.stop = status != 1;
   if (threadIdx.x == 0 && writer) {
     st->rho_hist[k & 1] = r.rho;
@@ -244,7 +246,7 @@ __device__ __forceinline__ FusedScalars fused_scalars(CgState* st, int k,
   int status = 1;
   if (!isfinite(rho)) status = -5;
   else if (rho <= st->tol2 && !(st->even_stop && (k & 1))) status = 0;
-  else if (k >= st->maxit) status = -4;
+  else if (k - st->idle >= st->maxit) status = -4;
   f.stop = status != 1;
   if (threadIdx.x == 0 && writer) {
     st->sigma = sigma;

@@ -174,6 +174,8 @@ __global__ void k_state_init(CgState* st, int maxit, double rtol) {
     st->scale = 1.0;
     st->xk = -1;
     st->xused = -1;
+    st->idle = 0;
+    st->outer = 0;
   }
 }
 

@@ -95,9 +95,9 @@ def test_batch_matches_direct_and_single(pd, prec):
         nx, ny, Lx, Ly, N = p
         print(f"  problem {j}: {p} info={infos[j]}", flush=True)
         assert infos[j]["status"] == pd.PD_OK
-        # FP64 stops on its recurrence residual, which drifts below the true one over thousands
-        # of iterations (6.4e-12 true at 8.4e-13 recurrence after 6048 iterations for N = 7);
-        # the refinement stops on the recomputed FP64 residual itself
+        # the refinement stops on the recomputed FP64 residual itself; FP64 checks it when the
+        # recurrence (which drifts below it over thousands of iterations) meets the tolerance
+        # and ends at the FP64 rounding floor when that is above it
         assert infos[j]["rel_res_true"] <= (1e-11 if prec == pd.PD_FP64 else 1e-12)
         g = Grid((nx, ny), (Lx, Ly), N)
         xj = xh[B.offsets[j]:B.offsets[j + 1]]
@@ -113,14 +113,14 @@ def test_batch_matches_direct_and_single(pd, prec):
         alone = layout.blocked_to_tensor(xs.cpu().numpy(), (nx, ny), N + 1)
         assert mass_norm(g, got - alone) <= 2e-10 * mass_norm(g, ref)
         if prec == pd.PD_FP64:
-            # the recurrence is the same CG in the same precision: the iteration counts agree up
-            # to the rounding of the dot products (different partial-sum order) until the single
-            # solve's first stop; the single solve then continues while its recomputed residual
-            # is above rtol (the batched FP64 solve stops on the recurrence)
-            if info["outer_iters"] == 1:
+            # the same CG in the same precision with the same true-residual checks: the counts
+            # of iterations run agree up to the rounding of the dot products (different
+            # partial-sum order) and the batch's stops at even iterations, as long as both took
+            # the same number of checks (near the tolerance one may need a continuation that
+            # the other does not)
+            print(f"    single: iters {info['iters']} checks {info['outer_iters']}", flush=True)
+            if info["outer_iters"] == infos[j]["outer_iters"]:
                 assert abs(info["iters"] - infos[j]["iters"]) <= max(3, info["iters"] // 50)
-            else:
-                assert info["iters"] >= infos[j]["iters"] - max(3, info["iters"] // 50)
         ctx.close()
     B.close()
 
