@@ -907,6 +907,20 @@ int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int
     delete c;
     return fail(nullptr, PD_EINVAL, "grid too large");
   }
+  // one operator launch holds at most kMaxPartials workgroups (2D grids always fit: workgroups
+  // take more tiles; a 3D workgroup owns one column of cells, so the columns must fit)
+  for (int f = 0; f < 2; ++f) {
+    pdk::ApplyLaunch L;
+    L.dim = dim;
+    L.N = N;
+    for (int d = 0; d < 3; ++d) L.nc[d] = d < dim ? ncell[d] : 1;
+    L.fp32 = f == 1;
+    if (pdk::apply_blocks(L) > (unsigned)pdk::kMaxPartials) {
+      delete c;
+      return fail(nullptr, PD_EINVAL,
+                  "grid too large: more cell columns than one operator launch holds");
+    }
+  }
   c->dt = dt;
   c->theta = theta;
   c->nu = nu;

@@ -383,6 +383,11 @@ static Geom geometry(const ApplyLaunch& L) {
       const long long cap = L.fuse == 3 ? 4 : 3;
       if (res > 0) per = std::min<long long>(cap, std::max<long long>(1, (ntiles + res - 1) / res));
     }
+    // Large grids: at most kTarget2D workgroups (every block of the next launch re-sums one
+    // partial per block, and the partial buffers hold kMaxPartials). 1024^2 N = 6 FP64 (32768
+    // tiles): 607-614 us per fused launch for 3 to 16 tiles per workgroup alike.
+    constexpr long long kTarget2D = 8192;
+    per = std::max(per, (ntiles + kTarget2D - 1) / kTarget2D);
     g.kz = (int)per;
     g.ntz = 1;
     g.blocks = (unsigned long long)((ntiles + per - 1) / per);
@@ -414,6 +419,13 @@ static Geom geometry(const ApplyLaunch& L) {
     if (kz < 4) kz = 4;
     if (kz > nz) kz = nz;
     if (L.kz_override > 0) kz = L.kz_override < nz ? L.kz_override : nz;
+    // no more than kMaxPartials workgroups: longer segments when the columns allow it (more
+    // columns than that are rejected at setup)
+    if (cols > 0 && cols <= kMaxPartials) {
+      const long long segs = kMaxPartials / cols;
+      const int kmin = (int)((nz + segs - 1) / segs);
+      if (kz < kmin) kz = kmin;
+    }
     g.kz = kz;
     g.ntz = (nz + kz - 1) / kz;
   }

@@ -336,6 +336,68 @@ def test_full_size_apply_sampled(pd):
         ctx.close()
 
 
+def test_large_2d_grids(pd):
+    """2D grids with more tiles than one launch holds workgroups (2050^2 N = 0: 66049 tiles of
+    8x8 cells; 1460^2 N = 6: 66795 tiles of 8x4) run with several tiles per workgroup: sampled
+    pd_apply outputs (periodic seams included) against the definition evaluated one output at
+    a time; 3 FP64 CG iterations equal the oracle's CG iterate (N = 0) or keep the recurrence
+    and the recomputed residual consistent (N = 6); 3 FP32+refine iterations run."""
+    import torch
+    from scipy.sparse.linalg import LinearOperator
+    for cells, N in [((2050, 2050), 0), ((1460, 1460), 6)]:
+        print(f"large 2D grid cells={cells} N={N}", flush=True)
+        L, dt = (1.0, 1.0), 5e-4
+        g = Grid(cells, L, N)
+        ctx = pd.pd_setup(2, cells, L, N, dt, 0.6, 1e-3)
+        rng = np.random.default_rng(91)
+        x = rng.standard_normal(g.ndof)
+        y = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+        pd.pd_apply(ctx, 0, pd.PD_FP64, dev(x), y)
+        xt = layout.blocked_to_tensor(x, cells, g.n)
+        del x
+        yt = layout.blocked_to_tensor(host(y), cells, g.n)
+        del y
+        shp = g.shape()
+        idx = np.stack([rng.integers(0, s, size=200) for s in shp], axis=1)
+        idx[:4] = 0
+        idx[4:8] = np.array(shp) - 1
+        ref = apply_at(g, xt, idx, 0.0, dt)
+        got = yt[tuple(idx.T)]
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        del xt, yt
+        b = synthetic.random_rhs(92, g.ndof)
+        xs = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+        info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(b), xs, 1e-30, 3)
+        print(f"  fp64 {info}", flush=True)
+        assert info["status"] == pd.PD_ENOCONV and info["iters"] == 3
+        if N == 0:
+            bt = project_null(g, layout.blocked_to_tensor(b, cells, g.n),
+                              [null_basis_tiled(c, N) for c in cells])
+            A = LinearOperator((g.ndof, g.ndof), dtype=np.float64,
+                               matvec=lambda v: apply_operator(g, v, 0.0, dt).reshape(-1))
+            x_ref, it, _ = cg(A, bt.reshape(-1), 1e-30, 3)
+            got = layout.blocked_to_tensor(host(xs), cells, g.n).reshape(-1)
+            assert np.linalg.norm(got - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
+        else:
+            assert abs(info["rel_res_true"] - info["rel_res_recur"]) <= 1e-10
+        xs.zero_()
+        info = pd.pd_cg_solve(ctx, 0, pd.PD_FP32_REFINE64, dev(b), xs, 1e-30, 3)
+        print(f"  fp32 refine {info}", flush=True)
+        assert info["iters"] == 3 and np.isfinite(info["rel_res_true"])
+        assert info["rel_res_true"] < 1.0
+        del xs
+        ctx.close()
+
+
+def test_setup_rejects_too_many_3d_columns(pd):
+    """A 3D workgroup owns one column of cells: a grid with more columns (4112^2 x 4 cells at
+    N = 0, 16x16-cell columns: 66049) than one launch holds workgroups is refused at setup with
+    PD_EINVAL, before any allocation."""
+    with pytest.raises(pd.PdError) as e:
+        pd.pd_setup(3, (4112, 4112, 4), (1.0, 1.0, 1.0), 0, 1e-3, 0.6, 1e-3)
+    assert e.value.code == pd.PD_EINVAL
+
+
 @pytest.mark.parametrize("dim,cells,N,dt,m", [(2, (256, 256), 6, 5e-4, 4), (3, (64, 64, 64), 4, 1e-3, 2)])
 def test_full_size_cg_iterates_in_bench_configuration(pd, dim, cells, N, dt, m):
     """The fused CG kernels at full size in the launch configuration the benchmark times (256^2
