@@ -321,8 +321,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="batch2d_64: pick tile shapes with the autotuner (PD_AUTOTUNE_CACHE)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="batch2d_64: the largest fitting tile everywhere instead of the tile "
+                         "shapes the autotuner picks per (degree, size bucket, precision)")
     ap.add_argument("--fd-dirs", type=int, default=16,
                     help="adjoint3d_48_N3: finite-difference directions checked after timing")
     args = ap.parse_args()
