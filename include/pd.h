@@ -265,8 +265,12 @@ typedef struct pd_batch pd_batch;
 enum { PD_BATCH_AUTOTUNE = 1, PD_BATCH_RETUNE = 2 };
 
 /* Create a batch (tables, descriptors, packed workspace; tuning if asked). ncell, len: 2*count
- * host values; N: count host values; dt > 0. On error *out is NULL and the message is available
- * from pd_batch_last_error(NULL). Synchronises. */
+ * host values; N: count host values; dt > 0; each problem has at most 2^26 cells. The batched
+ * operator runs one tile of cells per workgroup and every workgroup of a problem re-sums that
+ * problem's per-tile partial sums at each iteration (O(tiles^2) reads per launch): the batch is
+ * meant for many problems of up to about 512^2 cells; a single larger problem is better solved
+ * with pd_cg_solve. On error *out is NULL and the message is available from
+ * pd_batch_last_error(NULL). Synchronises. */
 int pd_batch_setup(pd_batch** out, int count, const int* ncell, const double* len, const int* N,
                    double dt, unsigned flags, void* hip_stream);
 

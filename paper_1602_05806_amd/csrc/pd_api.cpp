@@ -947,14 +947,6 @@ int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int
     pd_destroy(c);
     return rc;
   }
-  if (c->dim == 2 &&
-      ((rc = dev_alloc(c, &c->r64b, n)) || (rc = dev_alloc(c, &c->q64b, n)) ||
-       (rc = dev_alloc(c, &c->r32b, n)) || (rc = dev_alloc(c, &c->q32b, n)) ||
-       (rc = dev_alloc(c, &c->fpart, 8 * (size_t)pdk::kMaxPartials)))) {
-    g_setup_err = c->err;
-    pd_destroy(c);
-    return rc;
-  }
   hipStream_t s = S(hip_stream);
   hipError_t he = hipHostMalloc((void**)&c->hst, 2 * sizeof(CgState), hipHostMallocDefault);
   if (he == hipSuccess) he = hipEventCreate(&c->ev[0]);
@@ -1308,6 +1300,15 @@ int pd_configure(pd_ctx* c, int key, double v) {
       break;
     case PD_CFG_ONE_KERNEL:
       if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_ONE_KERNEL must be 0 or 1");
+      if (v == 1 && c->dim == 2 && !c->fpart) {
+        // the form's second residual and A p buffers and its partials, on first use
+        const size_t n = (size_t)c->ndof;
+        int rc = PD_OK;
+        if ((rc = dev_alloc(c, &c->r64b, n)) || (rc = dev_alloc(c, &c->q64b, n)) ||
+            (rc = dev_alloc(c, &c->r32b, n)) || (rc = dev_alloc(c, &c->q32b, n)) ||
+            (rc = dev_alloc(c, &c->fpart, 8 * (size_t)pdk::kMaxPartials)))
+          return rc;
+      }
       c->one_kernel = (int)v;
       break;
     default:
