@@ -243,8 +243,9 @@ int cg_launch(pd_ctx* c, CgRun* R) {
   PD_HIP(c, pdk::launch_apply(L, R->s));
   if (!R->one)
     PD_HIP(c, pdk::launch_cg_update(R->fp32, R->defer ? nullptr : R->x,
-                                  R->defer ? nullptr : buf[(k + 1) & 1], R->B.q, R->B.r, c->ndof,
-                                  R->st, k, c->sigpart, R->nsig, R->rho[(k + 1) & 1], R->s));
+                                    R->defer ? nullptr : buf[(k + 1) & 1], R->B.q, R->B.r,
+                                    c->ndof, R->st, k, c->sigpart, R->nsig,
+                                    R->rho[(k + 1) & 1], R->s));
   ++R->k;
   return PD_OK;
 }
