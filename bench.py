@@ -39,7 +39,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1602_05806_amd/csrc/pd_apply.hip", "paper_1602_05806_amd/csrc/pd_apply2d.h",
-                  "paper_1602_05806_amd/csrc/pd_device.h"]
+                  "paper_1602_05806_amd/csrc/pd_device.h", "paper_1602_05806_amd/csrc/pd_vec.hip"]
 # every TIMING_STRIDE-th operator launch of the timed solves carries dispatch events (events on
 # every launch would add a few microseconds to each iteration of the measured solve)
 TIMING_STRIDE = 16

@@ -1,7 +1,12 @@
 // Streaming vector kernels of the conjugate-gradient loop (arXiv:1602.05806 Section 2.1: the
 // pressure system is solved by a matrix-free CG method) and of the null-space projection.
-// Every reduction accumulates in FP64, sums per block in a fixed order and finishes in the last
-// block to arrive (deterministic: repeated runs give bit-identical scalars).
+// Every reduction accumulates in FP64 and writes one partial per block; the consumer (the next
+// kernel, or a single-block finalize) re-sums the partials in block order (deterministic:
+// repeated runs give bit-identical scalars).
+#include <stdint.h>
+
+#include <type_traits>
+
 #include "pd_device.h"
 #include "pd_launch.h"
 
@@ -104,6 +109,85 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T
     if (XU) x[i] = x[i] + a * p[i];
     const T rn = r[i] - a * q[i];
     r[i] = rn;
+    s += (double)rn * (double)rn;
+  }
+  s = block_sum_all<kBlock>(s);
+  if (threadIdx.x == 0) rho_next[blockIdx.x] = s;
+}
+
+// The deferred form (XU = 0) with 16-byte accesses (float4 / double2): q and r 16-byte aligned,
+// the n % W tail elements handled element-wise. Same arithmetic per element as k_cg_update (only
+// the summation order of the <r, r> partials differs); J vectors per thread (64 B of each array in
+// flight in FP32 against 16 B with element accesses) are loaded before sigma is reduced.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update_vec(const T* __restrict__ q,
+                                                          T* __restrict__ r, long long n,
+                                                          CgState* st, int k,
+                                                          const double* __restrict__ sigpart,
+                                                          int nsig, double* __restrict__ rho_next) {
+  using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  constexpr int W = 16 / (int)sizeof(T);
+  constexpr int J = 4;
+  if (st->done) return;
+  const long long nv = n / W;
+  const V* __restrict__ qv = reinterpret_cast<const V*>(q);
+  V* __restrict__ rv = reinterpret_cast<V*>(r);
+  const long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  V qa[J], ra[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const long long i = i0 + j * stride;
+    if (i < nv) {
+      qa[j] = qv[i];
+      ra[j] = rv[i];
+    }
+  }
+  const double sigma = sum_partials<kBlock>(sigpart, nsig);
+  const double alpha = st->rho / sigma;
+  if (!(sigma > 0.0) || !isfinite(alpha)) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+      st->sigma = sigma;
+      st->status = -5;
+      st->iter = k;
+      st->done = 1;
+    }
+    return;
+  }
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->sigma = sigma;
+    st->alpha = alpha;
+    st->xk = k;
+  }
+  const T a = (T)alpha;
+  double s = 0.0;
+  auto upd = [&](const V& qq, V& rr) {
+    rr.x = rr.x - a * qq.x;
+    rr.y = rr.y - a * qq.y;
+    s += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
+    if constexpr (W == 4) {
+      rr.z = rr.z - a * qq.z;
+      rr.w = rr.w - a * qq.w;
+      s += (double)rr.z * (double)rr.z + (double)rr.w * (double)rr.w;
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const long long i = i0 + j * stride;
+    if (i < nv) {
+      upd(qa[j], ra[j]);
+      rv[i] = ra[j];
+    }
+  }
+  for (long long i = i0 + J * stride; i < nv; i += stride) {
+    const V qq = qv[i];
+    V rr = rv[i];
+    upd(qq, rr);
+    rv[i] = rr;
+  }
+  for (long long e = nv * W + i0; e < n; e += stride) {
+    const T rn = r[e] - a * q[e];
+    r[e] = rn;
     s += (double)rn * (double)rn;
   }
   s = block_sum_all<kBlock>(s);
@@ -319,6 +403,16 @@ hipError_t launch_cg_update(bool fp32, void* x, const void* p, const void* q, vo
                             long long n, CgState* st, int k, const double* sigpart, int nsig,
                             double* rho_next, hipStream_t s) {
   const unsigned G = stream_blocks(n, 4);
+  const bool vec = !x && ((reinterpret_cast<uintptr_t>(q) | reinterpret_cast<uintptr_t>(r)) & 15) == 0;
+  if (vec) {
+    if (fp32)
+      hipLaunchKernelGGL(k_cg_update_vec<float>, dim3(G), dim3(kBlock), 0, s, (const float*)q,
+                         (float*)r, n, st, k, sigpart, nsig, rho_next);
+    else
+      hipLaunchKernelGGL(k_cg_update_vec<double>, dim3(G), dim3(kBlock), 0, s, (const double*)q,
+                         (double*)r, n, st, k, sigpart, nsig, rho_next);
+    return hipGetLastError();
+  }
   if (fp32) {
     if (x)
       hipLaunchKernelGGL((k_cg_update<float, 1>), dim3(G), dim3(kBlock), 0, s, (float*)x,
