@@ -125,6 +125,36 @@ def test_batch_matches_direct_and_single(pd, prec):
     B.close()
 
 
+def test_fp64_true_residual_continuation(pd):
+    """10x12 N = 7 (2:1 cells) at rtol 1e-12: after ~6000 FP64 iterations the recurrence residual
+    sits 7x below the true one. The batched FP64 solve checks the recomputed residual at the chunk
+    end and continues from it with a new direction (the drift exceeds 4x), as the single solve
+    does; both end at or below the tolerance and at the minimum-norm solution."""
+    import torch
+    probs = [(10, 12, 2.0, 1.0, 7), (7, 8, 1.0, 1.0, 4)]
+    parts = packed_rhs(probs, 509)
+    B = make_batch(pd, probs)
+    x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+    rc, infos = pd.pd_batch_cg_solve(B, pd.PD_FP64, dev(np.concatenate(parts)), x, 1e-12, 200000)
+    print(f"  batch: {infos[0]}", flush=True)
+    assert rc == pd.PD_OK
+    assert infos[0]["outer_iters"] >= 2 and infos[0]["restarts"] >= 1
+    assert infos[0]["rel_res_true"] <= 1e-12
+    nx, ny, Lx, Ly, N = probs[0]
+    g = Grid((nx, ny), (Lx, Ly), N)
+    ref = FastDiag(g).solve(layout.blocked_to_tensor(parts[0], (nx, ny), N + 1), 0.0, DT)
+    got = layout.blocked_to_tensor(x.cpu().numpy()[B.offsets[0]:B.offsets[1]], (nx, ny), N + 1)
+    assert mass_norm(g, got - ref) <= 1e-10 * mass_norm(g, ref)
+    B.close()
+    ctx = pd.pd_setup(2, (nx, ny), (Lx, Ly), N, DT, 0.6, 0.0)
+    xs = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+    info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(parts[0]), xs, 1e-12, 200000)
+    print(f"  single: {info}", flush=True)
+    ctx.close()
+    assert info["status"] == pd.PD_OK and info["outer_iters"] >= 2 and info["restarts"] >= 1
+    assert info["rel_res_true"] <= 1e-12
+
+
 @pytest.mark.parametrize("prec", [0, 2])
 def test_batch_graph_equals_eager(pd, prec):
     """Replaying the captured graph and enqueueing the same kernels one by one give bit-identical

@@ -398,15 +398,18 @@ def test_setup_rejects_too_many_3d_columns(pd):
     assert e.value.code == pd.PD_EINVAL
 
 
-@pytest.mark.parametrize("dim,cells,N,dt,m", [(2, (256, 256), 6, 5e-4, 4), (3, (64, 64, 64), 4, 1e-3, 2)])
-def test_full_size_cg_iterates_in_bench_configuration(pd, dim, cells, N, dt, m):
+@pytest.mark.parametrize("dim,cells,N,dt,m,one", [(2, (256, 256), 6, 5e-4, 4, 0),
+                                                   (2, (256, 256), 6, 5e-4, 5, 1),
+                                                   (3, (64, 64, 64), 4, 1e-3, 2, 0)])
+def test_full_size_cg_iterates_in_bench_configuration(pd, dim, cells, N, dt, m, one):
     """The fused CG kernels at full size in the launch configuration the benchmark times (256^2
     N = 6: three tiles per workgroup with the next tile's loads in flight; 64^3 N = 4: whole-column
-    z segments), with the deferred x update: after m FP64 iterations from x0 = 0 the iterate
+    z segments), with the deferred x update (and, at 256^2, also in the opt-in one-kernel form at
+    its own shape, four tiles per workgroup): after m FP64 iterations from x0 = 0 the iterate
     equals the oracle's plain CG iterate computed with the matrix-free oracle operator."""
     import torch
     from scipy.sparse.linalg import LinearOperator
-    print(f"full-size CG iterates dim={dim} cells={cells} N={N} m={m}", flush=True)
+    print(f"full-size CG iterates dim={dim} cells={cells} N={N} m={m} one={one}", flush=True)
     L = (1.0,) * dim
     g = Grid(cells, L, N)
     rng = np.random.default_rng(81)
@@ -416,6 +419,7 @@ def test_full_size_cg_iterates_in_bench_configuration(pd, dim, cells, N, dt, m):
     x_ref, it, _ = cg(A, bt.reshape(-1), 1e-30, m)
     assert it == m
     ctx = pd.pd_setup(dim, cells, L, N, dt, 0.6, 1e-3)
+    pd.pd_configure(ctx, pd.PD_CFG_ONE_KERNEL, one)
     x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
     info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, dev(layout.tensor_to_blocked(bt, cells, g.n)), x,
                           1e-30, m)
