@@ -38,6 +38,7 @@ struct ApplyArgs {
   double* fout;
   int npart;
   int first;
+  int remap;          // single-problem 2D launch: 1 = XCD-contiguous tile ranges (xcd_remap)
 };
 
 __device__ __forceinline__ int wrapi(int i, int m) {
