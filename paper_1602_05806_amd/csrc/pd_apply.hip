@@ -31,20 +31,20 @@
 
 namespace pdk {
 
-// Single problem: persistent workgroups, each over the contiguous tile range
-// [lw * kz, lw * kz + kz) with lw the XCD-contiguous workgroup index (neighbouring tiles, whose
-// halos overlap, share one XCD's L2) or, for a launch of one tile per workgroup that the device
-// holds at once (a.remap = 0), the dispatch order itself, which deals neighbouring tiles to
-// different XCDs: 256^2 N = 6 FP32 28.6 against 30.3 us, 256^2 N = 3 FP64 16.7 against 17.5 us;
-// with several tiles per workgroup or several waves of workgroups the XCD-contiguous order is as
-// fast or faster (256^2 N = 6 FP64, 3 tiles: 44.2 against 44.5 us).
+// Single problem: persistent workgroups; workgroup lw takes tiles lw, lw + G, lw + 2G, ... (G
+// workgroups), so that at every step the workgroups of one XCD (lw is the XCD-contiguous index)
+// hold a contiguous band of tiles whose halos they share in that XCD's L2, and the band of the
+// next step is prefetched during the current one. 256^2 N = 6 FP64, 3 tiles per workgroup:
+// 40.9 us per launch against 44.2 us with each workgroup taking 3 consecutive tiles; N = 8:
+// 63.3 against 66.1 us. For a launch of one tile per workgroup that the device holds at once
+// (a.remap = 0) lw is the dispatch order itself, which deals neighbouring tiles to different
+// XCDs: 256^2 N = 6 FP32 28.6 against 30.3 us, 256^2 N = 3 FP64 16.7 against 17.5 us (with
+// several tiles per workgroup or several waves the XCD-contiguous index is as fast or faster).
 template <typename T, int N, int V, int FUSE, int PF>
 __global__ __launch_bounds__(256) void k_apply2d(ApplyArgs<T> a, Blk<T, N> B) {
   const unsigned lw = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int ntiles = a.ntx * a.nty;
-  const int t_begin = (int)lw * a.kz;           // kz = tiles per workgroup in 2D
-  const int t_end = min(t_begin + a.kz, ntiles);
-  apply2d_body<T, N, V, FUSE, PF>(a, B, t_begin, t_end, blockIdx.x);
+  apply2d_body<T, N, V, FUSE, PF>(a, B, (int)lw, ntiles, (int)gridDim.x, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ 3D z-marching kernel

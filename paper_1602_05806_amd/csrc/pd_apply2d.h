@@ -113,10 +113,11 @@ struct Tile2D {
 
 // 2D: LDS holds the tile and its face halos as a (TX+2) x (TY+2) box of cells (corners unused),
 // box cell (bi, bj) = tile cell (bi-1, bj-1). Box row bj is one contiguous run of cells in global
-// memory unless it crosses the periodic seam, so staging is a flat copy per row.
+// memory unless it crosses the periodic seam, so staging is a flat copy per row. The workgroup
+// processes tiles t_begin, t_begin + t_stride, ... below t_end.
 template <typename T, int N, int V, int FUSE, int PF>
 __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T, N>& B,
-                                             int t_begin, int t_end, int slot) {
+                                             int t_begin, int t_end, int t_stride, int slot) {
   constexpr bool RU = FUSE == 3;                // residual update folded in
   using TL = Tile2D<T, N, V>;
   constexpr int n = N + 1, NC = n * n, TX = TL::TX, TY = TL::TY, NT = TX * TY;
@@ -207,7 +208,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
     }
   }
   double dot = 0.0, gam = 0.0, nu = 0.0, rr = 0.0;   // RU: <r, A p>, <A p, A p>, <r, r>
-  for (int tile = t_begin; tile < t_end; ++tile) {
+  for (int tile = t_begin; tile < t_end; tile += t_stride) {
     const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
     // registers -> LDS (p = r + beta p_old formed here; owned cells also stored to global)
 #pragma unroll
@@ -248,7 +249,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
     // x-lines, half before the y-lines (issuing all at once stalls this wave's x-lines while the
     // memory pipeline drains)
     constexpr int HALF = (TY + 2) / 2;
-    if (PF && tile + 1 < t_end) stage_load(tile + 1, 0, HALF);
+    if (PF && tile + t_stride < t_end) stage_load(tile + t_stride, 0, HALF);
 
     // x-lines: (cell c, l2); nodes l1 = 0..N
     for (int L = tid; L < NT * n; L += 256) {
@@ -266,7 +267,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
       line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + l2 * n + l1] = wgt * v; });
     }
     __syncthreads();
-    if (PF && tile + 1 < t_end) stage_load(tile + 1, HALF, TY + 2);
+    if (PF && tile + t_stride < t_end) stage_load(tile + t_stride, HALF, TY + 2);
 
     // y-lines: (cell c, l1); nodes l2 = 0..N; final values are stored here
     for (int L = tid; L < NT * n; L += 256) {
@@ -317,7 +318,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
         }
       }
     }
-    if (!PF && tile + 1 < t_end) stage_load(tile + 1, 0, TY + 2);
+    if (!PF && tile + t_stride < t_end) stage_load(tile + t_stride, 0, TY + 2);
   }
   if (RU) {
     double s4[4] = {dot, gam, nu, rr};

@@ -197,7 +197,7 @@ __global__ __launch_bounds__(256) void k_apply2d_batch(BatchIter it, const int* 
   a.sigpart = it.sig + P.sig_off;
   a.xsol = FUSE == 2 ? xsol + P.dof_off : nullptr;
   const int tile = b - toff[g];
-  apply2d_body<T, N, V, FUSE, 0>(a, B, tile, tile + 1, tile);
+  apply2d_body<T, N, V, FUSE, 0>(a, B, tile, tile + 1, 1, tile);
 }
 
 // ---- streaming passes over the listed problems (see launch_stream_batch)
