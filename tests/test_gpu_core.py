@@ -336,6 +336,37 @@ def test_full_size_apply_sampled(pd):
         ctx.close()
 
 
+@pytest.mark.parametrize("cells,N", [((23, 19), 3), ((17, 30), 6), ((41, 9), 1)])
+def test_tiles_per_workgroup_shapes_agree(pd, cells, N):
+    """Workgroups taking several tiles strided over the grid (PD_CFG_TILES_PER_WG = 2, 3, 5 on
+    ragged tile counts, so that some workgroups get one tile fewer) give the same operator apply
+    bit for bit as one tile per workgroup, and the same CG iterate after 9 iterations up to the
+    block order of the dot-product partial sums."""
+    import torch
+    print(f"tiles per workgroup cells={cells} N={N}", flush=True)
+    L = (1.0, 1.0)
+    g = Grid(cells, L, N)
+    ctx = pd.pd_setup(2, cells, L, N, 5e-4, 0.6, 1e-3)
+    rng = np.random.default_rng(17)
+    xin = dev(rng.standard_normal(g.ndof))
+    b = dev(synthetic.random_rhs(18, g.ndof))
+    out = {}
+    for per in (1, 2, 3, 5):
+        pd.pd_configure(ctx, pd.PD_CFG_TILES_PER_WG, per)
+        y = torch.empty(g.ndof, dtype=torch.float64, device="cuda")
+        pd.pd_apply(ctx, 0, pd.PD_FP64, xin, y)
+        x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+        info = pd.pd_cg_solve(ctx, 0, pd.PD_FP64, b, x, 1e-30, 9)
+        assert info["iters"] == 9
+        out[per] = (host(y), host(x))
+    ctx.close()
+    y1, x1 = out[1]
+    for per in (2, 3, 5):
+        y, x = out[per]
+        assert np.array_equal(y, y1)
+        assert np.linalg.norm(x - x1) <= 1e-12 * np.linalg.norm(x1)
+
+
 def test_large_2d_grids(pd):
     """2D grids with more tiles than one launch holds workgroups (2050^2 N = 0: 66049 tiles of
     8x8 cells; 1460^2 N = 6: 66795 tiles of 8x4) run with several tiles per workgroup: sampled
