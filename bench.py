@@ -242,12 +242,11 @@ def bench_adjoint(args, pd, torch):
     field.normalise(cfg["vmax"])
     U = field.eval(synthetic.staggered_coords(cells, cfg["lengths"], xi))
     u0 = [torch.tensor(synthetic.tensor_to_blocked(x, cells, N + 1), device="cuda") for x in U]
-    W = ag.quadrature_weights(ctx)
     steps, every = cfg["steps"], cfg["checkpoint"]
 
     def gradient():
         ur = [x.clone().requires_grad_(True) for x in u0]
-        loss = ag.kinetic_energy(ctx, ag.Rollout.apply(ctx, steps, every, *ur), W)
+        loss = ag.kinetic_energy(ctx, ag.Rollout.apply(ctx, steps, every, *ur))
         loss.backward()
         return float(loss.detach()), [x.grad for x in ur]
 
@@ -273,9 +272,9 @@ def bench_adjoint(args, pd, torch):
         eps = 1e-6 * unorm / float(torch.sqrt(sum((x * x).sum() for x in v)))
         with torch.no_grad():
             fp = float(ag.kinetic_energy(ctx, ag.Rollout.apply(
-                ctx, steps, every, *[a + eps * b for a, b in zip(u0, v)]), W))
+                ctx, steps, every, *[a + eps * b for a, b in zip(u0, v)])))
             fm = float(ag.kinetic_energy(ctx, ag.Rollout.apply(
-                ctx, steps, every, *[a - eps * b for a, b in zip(u0, v)]), W))
+                ctx, steps, every, *[a - eps * b for a, b in zip(u0, v)])))
         f = (fp - fm) / (2 * eps)
         gv = float(sum((a * b).sum() for a, b in zip(grad, v)))
         fd.append(abs(gv - f) / abs(f))

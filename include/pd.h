@@ -123,8 +123,8 @@ int pd_apply(pd_ctx* ctx, int op, int prec, const void* x, void* y, void* hip_st
  * is above but within 16x, it replaces the recurrence residual and the iterations continue (up
  * to 8 times, while each replacement at least halves it; a larger gap is the FP64 rounding
  * floor of b - A x and ends the solve with PD_OK, rel_res_true reporting it).
- * PD_FP32_REFINE64 stops on the recomputed FP64 residual. Synchronises with the stream at exit;
- * info may be NULL.
+ * PD_FP32_REFINE64 stops on the recomputed FP64 residual. b and x must not alias (PD_EINVAL).
+ * Synchronises with the stream at exit; info may be NULL.
  * Returns PD_OK, PD_ENOCONV (maxit reached) or PD_EBREAKDOWN. */
 int pd_cg_solve(pd_ctx* ctx, int op, int prec, const void* b, void* x, double rtol, int maxit,
                 pd_solve_info* info, void* hip_stream);
@@ -193,11 +193,22 @@ int pd_convect_adjoint(pd_ctx* ctx, void* const um[3], void* const ubar[3], void
 int pd_step_adjoint(pd_ctx* ctx, void* const u[3], void* const ubar[3], pd_solve_info info[4],
                     void* hip_stream);
 
+/* Mean kinetic energy of a dual velocity field, the K = (1/|Omega|) int |v|^2 / 2 of the 3D
+ * Taylor-Green subsection of Section 2.4 (the loss of the adjoint rollout): every component is
+ * integrated by Gauss-Legendre quadrature on its own dual grid, so on the uniform grid
+ * K = (1 / (2 ncells)) sum_d sum_i W_i u_d,i^2 with W_i the product of the GL weights of node i.
+ * u[0..dim-1]: FP64 dual components (read only). *energy (host) receives K. grad may be NULL;
+ * otherwise grad[d] (FP64, dual layout of component d, must not alias any u[e]) is overwritten
+ * with gscale * dK/du_d = gscale W u_d / ncells, the cotangent of the velocity for an incoming
+ * loss cotangent gscale (finite). Synchronises. */
+int pd_kinetic_energy(pd_ctx* ctx, void* const u[3], double gscale, void* const grad[3],
+                      double* energy, void* hip_stream);
+
 /* Settings used by pd_step and the timing hooks (key, value):
  *   PD_CFG_STEP_PREC     PD_FP64 (default) or PD_FP32_REFINE64 for the step's solves
  *   PD_CFG_P_RTOL        pressure tolerance in pd_step (default 1e-10)
  *   PD_CFG_V_RTOL        viscous tolerance in pd_step (default 1e-12)
- *   PD_CFG_MAXIT         iteration cap for the step's solves (default 100000)
+ *   PD_CFG_MAXIT         iteration cap for the step's solves (default 100000, at most 2^30)
  *   PD_CFG_CONVECTION    1 (default) = explicit convection on, 0 = off (unsteady Stokes step)
  *   PD_CFG_RU_FACTOR     PD_FP32_REFINE64: the FP32 residual is replaced by the FP64 residual
  *                        b - A x each time it has dropped by this factor (default 0.1)
@@ -205,9 +216,12 @@ int pd_step_adjoint(pd_ctx* ctx, void* const u[3], void* const ubar[3], pd_solve
  *                        inside solves carries start/stop HIP events (see pd_timing; 1 = every
  *                        launch; events add a few microseconds per timed launch), 0 (default) =
  *                        off
- *   PD_CFG_CHECK_EVERY   convergence poll interval of the solve loop in iterations (default 32)
- *   PD_CFG_KZ            3D operator kernel: planes per column segment (0 = automatic)
- *   PD_CFG_TILES_PER_WG  2D operator kernel: tiles per persistent workgroup (0 = automatic)
+ *   PD_CFG_CHECK_EVERY   convergence poll interval of the solve loop in iterations (default 32,
+ *                        at most 2^20)
+ *   PD_CFG_KZ            3D operator kernel: planes per column segment (0 = automatic, at most
+ *                        2^30)
+ *   PD_CFG_TILES_PER_WG  2D operator kernel: tiles per persistent workgroup (0 = automatic, at
+ *                        most 2^30)
  *   PD_CFG_PREFETCH      1 (default) = the operator kernel prefetches the next tile (2D) or the
  *                        next plane's halo (3D) into registers during compute, 0 = no prefetch
  *   PD_CFG_TILE_VARIANT  2D operator kernel tile shape: 0 (default) = the largest tile of cells

@@ -16,7 +16,8 @@ respect to the dual component U_d is (cell volume / domain volume) W U_d (W: GL 
 import numpy as np
 
 from .operators import apply_along, l2_dual_to_main_1d, l2_main_to_dual_1d
-from .step import StepOracle, dual_to_main, main_to_dual, convective_rate, kinetic_energy
+from .step import (StepOracle, dual_to_main, main_to_dual, convective_rate, kinetic_energy,
+                   kinetic_energy_grad)
 
 
 def _ax(grid, d):
@@ -233,8 +234,7 @@ def rollout_gradient(grid, U0, steps, dt, theta, nu, convection=True):
         U, P = r["U_new"], r["P_new"]
         states.append(U)
     loss = kinetic_energy(grid, U)
-    scale = float(np.prod(grid.h)) / float(np.prod(grid.lengths))
-    Ubar = [scale * adj.Wt * U[d] for d in range(grid.dim)]
+    Ubar = kinetic_energy_grad(grid, U)
     for n in range(steps - 1, -1, -1):
         Ubar = adj.vjp(states[n], Ubar, convection=convection)
     return loss, Ubar

@@ -219,6 +219,21 @@ def apply_operator(grid, X, alpha, beta, absolute=False):
     return out
 
 
+def div_rhs_apply(grid, U):
+    """b = sum_d B_d U_d (eq. LOpressure) without assembling the d-dimensional B_d: along
+    direction d the 1D D_d^T / h_d, along every other direction the diagonal 1D mass. U: list of
+    dual components in tensor layout."""
+    b = np.zeros(grid.shape())
+    for d in range(grid.dim):
+        T = apply_along(grad_1d(grid.cells[d], grid.N).T.tocsr(), np.asarray(U[d], dtype=np.float64),
+                        grid.dim - 1 - d) / grid.h[d]
+        for e in range(grid.dim):
+            if e != d:
+                T = apply_along(mass_1d(grid.cells[e], grid.N), T, grid.dim - 1 - e)
+        b = b + T
+    return b
+
+
 def project_null(grid, X, Zs):
     """v <- v - Z Z^T v with Z = kron of the per-direction orthonormal bases Zs[d].
 

@@ -172,5 +172,18 @@ def kinetic_energy(grid, U):
     return 0.5 * sum(float(np.sum(Wt * U[d] ** 2)) for d in range(grid.dim)) * cellvol / vol
 
 
+def kinetic_energy_grad(grid, U):
+    """Gradient of kinetic_energy with respect to each dual component (Euclidean, per DoF):
+    (cell volume / domain volume) W U_d, the quadrature weights times the field."""
+    w = grid.tab.w
+    scale = float(np.prod(grid.h)) / float(np.prod(grid.lengths))
+    Wt = np.ones(grid.shape())
+    for d in range(grid.dim):
+        shp = [1] * grid.dim
+        shp[grid.dim - 1 - d] = -1
+        Wt = Wt * np.tile(w, grid.cells[d]).reshape(shp)
+    return [scale * Wt * U[d] for d in range(grid.dim)]
+
+
 __all__ = ["Grid", "StepOracle", "dual_to_main", "main_to_dual", "convective_rate", "rk3",
-           "kinetic_energy"]
+           "kinetic_energy", "kinetic_energy_grad"]

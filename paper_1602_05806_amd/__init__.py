@@ -38,7 +38,7 @@ EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "
             "pd_cg_solve", "pd_rhs_div", "pd_project_velocity", "pd_project_null",
             "pd_l2_project", "pd_convect", "pd_step", "pd_configure", "pd_timing",
             "pd_l2_project_adjoint", "pd_rhs_div_adjoint", "pd_project_velocity_adjoint",
-            "pd_convect_adjoint", "pd_step_adjoint",
+            "pd_convect_adjoint", "pd_step_adjoint", "pd_kinetic_energy",
             "pd_batch_setup", "pd_batch_destroy", "pd_batch_last_error", "pd_batch_layout",
             "pd_batch_variants", "pd_batch_configure", "pd_batch_cg_solve"]
 
@@ -84,6 +84,8 @@ _lib.pd_project_velocity_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _vp]
 _lib.pd_convect_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]
 _lib.pd_step_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.POINTER(pd_solve_info), _vp]
+_lib.pd_kinetic_energy.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_double, ctypes.POINTER(_vp),
+                                   ctypes.POINTER(ctypes.c_double), _vp]
 _lib.pd_batch_setup.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                 ctypes.c_double, ctypes.c_uint, _vp]
@@ -299,6 +301,16 @@ def pd_step_adjoint(ctx, u, ubar, stream=None):
                               ctypes.c_void_p(_stream(stream)))
     _check(ctx, rc, allow=(PD_ENOCONV, PD_EBREAKDOWN))
     return [i.as_dict() for i in info]
+
+
+def pd_kinetic_energy(ctx, u, grad=None, gscale=1.0, stream=None):
+    """Mean kinetic energy of the dual velocity u (returned as a float); with grad (dim FP64
+    tensors) also grad[d] = gscale * dK/du_d."""
+    e = ctypes.c_double()
+    g = _vec3(ctx, grad) if grad is not None else None
+    _check(ctx, _lib.pd_kinetic_energy(ctx.handle, _vec3(ctx, u), float(gscale), g,
+                                       ctypes.byref(e), ctypes.c_void_p(_stream(stream))))
+    return e.value
 
 
 def pd_configure(ctx, key, value):

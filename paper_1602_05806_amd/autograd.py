@@ -12,10 +12,12 @@ differentiated.
                                            from its checkpoint and runs the adjoint in reverse
   kinetic_energy(ctx, u)                   the mean kinetic energy (1/|Omega|) int |v|^2 / 2 with
                                            each component integrated by GL quadrature on its grid
+                                           (pd_kinetic_energy; its backward is the library's
+                                           cotangent W u / ncells)
 """
 import torch
 
-from . import pd_nodes, pd_step, pd_step_adjoint, PD_OK, PdError
+from . import pd_kinetic_energy, pd_step, pd_step_adjoint, PD_OK, PdError
 
 
 # solver work done through this module (forward steps, recomputed steps, adjoint steps)
@@ -98,17 +100,24 @@ class Rollout(torch.autograd.Function):
         return (None, None, None, *ubar)
 
 
-def quadrature_weights(ctx, device="cuda"):
-    """Per-DoF GL weight products (the diagonal of M^{xyz}) in the element-blocked layout."""
-    _, w = pd_nodes(ctx)
-    wt = torch.tensor(w, dtype=torch.float64, device=device)
-    node = wt
-    for _ in range(ctx.dim - 1):
-        node = torch.outer(wt, node).reshape(-1)   # slower directions outside, x fastest
-    return node.repeat(ctx.ncells)
+class KineticEnergy(torch.autograd.Function):
+    """Loss K(U) of pd_kinetic_energy; its backward asks the library for gscale * dK/dU."""
+
+    @staticmethod
+    def forward(fctx, ctx, *u):
+        fctx.pd = ctx
+        fctx.save_for_backward(*u)
+        e = pd_kinetic_energy(ctx, [x.detach().contiguous() for x in u])
+        return torch.tensor(e, dtype=torch.float64, device=u[0].device)
+
+    @staticmethod
+    def backward(fctx, g):
+        u = [x.detach().contiguous() for x in fctx.saved_tensors]
+        grads = [torch.empty_like(x) for x in u]
+        pd_kinetic_energy(fctx.pd, u, grads, float(g))
+        return (None, *grads)
 
 
-def kinetic_energy(ctx, u, weights=None):
-    """(1/|Omega|) int |v|^2 / 2 on a uniform grid: 0.5 / ncells * sum_d sum W u_d^2."""
-    W = quadrature_weights(ctx, u[0].device) if weights is None else weights
-    return 0.5 / ctx.ncells * sum((W * x * x).sum() for x in u)
+def kinetic_energy(ctx, u):
+    """(1/|Omega|) int |v|^2 / 2 of the dual velocity u, differentiable (pd_kinetic_energy)."""
+    return KineticEnergy.apply(ctx, *u)

@@ -338,7 +338,7 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
   int rc = plain_apply(c, op, false, x, c->q64, s);
   if (rc) return rc;
   PD_HIP(c, pdk::launch_residual(b, c->q64, c->r64, c->ndof, c->rhopart, s));
-  PD_HIP(c, pdk::launch_state_set(c->st, maxit, rtol * rtol * bnorm * bnorm, s));
+  PD_HIP(c, pdk::launch_state_set(c->st, maxit, rtol * rtol * bnorm * bnorm, 0, s));
   if ((rc = cg_prepare(c, &R))) return rc;
   CgState fin;
   inf->outer_iters = 0;
@@ -376,7 +376,7 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
       PD_HIP(c, hipMemcpyAsync(c->r64b, c->r64, c->ndof * sizeof(double),
                                hipMemcpyDeviceToDevice, s));
     R.kfirst = R.k;
-    PD_HIP(c, pdk::launch_state_set(c->st, maxit, rtol * rtol * bnorm * bnorm, s));
+    PD_HIP(c, pdk::launch_state_set(c->st, maxit, rtol * rtol * bnorm * bnorm, R.k, s));
   }
   cg_collect_timing(c, R);
   inf->iters = R.k;
@@ -427,7 +427,7 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
   R.timed = timed;
   PD_HIP(c, pdk::launch_zero(true, c->d32, n, s));
   PD_HIP(c, pdk::launch_to_f32_dot(c->r64, c->r32, n, 1.0 / scale, c->rhopart, s));
-  PD_HIP(c, pdk::launch_state_set(c->st, maxit, inner_tol2(1.0), s));
+  PD_HIP(c, pdk::launch_state_set(c->st, maxit, inner_tol2(1.0), 0, s));
   if ((rc = cg_prepare(c, &R))) return rc;
   double ref = 1.0;                             // scaled residual norm at the last replacement
   double best = 1.0;                            // smallest scaled FP64 residual so far
@@ -499,7 +499,7 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
     PD_HIP(c, pdk::launch_to_f32_dot(c->r64, r32k, n, 1.0 / scale, R.rho[R.k & 1], s));
     R.kfirst = R.k;
     ref = res / scale;
-    PD_HIP(c, pdk::launch_state_set(c->st, maxit, inner_tol2(ref), s));
+    PD_HIP(c, pdk::launch_state_set(c->st, maxit, inner_tol2(ref), R.k, s));
   }
   cg_collect_timing(c, R);
   inf->iters = R.k;
@@ -512,6 +512,7 @@ int solve(pd_ctx* c, int op, int prec, const double* b_in, double* x, double rto
   if (prec != PD_FP64 && prec != PD_FP32_REFINE64)
     return fail(c, PD_EINVAL, "pd_cg_solve precision must be PD_FP64 or PD_FP32_REFINE64");
   if (!b_in || !x) return fail(c, PD_EINVAL, "null array");
+  if ((const void*)b_in == (const void*)x) return fail(c, PD_EINVAL, "b and x must not alias");
   if (!(rtol > 0.0)) return fail(c, PD_EINVAL, "rtol must be > 0");
   if (maxit < 0) return fail(c, PD_EINVAL, "maxit must be >= 0");
   c->last_stream = s;
@@ -1246,8 +1247,42 @@ int pd_step_adjoint(pd_ctx* c, void* const u[3], void* const ubar[3], pd_solve_i
   return PD_OK;
 }
 
+int pd_kinetic_energy(pd_ctx* c, void* const u[3], double gscale, void* const grad[3],
+                      double* energy, void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!u || !energy) return fail(c, PD_EINVAL, "null argument");
+  if (!std::isfinite(gscale)) return fail(c, PD_EINVAL, "gscale must be finite");
+  for (int d = 0; d < c->dim; ++d) {
+    if (!u[d]) return fail(c, PD_EINVAL, "null velocity component");
+    if (grad && !grad[d]) return fail(c, PD_EINVAL, "null gradient component");
+    if (grad)
+      for (int e = 0; e < c->dim; ++e)
+        if (grad[d] == u[e]) return fail(c, PD_EINVAL, "grad must not alias u");
+  }
+  hipStream_t s = S(hip_stream);
+  c->last_stream = s;
+  const double* uu[3] = {nullptr, nullptr, nullptr};
+  double* gg[3] = {nullptr, nullptr, nullptr};
+  for (int d = 0; d < c->dim; ++d) {
+    uu[d] = (const double*)u[d];
+    if (grad) gg[d] = (double*)grad[d];
+  }
+  // (1/|Omega|) int |v|^2/2 with |cell|/|Omega| = 1/ncells on the uniform grid
+  const double inv_cells = 1.0 / (double)c->ncells;
+  PD_HIP(c, pdk::launch_energy(c->dim, c->N, c->tab.w, uu, grad ? gg : nullptr,
+                               gscale * inv_cells, c->ncells, c->tmppart, s));
+  PD_HIP(c, pdk::launch_finalize(c->tmppart, (int)pdk::stream_grid(c->ndof), c->st2,
+                                 pdk::FIN_AUX, s));
+  CgState h;
+  int rc = read_state(c, c->st2, &h, s);
+  if (rc) return rc;
+  *energy = 0.5 * inv_cells * h.aux;
+  return PD_OK;
+}
+
 int pd_configure(pd_ctx* c, int key, double v) {
   if (!c) return PD_EINVAL;
+  constexpr double kMaxIntSetting = 1 << 30;   // integer settings are converted with (int)
   switch (key) {
     case PD_CFG_STEP_PREC:
       if (v != PD_FP64 && v != PD_FP32_REFINE64) return fail(c, PD_EINVAL, "bad step precision");
@@ -1262,7 +1297,7 @@ int pd_configure(pd_ctx* c, int key, double v) {
       c->v_rtol = v;
       break;
     case PD_CFG_MAXIT:
-      if (!(v >= 0)) return fail(c, PD_EINVAL, "maxit must be >= 0");
+      if (!(v >= 0 && v <= kMaxIntSetting)) return fail(c, PD_EINVAL, "maxit must be in [0, 2^30]");
       c->maxit = (int)v;
       break;
     case PD_CFG_CONVECTION:
@@ -1277,15 +1312,15 @@ int pd_configure(pd_ctx* c, int key, double v) {
       c->timing = (int)v;
       break;
     case PD_CFG_CHECK_EVERY:
-      if (!(v >= 1)) return fail(c, PD_EINVAL, "check interval must be >= 1");
+      if (!(v >= 1 && v <= 1 << 20)) return fail(c, PD_EINVAL, "check interval must be in [1, 2^20]");
       c->check_every = (int)v;
       break;
     case PD_CFG_KZ:
-      if (!(v >= 0)) return fail(c, PD_EINVAL, "planes per segment must be >= 0");
+      if (!(v >= 0 && v <= kMaxIntSetting)) return fail(c, PD_EINVAL, "planes per segment must be in [0, 2^30]");
       c->kz = (int)v;
       break;
     case PD_CFG_TILES_PER_WG:
-      if (!(v >= 0)) return fail(c, PD_EINVAL, "tiles per workgroup must be >= 0");
+      if (!(v >= 0 && v <= kMaxIntSetting)) return fail(c, PD_EINVAL, "tiles per workgroup must be in [0, 2^30]");
       c->tiles_per_wg = (int)v;
       break;
     case PD_CFG_PREFETCH:

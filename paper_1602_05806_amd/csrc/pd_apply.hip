@@ -67,8 +67,9 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   __shared__ T ys[NT * NC];
   __shared__ int hbase[NS];     // in-plane cell index (j*nx + i, wrapped) of every halo slot
   // launches queued after the run stopped exit before loading anything
+  const int kit = FUSE ? (a.kbase ? *a.kbase + a.k : a.k) : 0;
   if (FUSE) {
-    if (a.st->done) return;
+    if (!apply_may_run(a.st, kit)) return;
   }
   const T* __restrict__ xg = a.x;
   const T* __restrict__ pg = a.pold;
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
       if (FUSE == 2) xc[l3] = a.xsol[bc + l3 * NP];
     }
     if (FUSE) {
-      const int k = a.kbase ? *a.kbase + a.k : a.k;
+      const int k = kit;
       const IterScalars sc = iteration_scalars<NTH>(a.st, k, a.rho_cur, a.nrho, blockIdx.x == 0);
       if (sc.stop) return;
       beta = (T)sc.beta;

@@ -128,8 +128,9 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
   __shared__ T xs[(TY + 2) * BX * NC];
   __shared__ T ys[NT * NC];
   // launches queued after the run stopped exit before loading anything
+  const int kit = FUSE ? (a.kbase ? *a.kbase + a.k : a.k) : 0;
   if (FUSE) {
-    if (a.st->done) return;
+    if (!apply_may_run(a.st, kit)) return;
   }
   const T* __restrict__ xg = a.x;
   const T* __restrict__ pg = a.pold;
@@ -197,8 +198,8 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
     xupd = true;
     xalpha = (T)sc.alpha;
   } else if (FUSE) {
-    const int k = a.kbase ? *a.kbase + a.k : a.k;
-    const IterScalars sc = iteration_scalars<256>(a.st, k, a.rho_cur, a.nrho, t_begin == 0);
+    const int k = kit;
+    const IterScalars sc = iteration_scalars<256>(a.st, k, a.rho_cur, a.nrho, t_begin == 0, RU);
     if (sc.stop) return;
     beta = (T)sc.beta;
     if (FUSE == 2) {

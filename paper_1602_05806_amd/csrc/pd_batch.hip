@@ -37,9 +37,13 @@ __device__ __forceinline__ Slot slot_of(const BatchIter& it, const int* __restri
   return s;
 }
 
-// iterating kernels: the problem runs this iteration in this launch's precision
-__device__ __forceinline__ bool iterates(const BatchIter& it, const CgState* st) {
-  return !st->done && (it.want < 0 || st->mode64 == it.want);
+// iterating kernels: the problem runs iteration k in this launch's precision. The stamps are
+// written by the other kernel of the iteration, the chunk-end decision or the state reset, never
+// by another block of the reading launch (see CgState::run_a).
+__device__ __forceinline__ bool iterates(const BatchIter& it, const CgState* st, int k,
+                                         bool apply) {
+  if (st->fin || !(it.want < 0 || st->mode64 == it.want)) return false;
+  return apply ? apply_may_run(st, k) : st->run_u == k;
 }
 
 // other kernels: skip finished problems when asked, and problems of the other precision.
@@ -66,8 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_update_batch(BatchIter it, const T* 
   const Slot sl = slot_of(it, it.upd_off, blockIdx.x);
   const BProb& P = it.probs[sl.j];
   CgState* st = it.st + sl.j;
-  if (!iterates(it, st)) return;
   const int k = *it.kbase + it.koff;
+  if (!iterates(it, st, k, false)) return;
   const long long n = P.ndof;
   const long long stride = (long long)P.nupd * kBlock;
   const long long i0 = (long long)sl.lb * kBlock + threadIdx.x;
@@ -116,6 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_update_batch(BatchIter it, const T* 
     if (sl.lb == 0) {
       st->alpha = alpha;
       st->xk = k;
+      st->run_a[(k + 1) & 1] = k + 1;
       // the direction of this iteration now exists: later iterations may build on it (no reader
       // of this flag runs during this kernel)
       st->fresh = 0;
@@ -169,7 +174,7 @@ __global__ __launch_bounds__(256) void k_apply2d_batch(BatchIter it, const int* 
   const BProb& P = it.probs[j];
   CgState* st = it.st + j;
   if (FUSE) {
-    if (!iterates(it, st)) return;
+    if (!iterates(it, st, *it.kbase + it.koff, true)) return;
   } else if (!serves(it, st)) {
     return;
   }
@@ -320,7 +325,13 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
     st->switched = 0;
     const int k = *it.kbase + it.koff;
     if (st->mode64) {
-      if (!st->done) return;
+      // still iterating: it may have sat out this chunk in a plan that listed it with the FP32
+      // problems (it switched at an earlier chunk end and the host has not re-captured yet), so
+      // its permission stamp is renewed for the next chunk's first iteration
+      if (!st->done) {
+        st->run_a[k & 1] = k;
+        return;
+      }
       if (st->status != 0) {           // out of iterations or broken down
         st->fin = 1;
         return;
@@ -369,6 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
       }
       st->idle += k - st->iter;
       st->done = 0;
+      st->run_a[k & 1] = k;
       st->switched = 1;
       return;
     }
@@ -414,6 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
         st->tol2 = t * t;
       }
       st->done = 0;
+      st->run_a[k & 1] = k;
       st->status = 0;
     }
   }
@@ -510,6 +523,9 @@ __global__ void k_state_init_batch(CgState* st, int count, int maxit, double tol
     s.xused = -1;
     s.idle = 0;
     s.outer = 0;
+    s.run_a[0] = 0;
+    s.run_a[1] = -1;
+    s.run_u = -1;
   }
 }
 

@@ -61,7 +61,23 @@ struct CgState {
   // flush kernel.
   int xk;
   int xused;
+  // Permission stamps of the iterating kernels. The apply kernel of iteration k runs iff
+  // run_a[k % 2] == k, the update kernel of iteration k iff run_u == k. Each stamp is written
+  // only by a launch that no reader of it overlaps: the apply kernel of iteration k publishes
+  // run_u = k (two-kernel form) or run_a[(k + 1) % 2] = k + 1 (one-kernel form), the update
+  // kernel of iteration k publishes run_a[(k + 1) % 2] = k + 1, each only when the run goes on;
+  // state resets and chunk-end resumes publish run_a for the iteration that starts next. So an
+  // early exit never depends on a word that another block of the same launch writes, and every
+  // block of a launch takes the same decision (the done flag above is for the host and the
+  // chunk-end logic only).
+  int run_a[2];
+  int run_u;
 };
+
+// The apply kernel of iteration k may run (see CgState::run_a).
+__device__ __forceinline__ bool apply_may_run(const CgState* st, int k) {
+  return st->run_a[k & 1] == k;
+}
 
 // Finalizers of the stand-alone reductions (dot kernel + single-block finalize kernel).
 enum Finalize : int {
@@ -150,10 +166,11 @@ struct IterScalars {
 };
 
 // `writer`: the one block of the problem that mirrors the scalars into st.
+// `one`: one kernel per iteration (the next launch is the apply kernel of iteration k + 1).
 template <int NT>
 __device__ __forceinline__ IterScalars iteration_scalars(CgState* st, int k,
                                                          const double* rho_cur, int nrho,
-                                                         bool writer) {
+                                                         bool writer, bool one = false) {
   IterScalars r;
   r.rho = sum_partials<NT>(rho_cur, nrho);
   const double rho_old = k > 0 ? st->rho_hist[(k + 1) & 1] : 0.0;
@@ -171,6 +188,10 @@ __device__ __forceinline__ IterScalars iteration_scalars(CgState* st, int k,
     if (r.stop) {
       st->status = status;
       st->done = 1;
+    } else if (one) {
+      st->run_a[(k + 1) & 1] = k + 1;
+    } else {
+      st->run_u = k;
     }
   }
   return r;
@@ -262,6 +283,7 @@ __device__ __forceinline__ FusedScalars fused_scalars(CgState* st, int k,
       st->done = 1;
     } else {
       st->xused = k - 1;
+      st->run_a[(k + 1) & 1] = k + 1;
     }
   }
   return f;

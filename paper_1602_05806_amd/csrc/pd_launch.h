@@ -79,8 +79,9 @@ hipError_t launch_axpby(double a, const double* x, double b, double* y, long lon
 hipError_t launch_zero(bool fp32, void* x, long long n, hipStream_t s);
 // reset CG state for a new solve: maxit, rtol (kept in aux for FIN_BNORM), done = 0
 hipError_t launch_state_init(CgState* st, int maxit, double rtol, hipStream_t s);
-// set tol2 / maxit of a CG run and clear its done flag (resumes a stopped run)
-hipError_t launch_state_set(CgState* st, int maxit, double tol2, hipStream_t s);
+// set tol2 / maxit of a CG run, clear its done flag and let iteration k0 run next (starts or
+// resumes a run at iteration k0)
+hipError_t launch_state_set(CgState* st, int maxit, double tol2, int k0, hipStream_t s);
 // r32 = (float)(inv * r64) with partials of <r32, r32> (residual replacement)
 hipError_t launch_to_f32_dot(const double* r64, float* r32, long long n, double inv,
                              double* partials, hipStream_t s);
@@ -89,6 +90,12 @@ hipError_t launch_flush_f32(double* x64, float* d32, long long n, double scale, 
 // y = W^{(x)d} x (nodal mass weights), FP64
 hipError_t launch_mass(int dim, int N, const double* w, const double* x, double* y,
                        long long ncells, hipStream_t s);
+
+// Kinetic energy of a dual velocity field: partials (stream_grid(ncells * (N+1)^dim) of them)
+// of sum_i W_i sum_d u_d,i^2; with g non-null also g[d] = gs * W * u[d].
+hipError_t launch_energy(int dim, int N, const double* w, const double* const u[3],
+                         double* const g[3], double gs, long long ncells, double* partials,
+                         hipStream_t s);
 
 // ---- null-space projection (pd_vec.hip)
 // corr = (P (x) P (x) P) (sum over cells of v) / ncells, then v -= corr per cell.

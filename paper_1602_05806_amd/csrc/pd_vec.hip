@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T
                                                       long long n, CgState* st, int k,
                                                       const double* __restrict__ sigpart, int nsig,
                                                       double* __restrict__ rho_next) {
-  if (st->done) return;
+  if (st->run_u != k) return;        // the apply kernel of iteration k stopped the run
   // The first J elements of this thread are loaded before sigma is reduced (latency overlap).
   constexpr int J = 4;
   const long long i0 = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -92,6 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(T* __restrict__ x, const T
     st->sigma = sigma;
     st->alpha = alpha;
     if (!XU) st->xk = k;
+    st->run_a[(k + 1) & 1] = k + 1;
   }
   const T a = (T)alpha;
   double s = 0.0;
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_vec(const T* __restrict__ 
   using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   constexpr int W = 16 / (int)sizeof(T);
   constexpr int J = 4;
-  if (st->done) return;
+  if (st->run_u != k) return;        // the apply kernel of iteration k stopped the run
   const long long nv = n / W;
   const V* __restrict__ qv = reinterpret_cast<const V*>(q);
   V* __restrict__ rv = reinterpret_cast<V*>(r);
@@ -158,6 +159,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update_vec(const T* __restrict__ 
     st->sigma = sigma;
     st->alpha = alpha;
     st->xk = k;
+    st->run_a[(k + 1) & 1] = k + 1;
   }
   const T a = (T)alpha;
   double s = 0.0;
@@ -260,12 +262,19 @@ __global__ void k_state_init(CgState* st, int maxit, double rtol) {
     st->xused = -1;
     st->idle = 0;
     st->outer = 0;
+    st->run_a[0] = 0;
+    st->run_a[1] = -1;
+    st->run_u = -1;
   }
 }
 
-// Set the stopping data of a CG run: tol2 (squared absolute residual bound), maxit; clears done.
-__global__ void k_state_set(CgState* st, int maxit, double tol2) {
+// Set the stopping data of a CG run: tol2 (squared absolute residual bound), maxit; clears done
+// and lets the apply kernel of iteration k0 (the run's next iteration) run.
+__global__ void k_state_set(CgState* st, int maxit, double tol2, int k0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->run_a[k0 & 1] = k0;
+    st->run_a[(k0 + 1) & 1] = -1;
+    st->run_u = -1;
     st->tol2 = tol2;
     st->maxit = maxit;
     st->done = 0;
@@ -321,6 +330,38 @@ __global__ __launch_bounds__(kBlock) void k_mass(W9 W, int n, const double* __re
     if (DIM == 3) wt *= W.w[l3];
     y[i] = wt * x[i];
   }
+}
+
+// Mean kinetic energy of a dual velocity field: partials of sum_i W_i sum_d u_d,i^2 (W_i = product
+// of the GL weights of node i); with g[0] non-null also g_d = gs W u_d for every component.
+struct Vel3 {
+  const double* u[3];
+  double* g[3];
+};
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_energy(W9 W, int n, Vel3 v, double gs, long long ncells,
+                                                   double* __restrict__ partials) {
+  const int NC = DIM == 3 ? n * n * n : n * n;
+  const long long tot = ncells * NC;
+  double s = 0.0;
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < tot;
+       i += (long long)gridDim.x * kBlock) {
+    const int l = (int)(i % NC);
+    const int l1 = l % n, l2 = (l / n) % n, l3 = l / (n * n);
+    double wt = W.w[l1] * W.w[l2];
+    if (DIM == 3) wt *= W.w[l3];
+    double q = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double ud = v.u[d][i];
+      q += ud * ud;
+      if (v.g[0]) v.g[d][i] = gs * wt * ud;
+    }
+    s += wt * q;
+  }
+  s = block_sum_all<kBlock>(s);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
 // ---- null-space projection: per-node sums over cells, then correction per node
@@ -472,8 +513,8 @@ hipError_t launch_state_init(CgState* st, int maxit, double rtol, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_state_set(CgState* st, int maxit, double tol2, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_set, dim3(1), dim3(64), 0, s, st, maxit, tol2);
+hipError_t launch_state_set(CgState* st, int maxit, double tol2, int k0, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_set, dim3(1), dim3(64), 0, s, st, maxit, tol2, k0);
   return hipGetLastError();
 }
 
@@ -487,6 +528,26 @@ hipError_t launch_to_f32_dot(const double* r64, float* r32, long long n, double 
 hipError_t launch_flush_f32(double* x64, float* d32, long long n, double scale, hipStream_t s) {
   hipLaunchKernelGGL(k_flush_f32, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, x64, d32, n,
                      scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(int dim, int N, const double* w, const double* const u[3],
+                         double* const g[3], double gs, long long ncells, double* partials,
+                         hipStream_t s) {
+  W9 W;
+  for (int i = 0; i < 9; ++i) W.w[i] = i <= N ? w[i] : 0.0;
+  const int n = N + 1;
+  const long long tot = ncells * (dim == 3 ? n * n * n : n * n);
+  Vel3 v;
+  for (int d = 0; d < 3; ++d) {
+    v.u[d] = d < dim ? u[d] : nullptr;
+    v.g[d] = (g && d < dim) ? g[d] : nullptr;
+  }
+  const unsigned G = stream_grid(tot);
+  if (dim == 3)
+    hipLaunchKernelGGL(k_energy<3>, dim3(G), dim3(kBlock), 0, s, W, n, v, gs, ncells, partials);
+  else
+    hipLaunchKernelGGL(k_energy<2>, dim3(G), dim3(kBlock), 0, s, W, n, v, gs, ncells, partials);
   return hipGetLastError();
 }
 

@@ -149,7 +149,7 @@ def _c5_like(pd, cells, steps, every, ndirs, tol, smooth):
     directions (seed 5000 + k), eps = 1e-6 ||U0|| / ||v||; solves to 1e-13. smooth: random
     Fourier fields of the initial velocity's family (wavenumbers <= 6); else N(0,1) per DoF."""
     import torch
-    from paper_1602_05806_amd.autograd import Rollout, kinetic_energy, quadrature_weights
+    from paper_1602_05806_amd.autograd import Rollout, kinetic_energy
     cfg = synthetic.CONFIGS["adjoint3d_48_N3"]
     N = cfg["N"]
     ctx = pd.pd_setup(3, cells, cfg["lengths"], N, cfg["dt"], cfg["theta"], cfg["nu"])
@@ -160,14 +160,13 @@ def _c5_like(pd, cells, steps, every, ndirs, tol, smooth):
     field.normalise(cfg["vmax"])
     U = field.eval(synthetic.staggered_coords(cells, cfg["lengths"], xi))
     u0 = [torch.tensor(synthetic.tensor_to_blocked(x, cells, N + 1), device="cuda") for x in U]
-    W = quadrature_weights(ctx)
 
     def loss_of(u):
         with torch.no_grad():
-            return float(kinetic_energy(ctx, Rollout.apply(ctx, steps, every, *u), W))
+            return float(kinetic_energy(ctx, Rollout.apply(ctx, steps, every, *u)))
 
     ur = [x.clone().requires_grad_(True) for x in u0]
-    loss = kinetic_energy(ctx, Rollout.apply(ctx, steps, every, *ur), W)
+    loss = kinetic_energy(ctx, Rollout.apply(ctx, steps, every, *ur))
     loss.backward()
     grad = [x.grad for x in ur]
     unorm = float(torch.sqrt(sum((x * x).sum() for x in u0)))
@@ -211,3 +210,30 @@ def test_gradient_fd_full_48(pd):
     differences to miss by up to a few 1e-6 (measured), independently of the adjoint."""
     print("adjoint FD 48^3 N=3, 20 steps, 4 smooth directions", flush=True)
     _c5_like(pd, (48, 48, 48), 20, 5, 4, 1e-6, smooth=True)
+
+
+@pytest.mark.parametrize("dim,cells,lengths,N", CASES)
+def test_kinetic_energy_and_cotangent(pd, dim, cells, lengths, N):
+    """pd_kinetic_energy against the oracle's energy and its gradient (both pinned on the CPU by
+    closed forms and differences), element by element for the cotangent gscale * W u / ncells."""
+    import torch
+    from oracle.step import kinetic_energy, kinetic_energy_grad
+    print(f"kinetic energy dim={dim} cells={cells} N={N}", flush=True)
+    ctx, g = setup(pd, dim, cells, lengths, N)
+    rng = np.random.default_rng(70 + N)
+    U = [rng.standard_normal(g.shape()) for _ in range(dim)]
+    u = [dev(blocked(g, x)) for x in U]
+    e = pd.pd_kinetic_energy(ctx, u)
+    ref = kinetic_energy(g, U)
+    assert abs(e - ref) <= 1e-13 * abs(ref)
+    grads = [torch.full_like(x, float("nan")) for x in u]
+    gscale = 0.7
+    e2 = pd.pd_kinetic_energy(ctx, u, grads, gscale)
+    assert e2 == e
+    gref = kinetic_energy_grad(g, U)
+    for d in range(dim):
+        got = tensor(g, host(grads[d]))
+        assert np.abs(got - gscale * gref[d]).max() <= 1e-14 * np.abs(gref[d]).max()
+    with pytest.raises(pd.PdError):
+        pd.pd_kinetic_energy(ctx, u, u, 1.0)
+    ctx.close()

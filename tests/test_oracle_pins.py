@@ -408,3 +408,164 @@ def test_layout_round_trip_and_inputs_module_agree():
         assert np.array_equal(b, synthetic.tensor_to_blocked(t, cells, n))
         assert np.array_equal(layout.blocked_to_tensor(b, cells, n), t)
         assert np.array_equal(synthetic.blocked_to_tensor(b, cells, n), t)
+
+
+# ------------------------------------------------------------------ kinetic energy (3D TGV subsection)
+
+def _dual_weights(g):
+    W = np.ones(g.shape())
+    for d in range(g.dim):
+        shp = [1] * g.dim
+        shp[g.dim - 1 - d] = -1
+        W = W * np.tile(g.tab.w, g.cells[d]).reshape(shp)
+    return W
+
+
+def test_kinetic_energy_of_constant_fields():
+    """K = (1/|Omega|) integral of |v|^2 / 2 (the energy of the 3D Taylor-Green subsection of
+    Section 2.4): a constant velocity (1, 2, 3) on a non-cubic box of non-cubic cells has
+    K = (1 + 4 + 9) / 2 = 7 exactly, whatever the box volume (a missing 1/2, a missing 1/|Omega|
+    or a cell volume taken from the wrong direction all change it)."""
+    from oracle.step import kinetic_energy
+    g = Grid((3, 4, 2), (2.0, 3.0, 1.5), 2)
+    U = [np.full(g.shape(), c) for c in (1.0, 2.0, 3.0)]
+    assert abs(kinetic_energy(g, U) - 7.0) <= 1e-13
+    g2 = Grid((5, 3), (0.5, 4.0), 3)
+    assert abs(kinetic_energy(g2, [np.full(g2.shape(), -3.0), np.full(g2.shape(), 0.5)])
+               - (9.0 + 0.25) / 2) <= 1e-13
+
+
+def test_kinetic_energy_taylor_green_closed_forms():
+    """Taylor-Green initial data: the 3D field u = sin x cos y cos z, v = -cos x sin y cos z,
+    w = 0 on [0, 2 pi]^3 (3D Taylor-Green subsection of Section 2.4) has K = 1/8; the 2D field
+    u = sin 2pi x cos 2pi y, v = -cos 2pi x sin 2pi y on the unit square has K = 1/4. Each
+    component is interpolated at its own dual nodes; GL quadrature of the interpolant converges
+    spectrally to the exact integral."""
+    from oracle.step import kinetic_energy
+    L = 2 * np.pi
+    g = Grid((8, 8, 8), (L, L, L), 4)
+    co = synthetic.staggered_coords(g.cells, g.lengths, g.tab.xi)
+
+    def field(c, fx, fy, fz, amp):
+        x, y, z = co[c]
+        return amp * fz(z)[:, None, None] * fy(y)[None, :, None] * fx(x)[None, None, :]
+    U = [field(0, np.sin, np.cos, np.cos, 1.0), field(1, np.cos, np.sin, np.cos, -1.0),
+         np.zeros(g.shape())]
+    assert abs(kinetic_energy(g, U) - 0.125) <= 1e-6
+    g2 = Grid((16, 16), (1.0, 1.0), 3)
+    assert abs(kinetic_energy(g2, _tgv(g2)) - 0.25) <= 1e-6
+
+
+# ------------------------------------------------------------------ viscous solve (alpha != 0)
+
+@pytest.mark.parametrize("dim,cells,N", [(2, (5, 4), 3), (2, (3, 6), 6), (3, (3, 3, 2), 2),
+                                         (3, (2, 3, 3), 3)])
+def test_fastdiag_viscous_solve_matches_sparse_lu(dim, cells, N):
+    """(M + nu dt K) x = b of eq. (implicitviscosity) (with the dt and h factors of eqs. uSDG12,
+    Ux): the fast-diagonalisation solve with alpha = 1 equals a sparse LU solve of the assembled
+    viscous operator (a different algorithm on a different representation)."""
+    import scipy.sparse.linalg as spla
+    lengths = (1.0, 0.8, 1.3)[:dim]
+    g = Grid(cells, lengths, N)
+    dt, nu = 2e-3, 0.37
+    b = np.random.default_rng(11).standard_normal(g.shape())
+    x = FastDiag(g).solve(b, 1.0, nu * dt)
+    ref = spla.spsolve(viscous_operator(g, dt, nu).tocsc(), b.reshape(-1)).reshape(g.shape())
+    assert np.abs(x - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_fastdiag_viscous_N0_closed_form():
+    """N = 0 (all 1D matrices equal 1, the paper's degenerate case): M = I and K is the periodic
+    5-point Laplacian, so the Fourier mode exp(2 pi i (k x + l y)) is an eigenvector of
+    M + beta K with eigenvalue 1 + beta sum_d h_d^-2 (2 - 2 cos(2 pi k_d / n_d))."""
+    cells, lengths = (8, 6), (1.0, 0.75)
+    g = Grid(cells, lengths, 0)
+    beta = 0.013
+    fd = FastDiag(g)
+    for kx, ky in [(1, 0), (3, 2), (4, 3), (0, 1)]:
+        x = np.arange(cells[0])
+        y = np.arange(cells[1])
+        mode = np.cos(2 * np.pi * (kx * x[None, :] / cells[0] + ky * y[:, None] / cells[1]))
+        lam = 1.0 + beta * sum((2 - 2 * np.cos(2 * np.pi * k / n)) / h ** 2
+                               for k, n, h in zip((kx, ky), cells, g.h))
+        assert np.abs(fd.solve(mode, 1.0, beta) - mode / lam).max() <= 1e-14
+
+
+# ------------------------------------------------------------------ Taylor-Green decay (P10)
+
+@pytest.mark.parametrize("convection,tol", [(False, 1e-5), (True, 1e-2)])
+def test_taylor_green_decay(convection, tol):
+    """2D Taylor-Green vortex (validation subsection of Section 2.4, 2pi-scaled to the unit
+    square): the velocity is an eigenfunction of the Laplacian with eigenvalue -8 pi^2 and the
+    convective term is a pure gradient, so the exact solution decays as exp(-8 pi^2 nu t). After
+    m steps of the implicit viscous solve (eq. implicitviscosity) the mass-weighted projection of
+    the velocity on the initial field must decay at that rate (first order in dt: each implicit
+    Euler factor 1 / (1 + 8 pi^2 nu dt)); a wrong nu, dt or h scaling of A_v changes the rate."""
+    g = Grid((16, 16), (1.0, 1.0), 3)
+    dt, nu, steps = 1e-3, 5e-2, 20
+    so = StepOracle(g, dt, 0.6, nu)
+    U0 = _tgv(g)
+    U, P = [u.copy() for u in U0], np.zeros(g.shape())
+    for _ in range(steps):
+        r = so.step(U, P, convection=convection)
+        U, P = r["U_new"], r["P_new"]
+    W = _dual_weights(g)
+    amp = sum(np.sum(W * U[d] * U0[d]) for d in range(2)) / sum(np.sum(W * U0[d] ** 2)
+                                                                 for d in range(2))
+    rate = 8 * np.pi ** 2 * nu
+    t = steps * dt
+    implicit_euler = (1.0 + rate * dt) ** (-steps)
+    assert abs(np.log(amp) - np.log(implicit_euler)) <= tol * rate * t
+    assert abs(np.log(amp) + rate * t) <= (tol + rate * dt) * rate * t
+
+
+# ------------------------------------------------------------------ Rusanov speed (reading R7)
+
+@pytest.mark.parametrize("u0", [0.8, -0.6])
+def test_rusanov_speed_gives_upwind_for_small_perturbations(u0):
+    """eqs. (Fu)-(Fw) with the Rusanov flux at N = 0 (one value per cell): for the x-momentum
+    flux u^2 the largest wave speed is |d(u^2)/du| = 2|u|, and with s = 2 max(|u^-|, |u^+|) the
+    Rusanov flux of a small perturbation of a uniform stream u0 is the upwind flux
+    (u_upwind)^2 up to O(eps^2). Half that speed (or a sign error in the dissipation) leaves an
+    O(eps) difference."""
+    g = Grid((12, 3), (1.0, 1.0), 0)
+    eps = 1e-6
+    pert = np.random.default_rng(3).standard_normal(g.shape()[1])
+    u = np.tile(u0 + eps * pert, (g.shape()[0], 1))
+    v = np.zeros(g.shape())
+    rate = convective_rate(g, [u, v])[0]
+    up = np.roll(u, 1, axis=1) if u0 > 0 else u             # upwind state of face i - 1/2
+    un = u if u0 > 0 else np.roll(u, -1, axis=1)            # upwind state of face i + 1/2
+    upwind = -(un ** 2 - up ** 2) / g.h[0]
+    assert np.abs(rate - upwind).max() <= 50 * eps * np.abs(upwind).max()
+    assert np.abs(rate - upwind).max() <= 1e-3 * np.abs(upwind).max()
+
+
+def test_kinetic_energy_gradient_by_differences():
+    """The loss gradient of the adjoint (dK/dU_d = |cell| / |Omega| W U_d) against central
+    differences of the energy along random directions (K is quadratic, so central differences
+    are exact up to rounding)."""
+    from oracle.step import kinetic_energy, kinetic_energy_grad
+    g = Grid((3, 4, 2), (1.0, 2.0, 0.5), 2)
+    rng = np.random.default_rng(8)
+    U = [rng.standard_normal(g.shape()) for _ in range(3)]
+    G = kinetic_energy_grad(g, U)
+    for _ in range(4):
+        V = [rng.standard_normal(g.shape()) for _ in range(3)]
+        eps = 0.5                      # exact for a quadratic; a large step keeps rounding small
+        fd = (kinetic_energy(g, [a + eps * b for a, b in zip(U, V)])
+              - kinetic_energy(g, [a - eps * b for a, b in zip(U, V)])) / (2 * eps)
+        gv = sum(np.sum(a * b) for a, b in zip(G, V))
+        assert abs(gv - fd) <= 1e-12 * max(abs(fd), 1e-3)
+
+
+@pytest.mark.parametrize("cells,N", [((4, 3), 2), ((3, 2, 4), 3)])
+def test_matrix_free_divergence_matches_assembled(cells, N):
+    """The matrix-free b = sum_d B_d U_d (used at full sizes) equals the assembled B_d of
+    eq. (LOpressure) applied to the same dual components."""
+    from oracle.operators import div_rhs_apply
+    g = Grid(cells, (1.0, 0.7, 1.2)[:len(cells)], N)
+    rng = np.random.default_rng(4)
+    U = [rng.standard_normal(g.shape()) for _ in range(g.dim)]
+    ref = sum((div_rhs(g, d) @ U[d].reshape(-1)).reshape(g.shape()) for d in range(g.dim))
+    assert np.abs(div_rhs_apply(g, U) - ref).max() <= 1e-13 * np.abs(ref).max()
