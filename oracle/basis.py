@@ -62,6 +62,7 @@ class Tables:
       ML, MR  L2 projection matrices M^L, M^R                                  eq. (l2forward)
       phi0, phi1   phi_p(0) and phi_p(1) (face extrapolation vectors)
       dphi    dphi[k, m] = phi_k'(xi_m)
+      dphi0, dphi1 phi_p'(0) and phi_p'(1) (face derivative vectors)
     """
 
     def __init__(self, N):
@@ -115,6 +116,8 @@ class Tables:
         self.phi1 = np.array([phi(p, 1.0) for p in range(n)], dtype=np.float64)
         self.dphi = np.array([[dphi(k, xi[m]) for m in range(n)] for k in range(n)],
                              dtype=np.float64)
+        self.dphi0 = np.array([dphi(p, 0.0) for p in range(n)], dtype=np.float64)
+        self.dphi1 = np.array([dphi(p, 1.0) for p in range(n)], dtype=np.float64)
 
 
 _cache = {}

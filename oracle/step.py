@@ -52,10 +52,17 @@ def _merge(Xs, axis):
     return np.moveaxis(Xm, -1, axis)
 
 
-def convective_rate(grid, V):
+def convective_rate(grid, V, nu=0.0, convection=True):
     """L(V): time derivative of the main-grid velocity from the explicit DG convection term,
     -(1/|T|) M^-1 ( surface integral of omega F.n  -  volume integral of grad(omega).F ),
-    eqs. (Fu)-(Fw), with F_q = q v and the Rusanov flux. V is a list of d tensor arrays."""
+    eqs. (Fu)-(Fw), with F_q = q v and the Rusanov flux. V is a list of d tensor arrays.
+
+    nu > 0 adds the explicit viscous flux of the same equations (the explicit-viscosity
+    variant, Section 2.2): F_q = q v - nu grad q with the broken gradient of each cell's
+    polynomial at the nodes, the face flux averages the two sides' normal derivatives, and the
+    Rusanov speed gains the viscous part 2 nu (2N+1) / (h_e sqrt(pi/2)) (reading: h_e is the
+    mesh size normal to the face, as for the convective part). convection=False keeps only the
+    viscous flux (unsteady Stokes)."""
     t = grid.tab
     n = grid.n
     w = t.w
@@ -69,14 +76,22 @@ def convective_rate(grid, V):
         ve = _split(V[e], ax, nc, n)
         vm = ve @ t.phi1                           # value at the right face of each cell
         vp = np.roll(ve @ t.phi0, -1, axis=-1)     # value of cell i+1 at its left face
-        s = 2.0 * np.maximum(np.abs(vm), np.abs(vp))
+        s = 2.0 * np.maximum(np.abs(vm), np.abs(vp)) if convection else np.zeros_like(vm)
+        if nu:
+            s = s + 2.0 * nu * (2 * grid.N + 1) / (he * np.sqrt(np.pi / 2.0))
         for c in range(grid.dim):                  # momentum component q = V[c]
             qe = _split(V[c], ax, nc, n)
-            F = qe * ve                            # flux component along e at the nodes
+            F = qe * ve if convection else np.zeros_like(qe)   # flux along e at the nodes
+            if nu:
+                F = F - nu * (qe @ t.dphi) / he    # - nu dq/dx_e at the nodes
             vol = F @ Kv.T / he                    # sum_m Kv[k,m] F[m]
             qm = qe @ t.phi1
             qp = np.roll(qe @ t.phi0, -1, axis=-1)
-            Fhat = 0.5 * (qm * vm + qp * vp) - 0.5 * s * (qp - qm)   # at face i+1/2
+            Fhat = 0.5 * (qm * vm + qp * vp) * convection - 0.5 * s * (qp - qm)   # face i+1/2
+            if nu:
+                dqm = qe @ t.dphi1 / he                               # left cell, right face
+                dqp = np.roll(qe @ t.dphi0, -1, axis=-1) / he         # right cell, left face
+                Fhat = Fhat - 0.5 * nu * (dqm + dqp)
             Fhat_left = np.roll(Fhat, 1, axis=-1)                       # at face i-1/2
             surf = (Fhat[..., None] * t.phi1[None, :] - Fhat_left[..., None] * t.phi0[None, :]) \
                 / w[None, :] / he
@@ -84,13 +99,14 @@ def convective_rate(grid, V):
     return out
 
 
-def rk3(grid, V, dt):
-    """Third-order TVD Runge-Kutta (Shu-Osher) for dV/dt = L(V)."""
-    L0 = convective_rate(grid, V)
+def rk3(grid, V, dt, nu=0.0, convection=True):
+    """Third-order TVD Runge-Kutta (Shu-Osher) for dV/dt = L(V) (nu > 0: with the explicit
+    viscous flux)."""
+    L0 = convective_rate(grid, V, nu, convection)
     V1 = [V[c] + dt * L0[c] for c in range(grid.dim)]
-    L1 = convective_rate(grid, V1)
+    L1 = convective_rate(grid, V1, nu, convection)
     V2 = [0.75 * V[c] + 0.25 * (V1[c] + dt * L1[c]) for c in range(grid.dim)]
-    L2 = convective_rate(grid, V2)
+    L2 = convective_rate(grid, V2, nu, convection)
     return [V[c] / 3.0 + 2.0 / 3.0 * (V2[c] + dt * L2[c]) for c in range(grid.dim)]
 
 
@@ -136,12 +152,24 @@ class StepOracle:
         return [Ustar[d] - (self.G[d] @ q.reshape(-1)).reshape(g.shape())
                 for d in range(g.dim)]
 
-    def step(self, U, P, convection=True):
+    def step(self, U, P, convection=True, explicit_viscosity=False):
         """One step. U: list of dual components (tensor layout), P: P^n (tensor layout).
-        Returns dict with U_new, P_new, q, b, Ustar, Umain (after viscosity), Fmain."""
+        Returns dict with U_new, P_new, q, b, Ustar, Umain (after viscosity), Fmain.
+
+        explicit_viscosity: the variant of Section 2.2 in which the viscous flux is part of the
+        explicit TVD-RK3 advection-diffusion step (eqs. Fu-Fw with the viscous Rusanov speed)
+        and the implicit viscous solve is skipped."""
         g = self.grid
         w = g.tab.w
         Um = [dual_to_main(g, U[d], d) for d in range(g.dim)]
+        if explicit_viscosity:
+            Fm = rk3(g, Um, self.dt, self.nu, convection) if (convection or self.nu) else Um
+            Us = [main_to_dual(g, Fm[d], d) for d in range(g.dim)]
+            b = self.rhs(Us)
+            q = self.solve_pressure(b)
+            Un = self.project_velocity(q, Us)
+            Pn = (q - (1.0 - self.theta) * P) / self.theta
+            return dict(U_new=Un, P_new=Pn, q=q, b=b, Ustar=Us, Umain=Fm, Fmain=Fm, Um0=Um)
         Fm = rk3(g, Um, self.dt) if convection else Um
         # M^{xyz} as a tensor of nodal weights
         Wt = np.ones(g.shape())

@@ -569,3 +569,70 @@ def test_matrix_free_divergence_matches_assembled(cells, N):
     U = [rng.standard_normal(g.shape()) for _ in range(g.dim)]
     ref = sum((div_rhs(g, d) @ U[d].reshape(-1)).reshape(g.shape()) for d in range(g.dim))
     assert np.abs(div_rhs_apply(g, U) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------------ explicit viscosity (Section 2.2)
+
+def test_explicit_viscosity_N0_closed_form():
+    """N = 0 (piecewise constants, zero broken gradients): the viscous part of eqs. (Fu)-(Fw)
+    reduces to the penalty of the Rusanov speed, -s_v (q+ - q-) / 2 with
+    s_v = 2 nu (2N+1) / (h sqrt(pi/2)), so the rate of cell i is
+    nu / (h^2 sqrt(pi/2)) (q_{i+1} - 2 q_i + q_{i-1}) along each direction."""
+    g = Grid((7, 5), (1.0, 0.6), 0)
+    nu = 0.03
+    rng = np.random.default_rng(21)
+    V = [rng.standard_normal(g.shape()) for _ in range(2)]
+    r = convective_rate(g, V, nu, convection=False)
+    for c in range(2):
+        ref = np.zeros(g.shape())
+        for d in range(2):
+            ax = 1 - d
+            q = V[c]
+            ref = ref + nu / (g.h[d] ** 2 * np.sqrt(np.pi / 2)) * (
+                np.roll(q, -1, axis=ax) - 2 * q + np.roll(q, 1, axis=ax))
+        assert np.abs(r[c] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_explicit_viscosity_converges_to_laplacian(N):
+    """Viscous flux of eqs. (Fu)-(Fw) with the broken gradient and the averaged normal
+    derivative: on a smooth field the rate converges to nu times the Laplacian (here of
+    sin 2 pi x: -4 pi^2 nu sin 2 pi x) as the grid is refined, pointwise at order N - 1 (the
+    max-norm truncation order of a DG second derivative; measured 1.0 / 2.0 / 3.0 / 4.0 for
+    N = 2..5)."""
+    nu = 0.01
+
+    def err(nx):
+        g = Grid((nx, 2), (1.0, 1.0), N)
+        mc = synthetic.main_coords(g.cells, g.lengths, g.tab.xi)
+        u = np.tile(np.sin(2 * np.pi * mc[0])[None, :], (g.shape()[0], 1))
+        r = convective_rate(g, [u, np.zeros(g.shape())], nu, convection=False)
+        ex = -4 * np.pi ** 2 * nu * u
+        assert np.abs(r[1]).max() == 0.0
+        return np.abs(r[0] - ex).max() / np.abs(ex).max()
+    e1, e2 = err(16), err(32)
+    assert e2 < 2e-2 and np.log2(e1 / e2) >= N - 1.3   # pointwise order N - 1 (measured)
+
+
+def test_explicit_viscosity_taylor_green_decay_and_implicit_cross_check():
+    """The explicit-viscosity step (Section 2.2, with dt inside the viscous part of the CFL
+    condition eq. CFL) decays the Taylor-Green vortex at exp(-8 pi^2 nu t) and agrees with the
+    implicit-viscosity step to first order in dt."""
+    g = Grid((16, 16), (1.0, 1.0), 3)
+    nu, dt, steps = 5e-2, 2e-4, 100
+    # viscous part of eq. (CFL) with CFL = 1
+    assert dt * (2 * g.N + 1) ** 2 * sum(2 * nu / h ** 2 for h in g.h) < 1.0
+    so = StepOracle(g, dt, 0.6, nu)
+    U0 = _tgv(g)
+    Ue, Ui = [u.copy() for u in U0], [u.copy() for u in U0]
+    P = np.zeros(g.shape())
+    for _ in range(steps):
+        Ue = so.step(Ue, P, convection=False, explicit_viscosity=True)["U_new"]
+        Ui = so.step(Ui, P, convection=False)["U_new"]
+    W = _dual_weights(g)
+    den = sum(np.sum(W * U0[d] ** 2) for d in range(2))
+    amp = sum(np.sum(W * Ue[d] * U0[d]) for d in range(2)) / den
+    rate, t = 8 * np.pi ** 2 * nu, steps * dt
+    assert abs(np.log(amp) + rate * t) <= 1e-3 * rate * t
+    diff = np.sqrt(sum(np.sum(W * (Ue[d] - Ui[d]) ** 2) for d in range(2)) / den)
+    assert diff <= 2 * rate * dt * rate * t
