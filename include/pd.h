@@ -150,7 +150,9 @@ int pd_l2_project(pd_ctx* ctx, int d, int dir, const void* in, void* out, void* 
 
 /* One explicit convection step of eqs. (Fu)-(Fw) on the main grid with the third-order TVD
  * Runge-Kutta scheme: um[d] (FP64 main-grid velocity components) are replaced by the
- * predicted Fu, Fv, Fw. Rusanov flux with s = 2 max(|v_e^-|, |v_e^+|) on faces normal to e. */
+ * predicted Fu, Fv, Fw. Rusanov flux with s = 2 max(|v_e^-|, |v_e^+|) on faces normal to e.
+ * With PD_CFG_EXPLICIT_VISC set, the explicit viscous flux is included (see pd_configure);
+ * with PD_CFG_CONVECTION = 0 as well, only the viscous flux. */
 int pd_convect(pd_ctx* ctx, void* const um[3], void* hip_stream);
 
 /* One semi-implicit fractional step (eqs. LOdiffusionU-LOvelocityW): u[d] = dual velocity
@@ -158,6 +160,44 @@ int pd_convect(pd_ctx* ctx, void* const um[3], void* hip_stream);
  * report the viscous solves, info[3] the pressure solve (info may be NULL). Synchronises.
  * Solver settings come from pd_configure. */
 int pd_step(pd_ctx* ctx, void* const u[3], void* p, pd_solve_info info[4], void* hip_stream);
+
+/* ---- Space-time step (Section 3) -------------------------------------------------------------
+ * One step of the space-time scheme of degree M in time on the slab [t^n, t^n + dt] with the
+ * Picard pressure correction of Section 3.3 (eqs. LOdiffusionU_HO-LOvelocityW_HO), M + 1
+ * iterations. The velocity is a polynomial of degree M in time on the nodal Gauss-Legendre basis
+ * psi_0..psi_M of [0, 1]; the time matrices are those of eqs. (tmatrix1)-(tmatrix3)
+ * (M^t = diag(omega), At = M1 - MV). Iteration k forms, at every time node p, the right-hand
+ * side of the momentum equations (eq. uSDG1_ST) on the dual grids,
+ *   R_p = pi_{#->*}(psi_p(0) F) - omega_p G P_p      (k = 0: F = F^n, the semi-implicit
+ *         predictor of pd_step at t^n, i.e. TVD-RK3 advection and, for M = 0, the implicit
+ *         viscous solve; P = 0)
+ *   R_p = pi_{#->*}(psi_p(0) pi_{*->#} U^n + dt omega_p L(pi_{*->#} U_p)) - omega_p G P_p
+ *         (k >= 1: the space-time advective term of eq. Fu_ST at the current iterate; L is the
+ *         explicit DG rate, with the viscous flux when PD_CFG_EXPLICIT_VISC is set),
+ * solves the M + 1 decoupled pressure systems omega_s A_p dP_s = sum_d B_d R_{s,d} (eq. pSyst_ST2;
+ * each a pd_cg_solve with the step's precision and PD_CFG_P_RTOL), and sets
+ * U_s = sum_p Ainv[s][p] (R_p - omega_p G dP_p), P_s += dP_s: every iterate is discretely
+ * divergence free at every time node (eq. pSDG1_ST). M = 0 is the semi-implicit step of pd_step
+ * with theta = 1.
+ * u[0..dim-1]: FP64 dual components, U^n on entry (the previous slab's end value), the end value
+ * u(t^{n+1}) = sum_s psi_s(1) U_s on return. p_nodes: FP64 array of (M+1) * ndof, overwritten
+ * with the pressure at the M + 1 time nodes (node s at offset s * ndof). 0 <= M <= 4; M >= 1
+ * requires nu = 0 or PD_CFG_EXPLICIT_VISC (the non-symmetric space-time implicit viscous solve
+ * of eq. implicitviscosity_ST is not provided: PD_EINVAL). info: NULL or 3 + (M+1)^2 entries:
+ * [0..dim-1] the viscous solves (M = 0 with implicit viscosity, else zero), [3 + k (M+1) + s]
+ * the pressure solve of iteration k at node s. Allocates its workspace on first use of each M
+ * (about 3 dim (M+1) + M + 2 dim + 2 vectors of ndof doubles). Synchronises. */
+int pd_step_st(pd_ctx* ctx, int M, void* const u[3], void* p_nodes, pd_solve_info* info,
+               void* hip_stream);
+
+/* Host-only query of the time tables the library builds for degree M (0..4), no device use:
+ * which = PD_TTAB_NODES / PD_TTAB_WEIGHTS / PD_TTAB_PSI0 / PD_TTAB_PSI1 (M+1 values: Gauss-
+ * Legendre nodes tau and weights omega on [0, 1], psi_p(0), psi_p(1)), PD_TTAB_MV / PD_TTAB_AINV
+ * ((M+1)^2 values, row-major: MV of eq. tmatrix3 and the inverse of At = M1 - MV). Returns the
+ * number of values written, or PD_EINVAL. */
+enum { PD_TTAB_NODES = 0, PD_TTAB_WEIGHTS = 1, PD_TTAB_PSI0 = 2, PD_TTAB_PSI1 = 3,
+       PD_TTAB_MV = 4, PD_TTAB_AINV = 5 };
+int pd_time_table(int M, int which, double* out);
 
 /* ---- Adjoint (transposed linearisation) of the fractional step --------------------------------
  * The step maps the dual velocity U^n to U^{n+1} (P^n does not enter U^{n+1}). Its adjoint maps
@@ -229,6 +269,14 @@ int pd_kinetic_energy(pd_ctx* ctx, void* const u[3], double gscale, void* const 
  *   PD_CFG_DEFER_X       where CG iteration k's x += alpha_k p_k is made: 1 (default) = in the
  *                        operator kernel of iteration k + 1 (it reads p_k anyway; 9 instead of
  *                        10 vector words per DoF and iteration), 0 = in the update kernel
+ *   PD_CFG_EXPLICIT_VISC 1 = the explicit-viscosity variant of Section 2.2: the viscous flux
+ *                        -nu grad q is part of the explicit TVD-RK3 step of pd_step and pd_convect
+ *                        (broken gradient at the nodes, averaged normal derivatives on faces,
+ *                        Rusanov speed plus 2 nu (2N+1) / (h_e sqrt(pi/2)), eqs. Fu-Fw) and the
+ *                        implicit viscous solves are skipped; pd_step then requires the viscous
+ *                        part of the CFL condition eq. (CFL), dt (2N+1)^2 sum_d 2 nu / h_d^2 <= 1
+ *                        (PD_EINVAL otherwise); pd_step_adjoint and pd_convect_adjoint reject it.
+ *                        0 (default) = implicit viscosity (eq. implicitviscosity).
  *   PD_CFG_ONE_KERNEL    2D only: 1 = one kernel per CG iteration: the operator kernel of
  *                        iteration k also makes the residual update of iteration k - 1,
  *                        r_k = r_{k-1} - alpha_{k-1} q_{k-1}, and its x update (8 vector words
@@ -243,7 +291,7 @@ enum {
   PD_CFG_STEP_PREC = 0, PD_CFG_P_RTOL = 1, PD_CFG_V_RTOL = 2, PD_CFG_MAXIT = 3,
   PD_CFG_CONVECTION = 4, PD_CFG_RU_FACTOR = 5, PD_CFG_TIMING = 6, PD_CFG_CHECK_EVERY = 7,
   PD_CFG_KZ = 8, PD_CFG_TILES_PER_WG = 9, PD_CFG_PREFETCH = 10, PD_CFG_TILE_VARIANT = 11,
-  PD_CFG_DEFER_X = 12, PD_CFG_ONE_KERNEL = 13
+  PD_CFG_DEFER_X = 12, PD_CFG_ONE_KERNEL = 13, PD_CFG_EXPLICIT_VISC = 14
 };
 int pd_configure(pd_ctx* ctx, int key, double value);
 

@@ -29,16 +29,19 @@ PD_FP64, PD_FP32, PD_FP32_REFINE64 = 0, 1, 2
 PD_OP_PRESSURE, PD_OP_VISCOUS = 0, 1
 (PD_CFG_STEP_PREC, PD_CFG_P_RTOL, PD_CFG_V_RTOL, PD_CFG_MAXIT, PD_CFG_CONVECTION,
  PD_CFG_RU_FACTOR, PD_CFG_TIMING, PD_CFG_CHECK_EVERY, PD_CFG_KZ, PD_CFG_TILES_PER_WG,
- PD_CFG_PREFETCH, PD_CFG_TILE_VARIANT, PD_CFG_DEFER_X, PD_CFG_ONE_KERNEL) = range(14)
+ PD_CFG_PREFETCH, PD_CFG_TILE_VARIANT, PD_CFG_DEFER_X, PD_CFG_ONE_KERNEL,
+ PD_CFG_EXPLICIT_VISC) = range(15)
 PD_BATCH_AUTOTUNE, PD_BATCH_RETUNE = 1, 2
 PD_BCFG_CHUNK, PD_BCFG_GRAPH, PD_BCFG_RU_FACTOR = 0, 1, 2
 PD_TAB_NODES, PD_TAB_WEIGHTS, PD_TAB_L, PD_TAB_C, PD_TAB_R, PD_TAB_PNULL = range(6)
+PD_TTAB_NODES, PD_TTAB_WEIGHTS, PD_TTAB_PSI0, PD_TTAB_PSI1, PD_TTAB_MV, PD_TTAB_AINV = range(6)
 
 EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "pd_table_1d", "pd_apply",
             "pd_cg_solve", "pd_rhs_div", "pd_project_velocity", "pd_project_null",
             "pd_l2_project", "pd_convect", "pd_step", "pd_configure", "pd_timing",
             "pd_l2_project_adjoint", "pd_rhs_div_adjoint", "pd_project_velocity_adjoint",
-            "pd_convect_adjoint", "pd_step_adjoint", "pd_kinetic_energy",
+            "pd_convect_adjoint", "pd_step_adjoint", "pd_kinetic_energy", "pd_step_st",
+            "pd_time_table",
             "pd_batch_setup", "pd_batch_destroy", "pd_batch_last_error", "pd_batch_layout",
             "pd_batch_variants", "pd_batch_configure", "pd_batch_cg_solve"]
 
@@ -86,6 +89,9 @@ _lib.pd_step_adjoint.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.POINTER(pd_solve_info), _vp]
 _lib.pd_kinetic_energy.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.c_double, ctypes.POINTER(_vp),
                                    ctypes.POINTER(ctypes.c_double), _vp]
+_lib.pd_step_st.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_vp), _vp, ctypes.POINTER(pd_solve_info),
+                            _vp]
+_lib.pd_time_table.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
 _lib.pd_batch_setup.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
                                 ctypes.c_double, ctypes.c_uint, _vp]
@@ -265,6 +271,28 @@ def pd_step(ctx, u, p, stream=None):
                       ctypes.c_void_p(_stream(stream)))
     _check(ctx, rc, allow=(PD_ENOCONV, PD_EBREAKDOWN))
     return [i.as_dict() for i in info]
+
+
+def pd_step_st(ctx, M, u, p_nodes, stream=None):
+    """One space-time step of degree M in time (Picard pressure correction) in place on u (dual
+    components, U^n in, end value out); p_nodes ((M+1) * ndof FP64) receives the pressure at the
+    time nodes. Returns the 3 + (M+1)^2 solve-info dicts (viscous x, y, z; pressure solves)."""
+    import torch
+    m = int(M) + 1
+    info = (pd_solve_info * (3 + m * m))()
+    rc = _lib.pd_step_st(ctx.handle, int(M), _vec3(ctx, u), _ptr(p_nodes, m * ctx.ndof, torch.float64),
+                         info, ctypes.c_void_p(_stream(stream)))
+    _check(ctx, rc, allow=(PD_ENOCONV, PD_EBREAKDOWN))
+    return [i.as_dict() for i in info]
+
+
+def pd_time_table(M, which):
+    """Host-only: the library's time table `which` (PD_TTAB_*) for degree M, as a list."""
+    out = (ctypes.c_double * 25)()
+    cnt = _lib.pd_time_table(int(M), int(which), out)
+    if cnt < 0:
+        raise PdError(cnt, f"pd_time_table: bad degree {M} or table {which}")
+    return list(out)[:cnt]
 
 
 def pd_l2_project_adjoint(ctx, d, direction, src, dst, stream=None):

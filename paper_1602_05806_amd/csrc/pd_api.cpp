@@ -34,6 +34,7 @@ struct pd_ctx {
   int tile_variant = 0;                          // 2D tile shape (0 = largest fitting)
   int defer_x = 1;         // 1: x update made by the next apply kernel, 0: by the update kernel
   int one_kernel = 0;      // 2D: one kernel per CG iteration (residual update folded in)
+  int explicit_visc = 0;   // 1: viscous flux in the explicit TVD-RK3 step, no viscous solve
   // device workspace
   CgState* st = nullptr;       // CG state of the (inner) solve
   CgState* st2 = nullptr;      // outer refinement / residual norms
@@ -54,6 +55,17 @@ struct pd_ctx {
   double* at[4][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr},
                       {nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};   // adjoint work
   double* abar = nullptr;                             // adjoint pressure right-hand side
+  // space-time step: node iterates U_s, right-hand sides R_s and pressure-gradient work W_s
+  // (dual grids, per node and component), pressure increments dP_s, pi_{*->#} U^n and two
+  // main-grid work arrays per component, one pressure right-hand side
+  double* stU[pdh::kMaxm][3] = {};
+  double* stR[pdh::kMaxm][3] = {};
+  double* stW[pdh::kMaxm][3] = {};
+  double* stdP[pdh::kMaxm] = {};
+  double* stum0[3] = {};
+  double* sta[3] = {};
+  double* stb[3] = {};
+  double* strhs = nullptr;
   CgState* hst = nullptr;      // pinned host mirror, 2 slots
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -431,7 +443,7 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
   if ((rc = cg_prepare(c, &R))) return rc;
   double ref = 1.0;                             // scaled residual norm at the last replacement
   double best = 1.0;                            // smallest scaled FP64 residual so far
-  int stall = 0;                                // replacements in a row without a new best
+  int stall = 0;                                // replacements in a row that did not halve best
   int stalled = 0;                              // FP32 breakdowns in a row without progress
   inf->status = PD_ENOCONV;
   for (;;) {
@@ -456,17 +468,23 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
       inf->status = PD_ENOCONV;
       break;
     }
-    // FP32 arithmetic has stopped reducing the FP64 residual (it grew beyond twice the best
-    // one, or no new best for 16 replacements: eps_32 cond(A) near 1 makes FP32 A p meaningless
-    // for the smallest eigenvalues): continue with FP64 iterations from the current x.
+    // FP32 arithmetic has stopped reducing the FP64 residual: it grew beyond twice the best
+    // one, or kStallRefine replacements in a row did not halve the best one (each replacement
+    // normally gains the factor ru_factor). Causes: eps_32 cond(A) near 1 makes FP32 A p
+    // meaningless for the smallest eigenvalues, or the goal lies below the FP64 rounding floor
+    // of b - A x. The solve continues with FP64 iterations from the current x, whose true-
+    // residual checks handle both (measured: 256^2 N = 6 at rtol 1e-12, below the floor of its
+    // smooth right-hand side, took 103k FP32 iterations when only 16 non-improving replacements
+    // triggered the switch).
+    constexpr int kStallRefine = 3;
     const double r = res / scale;
-    if (r < best) {
-      best = r;
+    if (r < 0.5 * best) {
       stall = 0;
     } else {
       ++stall;
     }
-    if (r > 2.0 * best || stall >= 16) {
+    if (r < best) best = r;
+    if (r > 2.0 * best || stall >= kStallRefine) {
       cg_collect_timing(c, R);
       inf->fallback_iter = R.k;
       pd_solve_info i64{};
@@ -617,8 +635,9 @@ int rhs_div(pd_ctx* c, void* const u[3], double* b, hipStream_t s) {
   return PD_OK;
 }
 
-// u_d -= dt/h_d M^-1 (R~ q[i+1] - L~ q[i])
-int project_velocity(pd_ctx* c, const double* q, void* const u[3], hipStream_t s) {
+// u_d -= scale dt/h_d M^-1 (R~ q[i+1] - L~ q[i])
+int project_velocity(pd_ctx* c, const double* q, void* const u[3], hipStream_t s,
+                     double scale = 1.0) {
   const int n = c->n;
   for (int d = 0; d < c->dim; ++d) {
     if (!u[d]) return fail(c, PD_EINVAL, "null velocity component");
@@ -632,7 +651,7 @@ int project_velocity(pd_ctx* c, const double* q, void* const u[3], hipStream_t s
     L.d = d;
     L.o0 = 1;
     L.o1 = 0;
-    L.coef = -c->dt / c->h[d];
+    L.coef = -scale * c->dt / c->h[d];
     L.accum = 1.0;
     L.in = q;
     L.out = (double*)u[d];
@@ -742,6 +761,23 @@ int ensure_step_buffers(pd_ctx* c) {
   return dev_alloc(c, &c->qbuf, n);
 }
 
+int ensure_st_buffers(pd_ctx* c, int m) {
+  const size_t n = (size_t)c->ndof;
+  int rc;
+  for (int q = 0; q < m; ++q) {
+    for (int d = 0; d < c->dim; ++d)
+      if ((rc = dev_alloc(c, &c->stU[q][d], n)) || (rc = dev_alloc(c, &c->stR[q][d], n)) ||
+          (rc = dev_alloc(c, &c->stW[q][d], n)))
+        return rc;
+    if ((rc = dev_alloc(c, &c->stdP[q], n))) return rc;
+  }
+  for (int d = 0; d < c->dim; ++d)
+    if ((rc = dev_alloc(c, &c->stum0[d], n)) || (rc = dev_alloc(c, &c->sta[d], n)) ||
+        (rc = dev_alloc(c, &c->stb[d], n)))
+      return rc;
+  return dev_alloc(c, &c->strhs, n);
+}
+
 int ensure_adjoint_buffers(pd_ctx* c) {
   int rc = ensure_step_buffers(c);
   if (rc) return rc;
@@ -767,6 +803,21 @@ void fill_conv_common(const pd_ctx* c, pdk::ConvLaunch* L) {
   }
   for (int i = 0; i < 81; ++i) L->Kv[i] = i < n * n ? c->tab.Kv[i] : 0;
   L->dt = c->dt;
+  L->nu = c->explicit_visc ? c->nu : 0.0;
+  L->conv = c->convection;
+  for (int i = 0; i < 9; ++i) {
+    L->dphi0[i] = i < n ? c->tab.dphi0[i] : 0;
+    L->dphi1[i] = i < n ? c->tab.dphi1[i] : 0;
+  }
+  for (int i = 0; i < 81; ++i) L->KD[i] = i < n * n ? c->tab.KD[i] : 0;
+}
+
+// Viscous part of the CFL condition of the explicit scheme (eq. CFL with CFL = 1):
+// dt (2N+1)^2 sum_d 2 nu / h_d^2 <= 1.
+bool explicit_visc_stable(const pd_ctx* c) {
+  double s = 0.0;
+  for (int d = 0; d < c->dim; ++d) s += 2.0 * c->nu / (c->h[d] * c->h[d]);
+  return c->dt * (2.0 * c->N + 1.0) * (2.0 * c->N + 1.0) * s <= 1.0;
 }
 
 // The first two Shu-Osher stages: s1 = U + dt L(U); s2 = 3/4 U + 1/4 (s1 + dt L(s1)).
@@ -985,6 +1036,20 @@ void pd_destroy(pd_ctx* c) {
       if (c->at[k][d]) (void)hipFree(c->at[k][d]);
   }
   if (c->abar) (void)hipFree(c->abar);
+  for (int q = 0; q < pdh::kMaxm; ++q) {
+    for (int d = 0; d < 3; ++d) {
+      if (c->stU[q][d]) (void)hipFree(c->stU[q][d]);
+      if (c->stR[q][d]) (void)hipFree(c->stR[q][d]);
+      if (c->stW[q][d]) (void)hipFree(c->stW[q][d]);
+    }
+    if (c->stdP[q]) (void)hipFree(c->stdP[q]);
+  }
+  for (int d = 0; d < 3; ++d) {
+    if (c->stum0[d]) (void)hipFree(c->stum0[d]);
+    if (c->sta[d]) (void)hipFree(c->sta[d]);
+    if (c->stb[d]) (void)hipFree(c->stb[d]);
+  }
+  if (c->strhs) (void)hipFree(c->strhs);
   if (c->hst) (void)hipHostFree(c->hst);
   for (int i = 0; i < 2; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
@@ -1106,11 +1171,15 @@ int pd_step(pd_ctx* c, void* const u[3], void* p, pd_solve_info info[4], void* h
   // 1. pi_{*->#}
   for (int d = 0; d < c->dim; ++d)
     if ((rc = l2_project(c, d, 0, (const double*)u[d], c->um[d], s))) return rc;
-  // 2. explicit convection (TVD RK3)
-  if (c->convection)
+  const bool evisc = c->explicit_visc && c->nu > 0.0;
+  if (evisc && !explicit_visc_stable(c))
+    return fail(c, PD_EINVAL, "explicit viscosity: dt exceeds the viscous CFL limit "
+                              "1 / ((2N+1)^2 sum_d 2 nu / h_d^2)");
+  // 2. explicit convection (TVD RK3), with the viscous flux in the explicit-viscosity variant
+  if (c->convection || evisc)
     if ((rc = convect(c, c->um, s))) return rc;
   // 3. implicit viscosity on the main grid: (M + nu dt K) U = M F, initial guess F
-  if (c->nu > 0.0) {
+  if (c->nu > 0.0 && !c->explicit_visc) {
     for (int d = 0; d < c->dim; ++d) {
       PD_HIP(c, pdk::launch_mass(c->dim, c->N, c->tab.w, c->um[d], c->s1[d], c->ncells, s));
       rc = solve(c, PD_OP_VISCOUS, c->step_prec, c->s1[d], c->um[d], c->v_rtol, c->maxit, &loc[d], s);
@@ -1134,6 +1203,166 @@ int pd_step(pd_ctx* c, void* const u[3], void* p, pd_solve_info info[4], void* h
   PD_HIP(c, pdk::launch_axpby(1.0 / c->theta, c->qbuf, -(1.0 - c->theta) / c->theta, (double*)p, n, s));
   PD_HIP(c, hipStreamSynchronize(s));
   return PD_OK;
+}
+
+int pd_step_st(pd_ctx* c, int M, void* const u[3], void* p_nodes, pd_solve_info* info,
+               void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!u || !p_nodes) return fail(c, PD_EINVAL, "null array");
+  for (int d = 0; d < c->dim; ++d) {
+    if (!u[d] || u[d] == p_nodes) return fail(c, PD_EINVAL, "null or aliased velocity component");
+    for (int e = 0; e < d; ++e)
+      if (u[e] == u[d]) return fail(c, PD_EINVAL, "aliased velocity components");
+  }
+  pdh::TimeTable tt;
+  std::string terr;
+  if (!pdh::build_time_table(M, &tt, &terr)) return fail(c, PD_EINVAL, terr);
+  const bool evisc = c->explicit_visc && c->nu > 0.0;
+  if (M >= 1 && c->nu > 0.0 && !c->explicit_visc)
+    return fail(c, PD_EINVAL, "pd_step_st: M >= 1 needs nu = 0 or PD_CFG_EXPLICIT_VISC (the "
+                              "space-time implicit viscous solve is not provided)");
+  if (evisc && !explicit_visc_stable(c))
+    return fail(c, PD_EINVAL, "explicit viscosity: dt exceeds the viscous CFL limit "
+                              "1 / ((2N+1)^2 sum_d 2 nu / h_d^2)");
+  const int m = tt.m;
+  int rc = ensure_step_buffers(c);
+  if (rc || (rc = ensure_st_buffers(c, m))) return rc;
+  hipStream_t s = S(hip_stream);
+  c->last_stream = s;
+  const long long n = c->ndof;
+  const int dim = c->dim;
+  pd_solve_info loc[3 + pdh::kMaxm * pdh::kMaxm];
+  std::memset(loc, 0, sizeof(loc));
+  double* P[pdh::kMaxm];
+  for (int q = 0; q < m; ++q) P[q] = (double*)p_nodes + (size_t)q * n;
+  auto report = [&](int count) {
+    if (info) std::memcpy(info, loc, sizeof(pd_solve_info) * count);
+  };
+  // F^n of the first iteration: the semi-implicit predictor (pi_{*->#}, TVD-RK3 advection with
+  // the explicit viscous flux in that variant, implicit viscous solve for M = 0), and
+  // pi_{*->#} U^n for the advective term of the later iterations
+  for (int d = 0; d < dim; ++d) {
+    if ((rc = l2_project(c, d, 0, (const double*)u[d], c->um[d], s))) return rc;
+    PD_HIP(c, pdk::launch_axpby(1.0, c->um[d], 0.0, c->stum0[d], n, s));
+  }
+  if (c->convection || evisc)
+    if ((rc = convect(c, c->um, s))) return rc;
+  if (c->nu > 0.0 && !c->explicit_visc) {
+    for (int d = 0; d < dim; ++d) {
+      PD_HIP(c, pdk::launch_mass(dim, c->N, c->tab.w, c->um[d], c->s1[d], c->ncells, s));
+      rc = solve(c, PD_OP_VISCOUS, c->step_prec, c->s1[d], c->um[d], c->v_rtol, c->maxit, &loc[d], s);
+      if (rc != PD_OK) {
+        report(3);
+        return rc;
+      }
+    }
+  }
+  for (int q = 0; q < m; ++q) PD_HIP(c, pdk::launch_zero(false, P[q], n, s));
+  const int total = 3 + m * m;
+  for (int k = 0; k < m; ++k) {
+    // right-hand sides R_p of the momentum equations on the dual grids
+    for (int p = 0; p < m; ++p) {
+      if (k == 0) {
+        for (int d = 0; d < dim; ++d)
+          PD_HIP(c, pdk::launch_axpby(tt.psi0[p], c->um[d], 0.0, c->stb[d], n, s));
+      } else {
+        // psi_p(0) pi_{*->#} U^n + dt omega_p L(pi_{*->#} U_p)  (eq. Fu_ST at node p)
+        for (int d = 0; d < dim; ++d)
+          if ((rc = l2_project(c, d, 0, c->stU[p][d], c->sta[d], s))) return rc;
+        pdk::ConvLaunch L;
+        fill_conv_common(c, &L);
+        for (int d = 0; d < dim; ++d) {
+          L.ucur[d] = c->sta[d];
+          L.u0[d] = c->stum0[d];
+          L.out[d] = c->stb[d];
+        }
+        L.a = tt.psi0[p];
+        L.cr = c->dt * tt.omega[p];
+        if (c->convection || evisc) {
+          PD_HIP(c, pdk::launch_convect_stage(L, s));
+        } else {
+          for (int d = 0; d < dim; ++d)
+            PD_HIP(c, pdk::launch_axpby(tt.psi0[p], c->stum0[d], 0.0, c->stb[d], n, s));
+        }
+      }
+      for (int d = 0; d < dim; ++d)
+        if ((rc = l2_project(c, d, 1, c->stb[d], c->stR[p][d], s))) return rc;
+      // pressure term of the current iterate on the dual grids: - omega_p G P_p
+      if (k > 0)
+        if ((rc = project_velocity(c, P[p], (void* const*)c->stR[p], s, tt.omega[p]))) return rc;
+    }
+    // decoupled pressure corrections: omega_s A_p dP_s = sum_d B_d R_{s,d}
+    for (int q = 0; q < m; ++q) {
+      if ((rc = rhs_div(c, (void* const*)c->stR[q], c->strhs, s))) return rc;
+      PD_HIP(c, pdk::launch_axpby(1.0 / tt.omega[q], c->strhs, 0.0, c->strhs, n, s));
+      PD_HIP(c, pdk::launch_zero(false, c->stdP[q], n, s));
+      pd_solve_info* si = &loc[3 + k * m + q];
+      rc = solve(c, PD_OP_PRESSURE, c->step_prec, c->strhs, c->stdP[q], c->p_rtol, c->maxit, si, s);
+      if (rc != PD_OK) {
+        report(total);
+        return rc;
+      }
+      for (int d = 0; d < dim; ++d) PD_HIP(c, pdk::launch_zero(false, c->stW[q][d], n, s));
+      if ((rc = project_velocity(c, c->stdP[q], (void* const*)c->stW[q], s))) return rc;   // -G dP
+      PD_HIP(c, pdk::launch_axpby(1.0, c->stdP[q], 1.0, P[q], n, s));
+    }
+    // U_s = sum_p Ainv[s][p] (R_p + omega_p W_p), W_p = -G dP_p
+    for (int d = 0; d < dim; ++d) {
+      pdk::TimeMix X;
+      X.m = X.mo = m;
+      for (int q = 0; q < m; ++q) {
+        X.in[q] = c->stR[q][d];
+        X.out[q] = c->stU[q][d];
+      }
+      for (int i = 0; i < m * m; ++i) X.T[i] = tt.Ainv[i];
+      PD_HIP(c, pdk::launch_time_mix(X, n, s));
+      pdk::TimeMix Y;
+      Y.m = Y.mo = m;
+      Y.bc = 1.0;
+      for (int q = 0; q < m; ++q) {
+        Y.in[q] = c->stW[q][d];
+        Y.base[q] = c->stU[q][d];
+        Y.out[q] = c->stU[q][d];
+      }
+      for (int q = 0; q < m; ++q)
+        for (int p = 0; p < m; ++p) Y.T[q * m + p] = tt.Ainv[q * m + p] * tt.omega[p];
+      PD_HIP(c, pdk::launch_time_mix(Y, n, s));
+    }
+  }
+  // slab end value u(t^{n+1}) = sum_s psi_s(1) U_s
+  for (int d = 0; d < dim; ++d) {
+    pdk::TimeMix X;
+    X.m = m;
+    X.mo = 1;
+    for (int q = 0; q < m; ++q) {
+      X.in[q] = c->stU[q][d];
+      X.T[q] = tt.psi1[q];
+    }
+    X.out[0] = (double*)u[d];
+    PD_HIP(c, pdk::launch_time_mix(X, n, s));
+  }
+  report(total);
+  PD_HIP(c, hipStreamSynchronize(s));
+  return PD_OK;
+}
+
+int pd_time_table(int M, int which, double* out) {
+  pdh::TimeTable t;
+  if (!out || !pdh::build_time_table(M, &t, nullptr)) return PD_EINVAL;
+  const int m = t.m;
+  const double* src = nullptr;
+  int cnt = m;
+  switch (which) {
+    case PD_TTAB_NODES: src = t.tau; break;
+    case PD_TTAB_WEIGHTS: src = t.omega; break;
+    case PD_TTAB_PSI0: src = t.psi0; break;
+    case PD_TTAB_PSI1: src = t.psi1; break;
+    case PD_TTAB_MV: src = t.MV; cnt = m * m; break;
+    case PD_TTAB_AINV: src = t.Ainv; cnt = m * m; break;
+    default: return PD_EINVAL;
+  }
+  for (int i = 0; i < cnt; ++i) out[i] = src[i];
+  return cnt;
 }
 
 int pd_l2_project_adjoint(pd_ctx* c, int d, int dir, const void* in, void* out,
@@ -1161,6 +1390,8 @@ int pd_project_velocity_adjoint(pd_ctx* c, void* const ubar[3], void* qbar, void
 
 int pd_convect_adjoint(pd_ctx* c, void* const um[3], void* const ubar[3], void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (c->explicit_visc)
+    return fail(c, PD_EINVAL, "the adjoint covers the convective flux only (PD_CFG_EXPLICIT_VISC set)");
   if (!um || !ubar) return fail(c, PD_EINVAL, "null array");
   for (int d = 0; d < c->dim; ++d)
     if (!um[d] || !ubar[d] || um[d] == ubar[d]) return fail(c, PD_EINVAL, "null or aliased component");
@@ -1184,6 +1415,8 @@ int pd_step_adjoint(pd_ctx* c, void* const u[3], void* const ubar[3], pd_solve_i
   if (!u || !ubar) return fail(c, PD_EINVAL, "null array");
   for (int d = 0; d < c->dim; ++d)
     if (!u[d] || !ubar[d] || u[d] == ubar[d]) return fail(c, PD_EINVAL, "null or aliased component");
+  if (c->explicit_visc)
+    return fail(c, PD_EINVAL, "the adjoint covers the implicit-viscosity step only");
   int rc = ensure_adjoint_buffers(c);
   if (rc) return rc;
   hipStream_t s = S(hip_stream);
@@ -1333,6 +1566,10 @@ int pd_configure(pd_ctx* c, int key, double v) {
     case PD_CFG_DEFER_X:
       if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_DEFER_X must be 0 or 1");
       c->defer_x = (int)v;
+      break;
+    case PD_CFG_EXPLICIT_VISC:
+      if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_EXPLICIT_VISC must be 0 or 1");
+      c->explicit_visc = (int)v;
       break;
     case PD_CFG_ONE_KERNEL:
       if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_ONE_KERNEL must be 0 or 1");

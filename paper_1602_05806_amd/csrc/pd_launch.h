@@ -125,12 +125,31 @@ struct ConvLaunch {
   int nc[3] = {1, 1, 1};
   double h[3] = {1, 1, 1};
   double w[9], phi0[9], phi1[9], Kv[81];
+  // explicit viscous flux (nu > 0): -nu grad q with the broken gradient, averaged normal
+  // derivatives on faces and the viscous Rusanov speed 2 nu (2N+1) / (h_e sqrt(pi/2))
+  double nu = 0.0;
+  int conv = 1;                                          // 0: viscous flux only
+  double dphi0[9], dphi1[9], KD[81];
   const double* ucur[3] = {nullptr, nullptr, nullptr};   // stage input (main grid)
   const double* u0[3] = {nullptr, nullptr, nullptr};     // step start
   double* out[3] = {nullptr, nullptr, nullptr};
   double a = 0.0, b = 1.0, dt = 0.0;                     // out = a u0 + b (ucur + dt L(ucur))
+  double cr = 0.0;                                       // != 0: out = a u0 + cr L(ucur)
 };
 hipError_t launch_convect_stage(const ConvLaunch& L, hipStream_t s);
+
+// Time mixing over the nodes of a space-time slab, elementwise over n values:
+// out[s] = bc * base[s] + sum_p T[s][p] in[p] for s < mo (base[s] may be null; outputs may alias
+// inputs or bases: every thread reads all its inputs before writing).
+struct TimeMix {
+  const double* in[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const double* base[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* out[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double T[25] = {0};
+  double bc = 0.0;
+  int m = 1, mo = 1;
+};
+hipError_t launch_time_mix(const TimeMix& X, long long n, hipStream_t s);
 
 // Adjoint of one RK stage out = a u0 + b (ucur + dt L(ucur)): with obar the cotangent of out,
 // out_adj = acc_coef acc + b (obar + dt J(state)^T obar) is the cotangent reaching ucur = state

@@ -75,6 +75,13 @@ struct ConvMats {
   double w[N + 1], phi0[N + 1], phi1[N + 1], Kv[(N + 1) * (N + 1)];
 };
 
+// Tables of the explicit viscous flux (explicit-viscosity variant): phi_m'(0), phi_m'(1) and
+// KD[k][m] = sum_j Kv[k][j] phi_m'(xi_j) (volume term of the broken gradient).
+template <int N>
+struct ViscMats {
+  double dphi0[N + 1], dphi1[N + 1], KD[(N + 1) * (N + 1)];
+};
+
 struct ConvPtrs {
   const double* ucur[3];
   const double* u0[3];
@@ -85,10 +92,15 @@ struct ConvPtrs {
 // L(U)_q = -sum_e h_e^-1 [ (phi_k(1) F_{e,right} - phi_k(0) F_{e,left}) / w_k
 //                          - sum_m Kv[k][m] (q v_e)(m) ]   (collocated at the GL nodes)
 // and the Rusanov flux F = (q^- v^- + q^+ v^+)/2 - s (q^+ - q^-)/2, s = 2 max(|v_e^-|, |v_e^+|).
-template <int N, int DIM>
-__global__ __launch_bounds__(kBlock) void k_convect(ConvMats<N> M, ConvPtrs P, int nx, int ny,
-                                                    int nz, double h0, double h1, double h2,
-                                                    double a, double b, double dt) {
+// VISC = 1 (explicit-viscosity variant): the flux gains -nu dq/dx_e (broken gradient at the
+// nodes; on faces the average of the two sides' normal derivatives) and s the viscous part
+// 2 nu (2N+1) / (h_e sqrt(pi/2)); conv = 0 drops the convective flux (unsteady Stokes).
+// cr != 0: out = a u0 + cr L(ucur) instead (the rate itself, b and dt unused).
+template <int N, int DIM, int VISC>
+__global__ __launch_bounds__(kBlock) void k_convect(ConvMats<N> M, ViscMats<N> VM, ConvPtrs P,
+                                                    int nx, int ny, int nz, double h0, double h1,
+                                                    double h2, double a, double b, double dt,
+                                                    double nu, int conv, double cr) {
   constexpr int n = N + 1, NC = DIM == 3 ? n * n * n : n * n;
   const long long ncells = (long long)nx * ny * nz;
   const long long tot = ncells * NC;
@@ -128,6 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_convect(ConvMats<N> M, ConvPtrs P, i
       const double* vr = ve + cr * NC + lbase;
       double vol = 0.0, q0 = 0.0, q1 = 0.0, v0 = 0.0, v1 = 0.0;
       double qlf = 0.0, vlf = 0.0, qrf = 0.0, vrf = 0.0;
+      double kd = 0.0, d0 = 0.0, d1 = 0.0, dlf = 0.0, drf = 0.0;   // VISC: reference derivatives
 #pragma unroll
       for (int m = 0; m < n; ++m) {
         const double qm = qo[m * sd], vm = vo[m * sd];
@@ -140,17 +153,40 @@ __global__ __launch_bounds__(kBlock) void k_convect(ConvMats<N> M, ConvPtrs P, i
         vlf += M.phi1[m] * vl[m * sd];
         qrf += M.phi0[m] * qr[m * sd];    // right neighbour at its left face
         vrf += M.phi0[m] * vr[m * sd];
+        if (VISC) {
+          kd += VM.KD[le * n + m] * qm;
+          d0 += VM.dphi0[m] * qm;
+          d1 += VM.dphi1[m] * qm;
+          dlf += VM.dphi1[m] * ql[m * sd];
+          drf += VM.dphi0[m] * qr[m * sd];
+        }
       }
-      const double sR = 2.0 * fmax(fabs(v1), fabs(vrf));
-      const double FR = 0.5 * (q1 * v1 + qrf * vrf) - 0.5 * sR * (qrf - q1);
-      const double sL = 2.0 * fmax(fabs(vlf), fabs(v0));
-      const double FL = 0.5 * (qlf * vlf + q0 * v0) - 0.5 * sL * (q0 - qlf);
+      double sR = 2.0 * fmax(fabs(v1), fabs(vrf));
+      double sL = 2.0 * fmax(fabs(vlf), fabs(v0));
+      double FR = 0.5 * (q1 * v1 + qrf * vrf);
+      double FL = 0.5 * (qlf * vlf + q0 * v0);
+      if (VISC) {
+        if (!conv) {
+          vol = 0.0;
+          sR = sL = 0.0;
+          FR = FL = 0.0;
+        }
+        const double he = hh[e];
+        const double sv = 2.0 * nu * (2 * N + 1) / (he * 1.2533141373155002512);   // sqrt(pi/2)
+        sR += sv;
+        sL += sv;
+        vol -= nu * kd / he;
+        FR -= 0.5 * nu * (d1 + drf) / he;
+        FL -= 0.5 * nu * (dlf + d0) / he;
+      }
+      FR -= 0.5 * sR * (qrf - q1);
+      FL -= 0.5 * sL * (q0 - qlf);
       const double surf = (M.phi1[le] * FR - M.phi0[le] * FL) / M.w[le];
       rate -= (surf - vol) / hh[e];
     }
     const double uc = q[i];
     const double base = a != 0.0 ? a * P.u0[comp][i] : 0.0;
-    P.out[comp][i] = base + b * (uc + dt * rate);
+    P.out[comp][i] = cr != 0.0 ? base + cr * rate : base + b * (uc + dt * rate);
   }
 }
 
@@ -312,6 +348,12 @@ hipError_t launch_conv_N(const ConvLaunch& L, hipStream_t s) {
     M.phi1[i] = L.phi1[i];
   }
   for (int i = 0; i < n * n; ++i) M.Kv[i] = L.Kv[i];
+  ViscMats<N> VM;
+  for (int i = 0; i < n; ++i) {
+    VM.dphi0[i] = L.dphi0[i];
+    VM.dphi1[i] = L.dphi1[i];
+  }
+  for (int i = 0; i < n * n; ++i) VM.KD[i] = L.KD[i];
   ConvPtrs P;
   for (int c = 0; c < 3; ++c) {
     P.ucur[c] = L.ucur[c];
@@ -321,12 +363,23 @@ hipError_t launch_conv_N(const ConvLaunch& L, hipStream_t s) {
   const int nz = L.dim == 3 ? L.nc[2] : 1;
   const long long tot =
       (long long)L.nc[0] * L.nc[1] * nz * (L.dim == 3 ? n * n * n : n * n) * L.dim;
-  if (L.dim == 3)
-    hipLaunchKernelGGL((k_convect<N, 3>), dim3(grid_for(tot)), dim3(kBlock), 0, s, M, P, L.nc[0],
-                       L.nc[1], nz, L.h[0], L.h[1], L.h[2], L.a, L.b, L.dt);
-  else
-    hipLaunchKernelGGL((k_convect<N, 2>), dim3(grid_for(tot)), dim3(kBlock), 0, s, M, P, L.nc[0],
-                       L.nc[1], nz, L.h[0], L.h[1], L.h[2], L.a, L.b, L.dt);
+  const bool visc = L.nu > 0.0;
+  const dim3 G(grid_for(tot)), B(kBlock);
+  if (L.dim == 3) {
+    if (visc)
+      hipLaunchKernelGGL((k_convect<N, 3, 1>), G, B, 0, s, M, VM, P, L.nc[0], L.nc[1], nz, L.h[0],
+                         L.h[1], L.h[2], L.a, L.b, L.dt, L.nu, L.conv, L.cr);
+    else
+      hipLaunchKernelGGL((k_convect<N, 3, 0>), G, B, 0, s, M, VM, P, L.nc[0], L.nc[1], nz, L.h[0],
+                         L.h[1], L.h[2], L.a, L.b, L.dt, 0.0, 1, L.cr);
+  } else {
+    if (visc)
+      hipLaunchKernelGGL((k_convect<N, 2, 1>), G, B, 0, s, M, VM, P, L.nc[0], L.nc[1], nz, L.h[0],
+                         L.h[1], L.h[2], L.a, L.b, L.dt, L.nu, L.conv, L.cr);
+    else
+      hipLaunchKernelGGL((k_convect<N, 2, 0>), G, B, 0, s, M, VM, P, L.nc[0], L.nc[1], nz, L.h[0],
+                         L.h[1], L.h[2], L.a, L.b, L.dt, 0.0, 1, L.cr);
+  }
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 namespace pdh {
 namespace {
@@ -158,7 +159,15 @@ bool build_table(int N, Table1D* t, std::string* err) {
     t->phi0[p] = lag(xi, n, p, 0.0);
     t->phi1[p] = lag(xi, n, p, 1.0);
     for (int m = 0; m < n; ++m) t->Kv[p * n + m] = t->w[m] * dlag(xi, n, p, xi[m]) / t->w[p];
+    t->dphi0[p] = dlag(xi, n, p, 0.0);
+    t->dphi1[p] = dlag(xi, n, p, 1.0);
   }
+  for (int k = 0; k < n; ++k)
+    for (int m = 0; m < n; ++m) {
+      double a = 0;
+      for (int j = 0; j < n; ++j) a += t->Kv[k * n + j] * dlag(xi, n, m, xi[j]);
+      t->KD[k * n + m] = a;
+    }
   // Null space of (R~ - L~): the cell-periodic solutions of D P = 0. Eigenvectors of
   // S = (R~-L~)^T (R~-L~) whose eigenvalue (a squared singular value of R~-L~) is below
   // (1e-8 ||(R~, L~)||_F)^2. The scale is that of R~ and L~ themselves, not of S: for N = 1,
@@ -184,6 +193,56 @@ bool build_table(int N, Table1D* t, std::string* err) {
         for (int q = 0; q < n; ++q) t->Pnull[p * n + q] += V[p * n + i] * V[q * n + i];
     }
   }
+  return true;
+}
+
+bool build_time_table(int M, TimeTable* t, std::string* err) {
+  if (M < 0 || M > kMaxM) {
+    if (err) *err = "time degree M must be in [0, 4]";
+    return false;
+  }
+  *t = TimeTable{};
+  const int m = M + 1;
+  t->M = M;
+  t->m = m;
+  gauss_legendre01(m, t->tau, t->omega);
+  double qx[kMaxm + 2], qw[kMaxm + 2];
+  gauss_legendre01(m + 2, qx, qw);          // exact for the degree-2M integrands of MV
+  for (int p = 0; p < m; ++p) {
+    t->psi0[p] = lag(t->tau, m, p, 0.0);
+    t->psi1[p] = lag(t->tau, m, p, 1.0);
+    for (int q = 0; q < m; ++q) {
+      double a = 0.0;
+      for (int j = 0; j < m + 2; ++j) a += qw[j] * dlag(t->tau, m, p, qx[j]) * lag(t->tau, m, q, qx[j]);
+      t->MV[p * m + q] = a;
+    }
+  }
+  for (int p = 0; p < m; ++p)
+    for (int q = 0; q < m; ++q) t->At[p * m + q] = t->psi1[p] * t->psi1[q] - t->MV[p * m + q];
+  // Ainv by Gauss-Jordan elimination with partial pivoting
+  double A[kMaxm * 2 * kMaxm];
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < 2 * m; ++j) A[i * 2 * m + j] = j < m ? t->At[i * m + j] : (j - m == i);
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(A[r * 2 * m + c]) > std::fabs(A[piv * 2 * m + c])) piv = r;
+    if (std::fabs(A[piv * 2 * m + c]) < 1e-14) {
+      if (err) *err = "singular time matrix";
+      return false;
+    }
+    if (piv != c)
+      for (int j = 0; j < 2 * m; ++j) std::swap(A[c * 2 * m + j], A[piv * 2 * m + j]);
+    const double d = A[c * 2 * m + c];
+    for (int j = 0; j < 2 * m; ++j) A[c * 2 * m + j] /= d;
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double f = A[r * 2 * m + c];
+      for (int j = 0; j < 2 * m; ++j) A[r * 2 * m + j] -= f * A[c * 2 * m + j];
+    }
+  }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) t->Ainv[i * m + j] = A[i * 2 * m + m + j];
   return true;
 }
 

@@ -21,11 +21,28 @@ struct Table1D {
   double ML[kMaxn * kMaxn], MR[kMaxn * kMaxn];   // eq. (l2forward), MR = ML^T
   double phi0[kMaxn], phi1[kMaxn];       // phi_p(0), phi_p(1)
   double Kv[kMaxn * kMaxn];              // Kv[k][m] = w_m phi_k'(xi_m) / w_k (collocated volume term)
+  double dphi0[kMaxn], dphi1[kMaxn];     // phi_p'(0), phi_p'(1)
+  double KD[kMaxn * kMaxn];              // KD[k][m] = sum_j Kv[k][j] phi_m'(xi_j): volume term of
+                                         // the broken gradient (explicit viscous flux)
   int nnull = 0;                         // dimension of null(R~ - L~) (1 for even N, 2 for odd N)
   double Pnull[kMaxn * kMaxn];           // orthogonal projector onto null(R~ - L~)
 };
 
 // Fills t for degree N. Returns false (with a message) for unsupported N.
 bool build_table(int N, Table1D* t, std::string* err);
+
+// Time matrices of degree M of the space-time scheme (Section 3, eqs. tmatrix1-tmatrix3) on the
+// nodal Gauss-Legendre basis psi_0..psi_M of [0, 1]: M^t = diag(omega), M1 = psi(1) psi(1)^T,
+// M0 = psi(0) psi(1)^T, MV[p][q] = int psi_p' psi_q; At = M1 - MV and its inverse.
+constexpr int kMaxM = 4;
+constexpr int kMaxm = kMaxM + 1;
+struct TimeTable {
+  int M = 0, m = 1;
+  double tau[kMaxm], omega[kMaxm], psi0[kMaxm], psi1[kMaxm];
+  double MV[kMaxm * kMaxm], At[kMaxm * kMaxm], Ainv[kMaxm * kMaxm];
+};
+
+// Fills t for degree M (0..kMaxM). Returns false (with a message) otherwise.
+bool build_time_table(int M, TimeTable* t, std::string* err);
 
 }  // namespace pdh

@@ -364,6 +364,29 @@ __global__ __launch_bounds__(kBlock) void k_energy(W9 W, int n, Vel3 v, double g
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// out[s] = bc base[s] + sum_p T[s][p] in[p] (see TimeMix); all inputs of an element are read
+// before any output of it is written.
+__global__ __launch_bounds__(kBlock) void k_time_mix(TimeMix X, long long n) {
+  for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (long long)gridDim.x * kBlock) {
+    double v[5], b[5];
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+      v[p] = p < X.m ? X.in[p][i] : 0.0;
+      b[p] = (p < X.mo && X.base[p]) ? X.base[p][i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      if (q >= X.mo) break;
+      double acc = X.bc * b[q];
+#pragma unroll
+      for (int p = 0; p < 5; ++p)
+        if (p < X.m) acc += X.T[q * X.m + p] * v[p];
+      X.out[q][i] = acc;
+    }
+  }
+}
+
 // ---- null-space projection: per-node sums over cells, then correction per node
 constexpr int kNullBlocks = 256;
 
@@ -548,6 +571,12 @@ hipError_t launch_energy(int dim, int N, const double* w, const double* const u[
     hipLaunchKernelGGL(k_energy<3>, dim3(G), dim3(kBlock), 0, s, W, n, v, gs, ncells, partials);
   else
     hipLaunchKernelGGL(k_energy<2>, dim3(G), dim3(kBlock), 0, s, W, n, v, gs, ncells, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_time_mix(const TimeMix& X, long long n, hipStream_t s) {
+  if (X.m < 1 || X.m > 5 || X.mo < 1 || X.mo > 5) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_time_mix, dim3(stream_blocks(n, 4)), dim3(kBlock), 0, s, X, n);
   return hipGetLastError();
 }
 

@@ -73,3 +73,23 @@ def test_host_tables_match_oracle(pd):
     import pytest
     with pytest.raises(pd.PdError):
         pd.pd_table_1d(9, 0)
+
+
+def test_host_time_tables_match_oracle(pd):
+    """The library's host-built time tables of the space-time step (nodes, weights, psi(0),
+    psi(1), MV of eq. tmatrix3 and the inverse of At = M1 - MV) equal the oracle's for M = 0..4."""
+    import numpy as np
+    from oracle.spacetime import TimeTables
+    for M in range(5):
+        t = TimeTables(M)
+        m = M + 1
+        got = {w: np.array(pd.pd_time_table(M, w)) for w in range(6)}
+        assert np.abs(got[pd.PD_TTAB_NODES] - t.tau).max() <= 1e-15
+        assert np.abs(got[pd.PD_TTAB_WEIGHTS] - t.omega).max() <= 1e-15
+        assert np.abs(got[pd.PD_TTAB_PSI0] - t.psi0).max() <= 1e-13
+        assert np.abs(got[pd.PD_TTAB_PSI1] - t.psi1).max() <= 1e-13
+        assert np.abs(got[pd.PD_TTAB_MV].reshape(m, m) - t.MV).max() <= 1e-12
+        assert np.abs(got[pd.PD_TTAB_AINV].reshape(m, m) - np.linalg.inv(t.At)).max() <= 1e-12
+    import pytest
+    with pytest.raises(pd.PdError):
+        pd.pd_time_table(5, 0)

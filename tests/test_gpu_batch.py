@@ -279,7 +279,9 @@ def test_batch_full_workload(pd):
     """The 64-problem workload (sides 45..253, N 2..8, about 77M DoFs) solved in FP32 with FP64
     residual replacement to 1e-10: every problem's FP64 residual b - A x recomputed by the oracle
     (matrix-free, direction by direction) is <= 1e-10 ||b||, x is orthogonal to the null space,
-    and the problems with at most 80 cells per side match the oracle's direct solution."""
+    and the problems with at most 80 cells per side match the oracle's direct solution to 1e-9
+    (white-noise right-hand sides at rtol 1e-10: the residual bounds the error only up to the
+    condition number; measured 6.7e-11 - 3.3e-10)."""
     import torch
     specs = synthetic.batch_problems(seed=4)
     probs = [(p["side"], p["side"], 1.0, 1.0, p["N"]) for p in specs]
@@ -325,5 +327,5 @@ def test_batch_full_workload(pd):
             ref = FastDiag(g).solve(Bt, 0.0, DT)
             err = mass_norm(g, X - ref) / mass_norm(g, ref)
             print(f"  problem {j} {p}: rel res {rel:.2e} err {err:.2e}", flush=True)
-            assert err <= 1e-6
+            assert err <= 1e-9          # measured 6.7e-11 - 3.3e-10 at rtol 1e-10
     B.close()
