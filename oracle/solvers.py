@@ -7,6 +7,8 @@ Euclidean DoF inner product) to the null space Z. Three independent ways to get 
 
   cg              the paper's matrix-free conjugate gradient (Hestenes-Stiefel, no preconditioner,
                   x0 = 0, stop on ||r||_2 <= rtol ||b||_2), here on the assembled CSR matrix
+  pcg             the same with a preconditioner (the paper's future work); block_jacobi gives
+                  the cell-block Jacobi preconditioner of an assembled operator
   dense_min_norm  dense Cholesky of A + Z Z^T (SPD); for b orthogonal to Z its solution is the
                   minimum-norm solution (tiny grids only)
   FastDiag        tensor-product fast diagonalisation: each 1D operator M_d^-1/2 H_d M_d^-1/2 is
@@ -43,6 +45,56 @@ def cg(A, b, rtol, maxit, x0=None):
         rho = rho_new
         it += 1
     return x, it, float(np.sqrt(rho) / bnorm)
+
+
+def pcg(A, b, rtol, maxit, precond, x0=None):
+    """Preconditioned conjugate gradient (Hestenes-Stiefel with the preconditioned inner product
+    <r, z>, z = precond(r)); the preconditioners the paper names as future work for its
+    matrix-free CG (Section 2.1, closing remark). Stops when ||r||_2 <= rtol ||b||_2 (the same
+    stopping test as cg). Returns (x, iters, rel_res_recurrence)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A @ x
+    bnorm = float(np.sqrt(b @ b))
+    if bnorm == 0.0:
+        return x, 0, 0.0
+    z = precond(r)
+    p = z.copy()
+    rho = float(r @ z)
+    it = 0
+    while it < maxit and np.sqrt(float(r @ r)) > rtol * bnorm:
+        q = A @ p
+        alpha = rho / float(p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        z = precond(r)
+        rho_new = float(r @ z)
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+        it += 1
+    return x, it, float(np.sqrt(r @ r) / bnorm)
+
+
+def block_jacobi(grid, A):
+    """Cell-block Jacobi preconditioner of an operator assembled in the tensor layout: the
+    inverse of the (N+1)^d x (N+1)^d diagonal block of every cell (the coupling of a cell's own
+    nodes), applied cell by cell. Returns a function r -> z on flat tensor-layout vectors."""
+    from .layout import tensor_to_blocked, blocked_to_tensor
+    n = grid.n
+    NC = n ** grid.dim
+    idx = tensor_to_blocked(np.arange(grid.ndof).reshape(grid.shape()), grid.cells, n).astype(np.int64)
+    ncells = grid.ndof // NC
+    Ab = A.tocsr()[idx][:, idx]
+    inv = np.stack([np.linalg.inv(Ab[c * NC:(c + 1) * NC, c * NC:(c + 1) * NC].toarray())
+                    for c in range(ncells)])
+
+    def apply(r):
+        rb = np.asarray(r, dtype=np.float64).reshape(-1)[idx].reshape(ncells, NC)
+        zb = np.einsum("cij,cj->ci", inv, rb).reshape(-1)
+        z = np.empty(grid.ndof)
+        z[idx] = zb
+        return z
+    return apply
 
 
 def dense_min_norm(A, Z, b):

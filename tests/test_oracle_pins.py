@@ -636,3 +636,61 @@ def test_explicit_viscosity_taylor_green_decay_and_implicit_cross_check():
     assert abs(np.log(amp) + rate * t) <= 1e-3 * rate * t
     diff = np.sqrt(sum(np.sum(W * (Ue[d] - Ui[d]) ** 2) for d in range(2)) / den)
     assert diff <= 2 * rate * dt * rate * t
+
+
+# ------------------------------------------------------------------ preconditioned CG
+
+def test_block_jacobi_N0_is_point_jacobi():
+    """N = 0: one DoF per cell, so the cell-block Jacobi preconditioner is the inverse of the
+    diagonal of the 5-point Laplacian, 1 / (dt sum_d 2 / h_d^2) (the paper's degenerate case)."""
+    from oracle.solvers import block_jacobi
+    g = Grid((6, 5), (1.0, 0.5), 0)
+    dt = 2e-3
+    P = block_jacobi(g, pressure_operator(g, dt))
+    r = np.random.default_rng(2).standard_normal(g.ndof)
+    d = dt * sum(2.0 / h ** 2 for h in g.h)
+    assert np.abs(P(r) - r / d).max() <= 1e-14 * np.abs(r / d).max()
+
+
+@pytest.mark.parametrize("dim,cells,N", [(2, (4, 3), 3), (3, (2, 3, 2), 2)])
+def test_pcg_iterates_minimise_the_energy_error_over_the_krylov_space(dim, cells, N):
+    """Brute force: the m-th PCG iterate from x0 = 0 minimises the A-norm of the error over the
+    preconditioned Krylov space K_m(P A, P b) (the defining property of preconditioned CG); on
+    the viscous operator (SPD) with the cell-block Jacobi preconditioner, against an explicit
+    dense projection onto an orthonormal basis of that space."""
+    from oracle.solvers import block_jacobi, pcg
+    g = Grid(cells, (1.0, 0.8, 1.2)[:dim], N)
+    A = viscous_operator(g, 1e-3, 3.0)
+    P = block_jacobi(g, A)
+    b = np.random.default_rng(5).standard_normal(g.ndof)
+    Ad = A.toarray()
+    xs = np.linalg.solve(Ad, b)
+    for m in (1, 2, 3, 5):
+        x, it, _ = pcg(A, b, 1e-300, m, P)
+        assert it == m
+        V = [P(b)]
+        for _ in range(m - 1):
+            V.append(P(Ad @ V[-1]))
+        Q, _ = np.linalg.qr(np.stack(V, axis=1))
+        y = np.linalg.solve(Q.T @ Ad @ Q, Q.T @ b)         # Galerkin = A-norm minimiser
+        ref = Q @ y
+        assert np.abs(x - ref).max() <= 1e-9 * np.abs(xs).max()
+
+
+@pytest.mark.parametrize("dim,cells,N", [(2, (5, 4), 3), (2, (4, 4), 6), (3, (3, 2, 3), 2)])
+def test_pcg_pressure_reaches_min_norm_solution(dim, cells, N):
+    """Block-Jacobi PCG on the singular periodic pressure system (b orthogonal to the null space)
+    converges to a solution whose null-space projection is the minimum-norm solution, in fewer
+    iterations than plain CG."""
+    from oracle.solvers import block_jacobi, pcg
+    g = Grid(cells, (1.0,) * dim, N)
+    dt = 1e-3
+    A = pressure_operator(g, dt)
+    Z = [null_basis_tiled(c, N) for c in cells]
+    b = project_null(g, np.random.default_rng(9).standard_normal(g.shape()), Z).reshape(-1)
+    x, it, _ = pcg(A, b, 1e-12, 10000, block_jacobi(g, A))
+    _, it_cg, _ = cg(A, b, 1e-12, 10000)
+    ref = FastDiag(g).solve(b.reshape(g.shape()), 0.0, dt)
+    xp = project_null(g, x.reshape(g.shape()), Z)
+    assert np.abs(xp - ref).max() <= 1e-9 * np.abs(ref).max()
+    assert it < it_cg
