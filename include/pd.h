@@ -144,6 +144,17 @@ int pd_project_velocity(pd_ctx* ctx, const void* q, void* const u[3], void* hip_
  * 1D weak gradient: 1 per direction for even N, 2 for odd N). In place. */
 int pd_project_null(pd_ctx* ctx, int prec, void* v, void* hip_stream);
 
+/* Allocation-free variant of pd_project_null, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, kernels and result (bit-identical to pd_project_null), but the projection's scratch
+ * (per-block node sums and the correction) lives in a fixed device array of the library,
+ * 256 x 729 + 729 doubles (1.5 MB, the maximum for N <= 8 in 3D), one copy per device held
+ * until the process ends; the call allocates nothing and calls no allocating routine. Every call
+ * on a device shares that device's array: calls that overlap on one device (several streams or
+ * host threads) race and must be serialised by the caller. PD_EINVAL for (N+1)^dim beyond the
+ * array (not reachable for N <= 8). */
+int pd_project_null_noalloc(pd_ctx* ctx, int prec, void* v, void* hip_stream);
+
 /* L2 projections between a dual grid and the main grid along direction d (eq. l2forward and
  * eq. l2backward): dir = 0: main = pi_{*->#}(dual); dir = 1: dual = pi_{#->*}(main). FP64. */
 int pd_l2_project(pd_ctx* ctx, int d, int dir, const void* in, void* out, void* hip_stream);

@@ -40,7 +40,7 @@ EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "
             "pd_cg_solve", "pd_rhs_div", "pd_project_velocity", "pd_project_null",
             "pd_l2_project", "pd_convect", "pd_step", "pd_configure", "pd_timing",
             "pd_l2_project_adjoint", "pd_rhs_div_adjoint", "pd_project_velocity_adjoint",
-            "pd_convect_adjoint", "pd_step_adjoint", "pd_kinetic_energy", "pd_step_st",
+            "pd_convect_adjoint", "pd_step_adjoint", "pd_kinetic_energy", "pd_project_null_noalloc", "pd_step_st",
             "pd_time_table",
             "pd_batch_setup", "pd_batch_destroy", "pd_batch_last_error", "pd_batch_layout",
             "pd_batch_variants", "pd_batch_configure", "pd_batch_cg_solve"]
@@ -74,6 +74,7 @@ _lib.pd_cg_solve.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c
 _lib.pd_rhs_div.argtypes = [_vp, ctypes.POINTER(_vp), _vp, _vp]
 _lib.pd_project_velocity.argtypes = [_vp, _vp, ctypes.POINTER(_vp), _vp]
 _lib.pd_project_null.argtypes = [_vp, ctypes.c_int, _vp, _vp]
+_lib.pd_project_null_noalloc.argtypes = [_vp, ctypes.c_int, _vp, _vp]
 _lib.pd_l2_project.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
 _lib.pd_convect.argtypes = [_vp, ctypes.POINTER(_vp), _vp]
 _lib.pd_step.argtypes = [_vp, ctypes.POINTER(_vp), _vp, ctypes.POINTER(pd_solve_info), _vp]
@@ -249,6 +250,11 @@ def pd_project_velocity(ctx, q, u, stream=None):
 def pd_project_null(ctx, prec, v, stream=None):
     _check(ctx, _lib.pd_project_null(ctx.handle, prec, _ptr(v, ctx.ndof, _dtype(prec)),
                                      ctypes.c_void_p(_stream(stream))))
+
+
+def pd_project_null_noalloc(ctx, prec, v, stream=None):
+    _check(ctx, _lib.pd_project_null_noalloc(ctx.handle, prec, _ptr(v, ctx.ndof, _dtype(prec)),
+                                             ctypes.c_void_p(_stream(stream))))
 
 
 def pd_l2_project(ctx, d, direction, src, dst, stream=None):

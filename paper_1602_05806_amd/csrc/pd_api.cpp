@@ -1009,6 +1009,8 @@ int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int
   if (he == hipSuccess) he = hipMemsetAsync(c->st, 0, sizeof(CgState), s);
   if (he == hipSuccess) he = hipMemsetAsync(c->st2, 0, sizeof(CgState), s);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
+  double* scratch_dev = nullptr;   // fixed scratch of pd_project_null_noalloc on this device
+  if (he == hipSuccess) he = pdk::noalloc_scratch(&scratch_dev);
   if (he != hipSuccess) {
     g_setup_err = std::string("setup: ") + hipGetErrorString(he);
     pd_destroy(c);
@@ -1134,6 +1136,18 @@ int pd_project_null(pd_ctx* c, int prec, void* v, void* hip_stream) {
   if (prec != PD_FP64 && prec != PD_FP32) return fail(c, PD_EINVAL, "prec must be PD_FP64 or PD_FP32");
   c->last_stream = S(hip_stream);
   return project_null(c, prec == PD_FP32, v, S(hip_stream));
+}
+
+int pd_project_null_noalloc(pd_ctx* c, int prec, void* v, void* hip_stream) {
+  if (!c) return PD_EINVAL;
+  if (!v) return fail(c, PD_EINVAL, "null array");
+  if (prec != PD_FP64 && prec != PD_FP32) return fail(c, PD_EINVAL, "prec must be PD_FP64 or PD_FP32");
+  if ((size_t)(256 + 1) * c->NC * sizeof(double) > pdk::noalloc_scratch_bytes())
+    return fail(c, PD_EINVAL, "pd_project_null_noalloc: (N+1)^dim exceeds the fixed scratch");
+  c->last_stream = S(hip_stream);
+  PD_HIP(c, pdk::launch_project_null_noalloc(prec == PD_FP32, v, c->ncells, c->dim, c->n,
+                                             c->tab.Pnull, S(hip_stream)));
+  return PD_OK;
 }
 
 int pd_l2_project(pd_ctx* c, int d, int dir, const void* in, void* out, void* hip_stream) {

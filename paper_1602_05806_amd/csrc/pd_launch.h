@@ -104,6 +104,15 @@ hipError_t launch_project_null(bool fp32, void* v, long long ncells, int dim, in
                                const double* Pnull_host, double* part, double* corr,
                                hipStream_t s);
 
+// The same projection with its scratch (node-sum partials and correction) in a fixed device
+// array of the library instead of caller- or context-owned memory: no allocation. Calls that
+// overlap on one device race on that array.
+hipError_t launch_project_null_noalloc(bool fp32, void* v, long long ncells, int dim, int n,
+                                       const double* Pnull_host, hipStream_t s);
+// device address of the fixed scratch array on the current device (looked up once per device)
+hipError_t noalloc_scratch(double** out);
+size_t noalloc_scratch_bytes();
+
 // ---- line operators and convection (pd_ops.hip)
 struct LineLaunch {
   int dim = 2, N = 0;

@@ -5,6 +5,7 @@
 // repeated runs give bit-identical scalars).
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "pd_device.h"
@@ -442,6 +443,49 @@ __global__ __launch_bounds__(kBlock) void k_sub_nodes(T* __restrict__ v, long lo
 }
 
 }  // namespace
+
+// Scratch of the allocation-free null-space projection: the node-sum partials of the k_node_sums
+// blocks (kNullBlocks rows of at most kMaxNC doubles) followed by the correction (kMaxNC
+// doubles): 1,499,904 bytes, one copy per device for the life of the process. Host code never
+// uses the name `scratch` as an address (on the host it is a stand-in symbol); the device
+// address comes from hipGetSymbolAddress, once per device with that device current.
+constexpr size_t kNoAllocParts = (size_t)kNullBlocks * kMaxNC;
+constexpr size_t kNoAllocDoubles = kNoAllocParts + kMaxNC;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices];
+}  // namespace
+
+hipError_t noalloc_scratch(double** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+size_t noalloc_scratch_bytes() { return kNoAllocDoubles * sizeof(double); }
+
+hipError_t launch_project_null_noalloc(bool fp32, void* v, long long ncells, int dim, int n,
+                                       const double* Pnull_host, hipStream_t s) {
+  const int NC = dim == 3 ? n * n * n : n * n;
+  if (NC > kMaxNC) return hipErrorInvalidValue;
+  double* base = nullptr;
+  hipError_t e = noalloc_scratch(&base);
+  if (e != hipSuccess) return e;
+  return launch_project_null(fp32, v, ncells, dim, n, Pnull_host, base, base + kNoAllocParts, s);
+}
 
 unsigned stream_grid(long long n) { return stream_blocks(n, 4); }
 
