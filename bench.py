@@ -374,9 +374,10 @@ def error_solves(pd, torch, ctx, cfg, u0, wl, outdir):
     import synthetic
     white = torch.tensor(synthetic.random_rhs(17, ctx.ndof), dtype=torch.float64, device="cuda")
     reports = {}
-    for rhs_name, rhs in (("workload_rhs", b), ("white_rhs", white)):
+    for rhs_name, rhs in (("workload_rhs", b), ("white_rhs", white), ("workload_rhs_pcg", b)):
+        pd.pd_configure(ctx, pd.PD_CFG_PRECOND, 1 if rhs_name.endswith("pcg") else 0)
         for prec_name, prec in (("fp64", pd.PD_FP64), ("fp32_refine64", pd.PD_FP32_REFINE64)):
-            rtol = cfg["rtol"] if rhs_name == "workload_rhs" else MATCHED_WHITE_RTOL[wl][prec_name]
+            rtol = MATCHED_WHITE_RTOL[wl][prec_name] if rhs_name == "white_rhs" else cfg["rtol"]
             x = torch.zeros_like(rhs)
             pd.pd_cg_solve(ctx, pd.PD_OP_PRESSURE, prec, rhs, x, rtol, 400000)   # warm-up
             x.zero_()
@@ -388,6 +389,7 @@ def error_solves(pd, torch, ctx, cfg, u0, wl, outdir):
             reports[(rhs_name, prec_name)] = dict(rtol=rtol, iters=info["iters"], ms=info["ms"],
                                                   rel_res_true=info["rel_res_true"], path=path)
             del x
+    pd.pd_configure(ctx, pd.PD_CFG_PRECOND, 0)
     del b, white
     return reports
 
@@ -419,9 +421,12 @@ def errors(cfg, paths):
     for kind in ("workload_rhs", "white_rhs"):
         ref = fd.solve(rhs[kind], 0.0, cfg["dt"])
         nref = np.sqrt(np.sum(W * ref ** 2))
-        for prec in ("fp64", "fp32_refine64"):
-            X = layout.blocked_to_tensor(np.load(paths[kind + "|" + prec]), cells, N + 1)
-            out[kind + "|" + prec] = float(np.sqrt(np.sum(W * (X - ref) ** 2)) / nref)
+        for sol in (kind, kind + "_pcg"):
+            for prec in ("fp64", "fp32_refine64"):
+                if sol + "|" + prec not in paths:
+                    continue
+                X = layout.blocked_to_tensor(np.load(paths[sol + "|" + prec]), cells, N + 1)
+                out[sol + "|" + prec] = float(np.sqrt(np.sum(W * (X - ref) ** 2)) / nref)
     return out
 """
 
@@ -459,7 +464,7 @@ def workload_line(pd, torch, wl, args, steps, warmup, outdir):
     u = initial_state(pd, ctx, cfg, torch)
     p = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
     res = time_steps(pd, torch, ctx, cfg, u, p, steps, warmup)
-    reports = error_solves(pd, torch, ctx, cfg, u, wl, outdir)
+    reports = {} if args.no_check else error_solves(pd, torch, ctx, cfg, u, wl, outdir)
     ndof = ctx.ndof
     ctx.close()
     del u, p
@@ -520,6 +525,14 @@ def attach_errors(summary, reports, checked):
             for k in ("fp64", "fp32_refine64")))
     block["workload_rhs"]["kind"] = ("b = sum_d B_d U0_d of the workload's seeded initial "
                                      "velocity, both paths at the timed rtol")
+    pc, base = block.get("workload_rhs_pcg"), block["workload_rhs"]
+    if pc is not None:
+        pc["kind"] = ("the workload right-hand side with the cell-block Jacobi preconditioned CG "
+                      "(PD_CFG_PRECOND) at the timed rtol")
+        for k in ("fp64", "fp32_refine64"):
+            pc[k]["speedup_vs_unpreconditioned"] = base[k]["solve_ms"] / pc[k]["solve_ms"]
+        pc["speedup_fp32_refine64_pcg_vs_fp64_cg"] = (base["fp64"]["solve_ms"] /
+                                                      pc["fp32_refine64"]["solve_ms"])
     block["white_rhs"]["kind"] = ("standard-normal b (seed 17), each path at the tolerance it "
                                   "needs for the 1e-10 error target")
     block["error_measure"] = "mass-weighted relative L2 against the oracle's minimum-norm solution"
@@ -540,6 +553,10 @@ def main():
                     help="skip the oracle legs (CPU baseline and the error check)")
     ap.add_argument("--steps3d", type=int, default=3,
                     help="timed steps of the 3D roofline workload in the default invocation")
+    ap.add_argument("--single", action="store_true",
+                    help="time only --workload (the default invocation also times the 3D one)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the error solves and the oracle legs (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
@@ -571,7 +588,10 @@ def main():
         bench_adjoint(args, pd, torch)
         return
     main_wl = args.workload
-    extra = [w for w in DEFAULT_WORKLOADS if w != main_wl] if main_wl == DEFAULT_WORKLOADS[0] else []
+    extra = ([w for w in DEFAULT_WORKLOADS if w != main_wl]
+             if main_wl == DEFAULT_WORKLOADS[0] and not args.single else [])
+    if args.no_check:
+        args.no_cpu = True
     with tempfile.TemporaryDirectory(prefix="pd_bench_") as outdir:
         cfg, s_main, rep_main = workload_line(pd, torch, main_wl, args, args.steps, args.warmup,
                                               outdir)
@@ -581,14 +601,17 @@ def main():
             others.append((wl,) + workload_line(pd, torch, wl, args, args.steps3d, 1, outdir))
         copy_gbs = device_copy_gbs(torch)
         checks = [(cfg, main_wl, rep_main)] + [(c, wl, r) for wl, c, s, r in others]
-        if args.no_cpu:
+        if args.no_check:
+            base, errs = None, None
+        elif args.no_cpu:
             base, errs = None, {wl: (None, "skipped (--no-cpu)") for _, wl, _ in checks}
         else:
             print("bench.py: oracle legs", file=sys.stderr, flush=True)
             base, errs = cpu_leg(cfg, checks)
-        attach_errors(s_main, rep_main, errs[main_wl])
-        for wl, c, s, r in others:
-            attach_errors(s, r, errs[wl])
+        if errs is not None:
+            attach_errors(s_main, rep_main, errs[main_wl])
+            for wl, c, s, r in others:
+                attach_errors(s, r, errs[wl])
     # roofline: the fused FP64 operator kernel of the workload that streams from HBM (the 3D one
     # when the default invocation times it), else of the timed workload itself
     hbm = next((s for wl, c, s, r in others if wl.startswith("rand3d")), s_main)
@@ -623,7 +646,7 @@ def main():
         "roofline": roof,
         "fp64": {k: v for k, v in f64.items() if k not in ("value", "unit", "ms_per_step")},
         "fp32_refine64": s_main["fp32_refine64"],
-        "error_vs_oracle": s_main["error_vs_oracle"],
+        "error_vs_oracle": s_main.get("error_vs_oracle"),
         "roofline_2d_infinity_cache_resident": {
             "workload": s_main["workload"], "kernel": "k_apply2d (fused CG form, FP64)",
             "note": "FP64 CG working set ~128 MB, held in the 256 MB Infinity Cache",

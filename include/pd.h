@@ -280,6 +280,15 @@ int pd_kinetic_energy(pd_ctx* ctx, void* const u[3], double gscale, void* const 
  *   PD_CFG_DEFER_X       where CG iteration k's x += alpha_k p_k is made: 1 (default) = in the
  *                        operator kernel of iteration k + 1 (it reads p_k anyway; 9 instead of
  *                        10 vector words per DoF and iteration), 0 = in the update kernel
+ *   PD_CFG_PRECOND       1 = preconditioned CG in pd_cg_solve, pd_step and pd_step_st (both
+ *                        precisions, both operators; the paper names preconditioning as future
+ *                        work for its matrix-free CG, end of Section 2.1): z = P r with P the
+ *                        cell-block Jacobi preconditioner, the inverse of each cell's diagonal
+ *                        (N+1)^d x (N+1)^d block of the operator, applied in the generalised
+ *                        eigenbasis of the 1D blocks (C, M) (tensor products of (N+1) x (N+1)
+ *                        transforms); beta = <r', z'> / <r, z>; the stopping test stays on
+ *                        ||r||_2. Allocates z in both precisions on first use. The one-kernel form
+ *                        is not used with it. 0 (default) = the paper's unpreconditioned CG.
  *   PD_CFG_EXPLICIT_VISC 1 = the explicit-viscosity variant of Section 2.2: the viscous flux
  *                        -nu grad q is part of the explicit TVD-RK3 step of pd_step and pd_convect
  *                        (broken gradient at the nodes, averaged normal derivatives on faces,
@@ -302,7 +311,7 @@ enum {
   PD_CFG_STEP_PREC = 0, PD_CFG_P_RTOL = 1, PD_CFG_V_RTOL = 2, PD_CFG_MAXIT = 3,
   PD_CFG_CONVECTION = 4, PD_CFG_RU_FACTOR = 5, PD_CFG_TIMING = 6, PD_CFG_CHECK_EVERY = 7,
   PD_CFG_KZ = 8, PD_CFG_TILES_PER_WG = 9, PD_CFG_PREFETCH = 10, PD_CFG_TILE_VARIANT = 11,
-  PD_CFG_DEFER_X = 12, PD_CFG_ONE_KERNEL = 13, PD_CFG_EXPLICIT_VISC = 14
+  PD_CFG_DEFER_X = 12, PD_CFG_ONE_KERNEL = 13, PD_CFG_EXPLICIT_VISC = 14, PD_CFG_PRECOND = 15
 };
 int pd_configure(pd_ctx* ctx, int key, double value);
 

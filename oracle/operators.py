@@ -21,13 +21,19 @@ from .basis import tables
 
 
 class Grid:
-    """Uniform periodic Cartesian grid: cells=(nx,ny[,nz]), lengths=(Lx,Ly[,Lz]), degree N."""
+    """Uniform Cartesian grid: cells=(nx,ny[,nz]), lengths=(Lx,Ly[,Lz]), degree N; periodic
+    along every direction unless `periodic` (one flag per direction) says otherwise. A
+    non-periodic direction carries a homogeneous Dirichlet pressure condition (see grad_1d)."""
 
-    def __init__(self, cells, lengths, N):
+    def __init__(self, cells, lengths, N, periodic=None):
         self.cells = tuple(int(c) for c in cells)
         self.lengths = tuple(float(x) for x in lengths)
         if len(self.cells) not in (2, 3) or len(self.lengths) != len(self.cells):
             raise ValueError("2D or 3D grids only")
+        self.periodic = (tuple(bool(p) for p in periodic) if periodic is not None
+                         else (True,) * len(self.cells))
+        if len(self.periodic) != len(self.cells):
+            raise ValueError("one periodic flag per direction")
         self.dim = len(self.cells)
         self.N = int(N)
         self.n = self.N + 1
@@ -47,12 +53,27 @@ def mass_1d(nc, N):
     return sp.kron(sp.identity(nc), sp.diags(tables(N).w), format="csr")
 
 
-def grad_1d(nc, N):
-    """Periodic weak gradient D of eq. (weakgradientop): (D P)_i = R~ P_{i+1} - L~ P_i.
+def grad_1d(nc, N, periodic=True):
+    """Weak gradient D of eq. (weakgradientop): (D P)_i = R~ P_{i+1} - L~ P_i.
 
-    Row block i is dual cell i (between main cells i and i+1)."""
+    Periodic: row block i is dual cell i (between main cells i and i+1, wrapping).
+    Non-periodic (homogeneous Dirichlet pressure, reading of the paper's "appropriate pressure
+    boundary conditions", Section 2.1): nc + 1 dual cells, the boundary ones straddling the
+    walls, with a zero ghost pressure outside; the jump term of R~ / L~ at the dual-cell midpoint,
+    which is the wall, imposes p = 0 there weakly. Row block 0 is the dual cell at x = 0
+    (R~ P_0), row block j + 1 the dual cell between main cells j and j + 1, the last row block
+    the dual cell at x = L (-L~ P_{nc-1})."""
     t = tables(N)
     n = t.n
+    if not periodic:
+        D = sp.lil_matrix(((nc + 1) * n, nc * n))
+        for j in range(-1, nc):
+            rb = (j + 1) * n
+            if j >= 0:
+                D[rb:rb + n, j * n:(j + 1) * n] = -t.Lt
+            if j + 1 < nc:
+                D[rb:rb + n, (j + 1) * n:(j + 2) * n] = t.Rt
+        return D.tocsr()
     D = sp.lil_matrix((nc * n, nc * n))
     for i in range(nc):
         ip = (i + 1) % nc
@@ -61,10 +82,10 @@ def grad_1d(nc, N):
     return D.tocsr()
 
 
-def pressure_1d(nc, N):
+def pressure_1d(nc, N, periodic=True):
     """H = D^T M^-1 D (eq. PerPrSyst), exactly symmetrised against rounding."""
-    D = grad_1d(nc, N)
-    Minv = sp.kron(sp.identity(nc), sp.diags(1.0 / tables(N).w))
+    D = grad_1d(nc, N, periodic)
+    Minv = sp.kron(sp.identity(D.shape[0] // (N + 1)), sp.diags(1.0 / tables(N).w))
     H = (D.T @ Minv @ D).tocsr()
     return ((H + H.T) * 0.5).tocsr()
 
@@ -118,7 +139,7 @@ def stiffness(grid):
     """K = sum_d h_d^-2 (W on the other directions) (x) H_d  (eq. pSyst without dt)."""
     K = None
     for d in range(grid.dim):
-        H = pressure_1d(grid.cells[d], grid.N)
+        H = pressure_1d(grid.cells[d], grid.N, grid.periodic[d])
         term = _kron_along(grid, d, H, lambda e: mass_1d(grid.cells[e], grid.N)) / grid.h[d] ** 2
         K = term if K is None else K + term
     return K.tocsr()
@@ -138,6 +159,13 @@ def pressure_operator(grid, dt):
 def viscous_operator(grid, dt, nu):
     """A_v = M^{xyz} + nu dt K (eq. implicitviscosity with the dt and h factors of eq. uSDG12)."""
     return (full_mass(grid) + nu * dt * stiffness(grid)).tocsr()
+
+
+def null_bases(grid):
+    """Per-direction orthonormal null bases of D: the cell-periodic kernel along periodic
+    directions, none along a Dirichlet direction (there A_p has no null space)."""
+    return [null_basis_tiled(grid.cells[d], grid.N) if grid.periodic[d]
+            else np.zeros((grid.cells[d] * grid.n, 0)) for d in range(grid.dim)]
 
 
 def div_rhs(grid, d):
@@ -208,7 +236,7 @@ def apply_operator(grid, X, alpha, beta, absolute=False):
             MX = apply_along(masses[d], MX, grid.dim - 1 - d)
         out = out + alpha * MX
     for d in range(grid.dim):
-        H = pressure_1d(grid.cells[d], grid.N)
+        H = pressure_1d(grid.cells[d], grid.N, grid.periodic[d])
         if absolute:
             H = abs(H)
         T = apply_along(H, X, grid.dim - 1 - d)
@@ -237,7 +265,10 @@ def div_rhs_apply(grid, U):
 def project_null(grid, X, Zs):
     """v <- v - Z Z^T v with Z = kron of the per-direction orthonormal bases Zs[d].
 
-    X is a tensor-layout array; returns the projected copy (range of A_p)."""
+    X is a tensor-layout array; returns the projected copy (range of A_p). A direction without
+    null vectors (Dirichlet) makes Z empty: nothing is removed."""
+    if any(z.shape[1] == 0 for z in Zs):
+        return np.array(X, dtype=np.float64, copy=True)
     C = X
     for d in range(grid.dim):
         C = apply_along(Zs[d].T, C, grid.dim - 1 - d)
@@ -272,6 +303,8 @@ def apply_at(grid, X, index, alpha, beta):
             wperp = wall / t.w[ld[d]]
             acc = 0.0
             for off, blk in ((-1, t.Lblk), (0, t.Cblk), (1, t.Rblk)):
+                if not grid.periodic[d] and not 0 <= i + off < nc:
+                    continue                              # zero ghost pressure
                 j = (i + off) % nc
                 for m in range(n):
                     gg = list(g)

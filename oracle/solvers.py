@@ -107,7 +107,8 @@ def dense_min_norm(A, Z, b):
 
 
 class FastDiag:
-    """Direct solver for alpha M^{xyz} + beta K on a uniform periodic grid (tensor layout)."""
+    """Direct solver for alpha M^{xyz} + beta K on a uniform grid (tensor layout), periodic or
+    with the Dirichlet directions of Grid.periodic (their 1D operators have no null space)."""
 
     def __init__(self, grid, zero_tol=1e-10):
         self.grid = grid
@@ -119,16 +120,18 @@ class FastDiag:
         w = grid.tab.w
         for d in range(grid.dim):
             nc = grid.cells[d]
-            H = pressure_1d(nc, grid.N).toarray()
+            per = grid.periodic[d]
+            H = pressure_1d(nc, grid.N, per).toarray()
             sq = np.sqrt(np.tile(w, nc))
             Hh = H / sq[:, None] / sq[None, :]
             Hh = 0.5 * (Hh + Hh.T)
             lam, V = np.linalg.eigh(Hh)
             self.V.append(V)
             self.lam.append(lam)
-            self.zero.append(np.abs(lam) <= zero_tol * np.abs(lam).max())
+            self.zero.append(np.abs(lam) <= zero_tol * np.abs(lam).max() if per
+                             else np.zeros(lam.shape, dtype=bool))
             self.sqw.append(sq)
-            self.Z.append(null_basis_1d(nc, grid.N))
+            self.Z.append(null_basis_1d(nc, grid.N) if per else np.zeros((nc * grid.n, 0)))
 
     def _weights(self):
         g = self.grid

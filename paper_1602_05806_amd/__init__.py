@@ -30,7 +30,7 @@ PD_OP_PRESSURE, PD_OP_VISCOUS = 0, 1
 (PD_CFG_STEP_PREC, PD_CFG_P_RTOL, PD_CFG_V_RTOL, PD_CFG_MAXIT, PD_CFG_CONVECTION,
  PD_CFG_RU_FACTOR, PD_CFG_TIMING, PD_CFG_CHECK_EVERY, PD_CFG_KZ, PD_CFG_TILES_PER_WG,
  PD_CFG_PREFETCH, PD_CFG_TILE_VARIANT, PD_CFG_DEFER_X, PD_CFG_ONE_KERNEL,
- PD_CFG_EXPLICIT_VISC) = range(15)
+ PD_CFG_EXPLICIT_VISC, PD_CFG_PRECOND) = range(16)
 PD_BATCH_AUTOTUNE, PD_BATCH_RETUNE = 1, 2
 PD_BCFG_CHUNK, PD_BCFG_GRAPH, PD_BCFG_RU_FACTOR = 0, 1, 2
 PD_TAB_NODES, PD_TAB_WEIGHTS, PD_TAB_L, PD_TAB_C, PD_TAB_R, PD_TAB_PNULL = range(6)

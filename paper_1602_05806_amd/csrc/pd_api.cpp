@@ -35,6 +35,7 @@ struct pd_ctx {
   int defer_x = 1;         // 1: x update made by the next apply kernel, 0: by the update kernel
   int one_kernel = 0;      // 2D: one kernel per CG iteration (residual update folded in)
   int explicit_visc = 0;   // 1: viscous flux in the explicit TVD-RK3 step, no viscous solve
+  int precond = 0;         // 1: cell-block Jacobi preconditioned CG (pd_cg_solve, pd_step)
   // device workspace
   CgState* st = nullptr;       // CG state of the (inner) solve
   CgState* st2 = nullptr;      // outer refinement / residual norms
@@ -48,6 +49,10 @@ struct pd_ctx {
   // 2D one-kernel CG iterations: second residual and A p buffers, 2 x 4-tuple partials
   double *r64b = nullptr, *q64b = nullptr, *fpart = nullptr;
   float *r32b = nullptr, *q32b = nullptr;
+  // preconditioned runs: z = P r in both precisions, 2 x partials of <r, r>
+  double* z64 = nullptr;
+  float* z32 = nullptr;
+  double* rrpart = nullptr;
   double* um[3] = {nullptr, nullptr, nullptr};
   double* s1[3] = {nullptr, nullptr, nullptr};
   double* s2[3] = {nullptr, nullptr, nullptr};
@@ -196,17 +201,43 @@ struct CgRun {
   int nrho = 0, nsig = 0;
   double* rho[2] = {nullptr, nullptr};
   pdk::ApplyLaunch L;
+  // preconditioned run: z = P r (cell-block Jacobi); rho[] then holds the partials of <r, z>
+  // and rr[] those of <r, r> (the stopping test)
+  bool pc = false;
+  void* z = nullptr;
+  double* rr[2] = {nullptr, nullptr};
+  pdk::PrecTables P;
 };
+
+pdk::PrecTables prec_tables(const pd_ctx* c, int op) {
+  pdk::PrecTables P;
+  const int n = c->n;
+  for (int i = 0; i < 81; ++i) P.V[i] = i < n * n ? c->tab.PV[i] : 0.0;
+  for (int i = 0; i < 9; ++i) P.lam[i] = i < n ? c->tab.Plam[i] : 0.0;
+  op_coefs(c, op, &P.alpha, P.coef);
+  return P;
+}
+
+// z = P r with the partials of <r, z> and <r, r> in the slots of iteration slot (start of a
+// preconditioned run, or its restart from a replaced residual)
+int pcg_init(pd_ctx* c, const struct CgRun* R, int slot, hipStream_t s);
 
 // Prepare a run whose residual r_0 and the partials of <r_0, r_0> (in rho[0]) are in place and
 // whose CG state holds tol2 / maxit.
 int cg_prepare(pd_ctx* c, CgRun* R) {
-  R->nrho = (int)pdk::stream_grid(c->ndof);
+  R->pc = c->precond != 0;
+  R->nrho = R->pc ? (int)pdk::pcg_grid(c->ncells, c->dim, c->N) : (int)pdk::stream_grid(c->ndof);
   R->rho[0] = c->rhopart;
   R->rho[1] = c->rhopart + pdk::kMaxStreamPartials;
+  if (R->pc) {
+    R->z = R->fp32 ? (void*)c->z32 : (void*)c->z64;
+    R->rr[0] = c->rrpart;
+    R->rr[1] = c->rrpart + pdk::kMaxStreamPartials;
+    R->P = prec_tables(c, R->op);
+  }
   R->L = base_launch(c, R->op, R->fp32);
   R->defer = c->defer_x != 0;
-  R->one = c->one_kernel != 0 && c->dim == 2 && R->B.rb && R->B.qb;
+  R->one = c->one_kernel != 0 && c->dim == 2 && R->B.rb && R->B.qb && !R->pc;
   R->L.fuse = R->one ? 3 : R->defer ? 2 : 1;
   R->L.xsol = (R->one || R->defer) ? R->x : nullptr;
   R->L.st = R->st;
@@ -217,6 +248,14 @@ int cg_prepare(pd_ctx* c, CgRun* R) {
   R->k = 0;
   R->kfirst = 0;
   PD_HIP(c, pdk::launch_zero(R->fp32, R->B.pa, c->ndof, R->s));
+  if (R->pc) return pcg_init(c, R, 0, R->s);
+  return PD_OK;
+}
+
+int pcg_init(pd_ctx* c, const CgRun* R, int slot, hipStream_t s) {
+  PD_HIP(c, pdk::launch_pcg_update(R->fp32, c->dim, c->N, false, nullptr, R->B.r, R->z, c->ncells,
+                                   R->st, 0, nullptr, 0, R->rho[slot & 1], R->rr[slot & 1], R->P,
+                                   s));
   return PD_OK;
 }
 
@@ -226,7 +265,8 @@ int cg_launch(pd_ctx* c, CgRun* R) {
   pdk::ApplyLaunch& L = R->L;
   L.k = k;
   L.rho_cur = R->rho[k & 1];
-  L.x = R->B.r;
+  L.res_cur = R->pc ? R->rr[k & 1] : nullptr;
+  L.x = R->pc ? R->z : R->B.r;
   L.pold = buf[k & 1];
   L.pnew = buf[(k + 1) & 1];
   L.y = R->B.q;
@@ -253,7 +293,11 @@ int cg_launch(pd_ctx* c, CgRun* R) {
     L.ev_stop = c->tev[2 * j + 1];
   }
   PD_HIP(c, pdk::launch_apply(L, R->s));
-  if (!R->one)
+  if (R->pc)
+    PD_HIP(c, pdk::launch_pcg_update(R->fp32, c->dim, c->N, true, R->B.q, R->B.r, R->z,
+                                     c->ncells, R->st, k, c->sigpart, R->nsig, R->rho[(k + 1) & 1],
+                                     R->rr[(k + 1) & 1], R->P, R->s));
+  else if (!R->one)
     PD_HIP(c, pdk::launch_cg_update(R->fp32, R->defer ? nullptr : R->x,
                                     R->defer ? nullptr : buf[(k + 1) & 1], R->B.q, R->B.r,
                                     c->ndof, R->st, k, c->sigpart, R->nsig,
@@ -378,12 +422,16 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
     const double goal = rtol * bnorm;
     if (res <= goal || res > kTrueGap * goal || (prev_res > 0.0 && res > 0.5 * prev_res)) break;
     prev_res = res;
-    if (!(res <= 4.0 * std::sqrt(fin.rho))) {
+    if (!(res <= 4.0 * std::sqrt(fin.res2))) {
       void* buf[2] = {R.B.pa, R.B.pb};
       PD_HIP(c, pdk::launch_zero(false, buf[R.k & 1], c->ndof, s));
       ++inf->restarts;
     }
-    PD_HIP(c, pdk::launch_dot(false, c->r64, c->r64, c->ndof, R.rho[R.k & 1], s));
+    if (R.pc) {
+      if ((rc = pcg_init(c, &R, R.k, s))) return rc;
+    } else {
+      PD_HIP(c, pdk::launch_dot(false, c->r64, c->r64, c->ndof, R.rho[R.k & 1], s));
+    }
     if (R.one && (R.k & 1))
       PD_HIP(c, hipMemcpyAsync(c->r64b, c->r64, c->ndof * sizeof(double),
                                hipMemcpyDeviceToDevice, s));
@@ -392,7 +440,7 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
   }
   cg_collect_timing(c, R);
   inf->iters = R.k;
-  inf->rel_res_recur = std::sqrt(fin.rho) / bnorm;
+  inf->rel_res_recur = std::sqrt(fin.res2) / bnorm;
   inf->status = fin.done ? fin.status : PD_ENOCONV;
   return PD_OK;
 }
@@ -507,7 +555,7 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
     // residual replacement: r32 = r64 / scale with the partials of <r32, r32> for iteration R.k.
     // If the FP32 recurrence residual had drifted well below the true one, beta would be huge
     // and the old direction would swamp the new residual: restart the direction (p_old = 0).
-    const double rec = std::sqrt(fin.rho);
+    const double rec = std::sqrt(fin.res2);
     if (broke || !(res / scale <= 4.0 * rec)) {
       void* buf[2] = {R.B.pa, R.B.pb};
       PD_HIP(c, pdk::launch_zero(true, buf[R.k & 1], n, s));
@@ -515,6 +563,8 @@ int solve_refine(pd_ctx* c, int op, const double* b, double* x, double rtol, dou
     }
     float* r32k = (R.one && (R.k & 1)) ? c->r32b : c->r32;
     PD_HIP(c, pdk::launch_to_f32_dot(c->r64, r32k, n, 1.0 / scale, R.rho[R.k & 1], s));
+    if (R.pc)
+      if ((rc = pcg_init(c, &R, R.k, s))) return rc;
     R.kfirst = R.k;
     ref = res / scale;
     PD_HIP(c, pdk::launch_state_set(c->st, maxit, inner_tol2(ref), R.k, s));
@@ -1027,7 +1077,8 @@ void pd_destroy(pd_ctx* c) {
   (void)hipDeviceSynchronize();
   void* bufs[] = {c->st, c->st2, c->rhopart, c->sigpart, c->tmppart, c->null_part, c->null_corr,
                   c->r64, c->pa64, c->pb64, c->q64, c->bw64, c->r32, c->pa32, c->pb32, c->q32,
-                  c->d32, c->qbuf, c->r64b, c->q64b, c->fpart, c->r32b, c->q32b};
+                  c->d32, c->qbuf, c->r64b, c->q64b, c->fpart, c->r32b, c->q32b, c->z64,
+                  c->z32, c->rrpart};
   for (void* p : bufs)
     if (p) (void)hipFree(p);
   for (int d = 0; d < 3; ++d) {
@@ -1580,6 +1631,17 @@ int pd_configure(pd_ctx* c, int key, double v) {
     case PD_CFG_DEFER_X:
       if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_DEFER_X must be 0 or 1");
       c->defer_x = (int)v;
+      break;
+    case PD_CFG_PRECOND:
+      if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_PRECOND must be 0 or 1");
+      if (v == 1) {
+        const size_t n = (size_t)c->ndof;
+        int rc = PD_OK;
+        if ((rc = dev_alloc(c, &c->z64, n)) || (rc = dev_alloc(c, &c->z32, n)) ||
+            (rc = dev_alloc(c, &c->rrpart, 2 * (size_t)pdk::kMaxStreamPartials)))
+          return rc;
+      }
+      c->precond = (int)v;
       break;
     case PD_CFG_EXPLICIT_VISC:
       if (!(v == 0 || v == 1)) return fail(c, PD_EINVAL, "PD_CFG_EXPLICIT_VISC must be 0 or 1");

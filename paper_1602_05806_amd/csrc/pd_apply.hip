@@ -121,7 +121,8 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     }
     if (FUSE) {
       const int k = kit;
-      const IterScalars sc = iteration_scalars<NTH>(a.st, k, a.rho_cur, a.nrho, blockIdx.x == 0);
+      const IterScalars sc = iteration_scalars<NTH>(a.st, k, a.rho_cur, a.nrho, blockIdx.x == 0,
+                                                    false, a.res_cur);
       if (sc.stop) return;
       beta = (T)sc.beta;
       if (FUSE == 2) {
@@ -459,6 +460,7 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   a.k = L.k;
   a.kbase = nullptr;
   a.rho_cur = L.rho_cur;
+  a.res_cur = L.res_cur;
   a.nrho = L.nrho;
   a.sigpart = L.sigpart;
   a.xsol = (T*)L.xsol;

@@ -22,6 +22,7 @@ struct ApplyArgs {
   int k;              // iteration index, or offset from *kbase when kbase is set
   const int* kbase;   // device-resident iteration base (graph-replayed batched runs) or null
   const double* rho_cur;
+  const double* res_cur;   // preconditioned runs: partials of <r_k, r_k> (x is then z = P r)
   int nrho;
   double* sigpart;
   T* xsol;            // FUSE = 2, 3: CG iterate, x += alpha_{k-1} p_old on owned cells
@@ -199,7 +200,8 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
     xalpha = (T)sc.alpha;
   } else if (FUSE) {
     const int k = kit;
-    const IterScalars sc = iteration_scalars<256>(a.st, k, a.rho_cur, a.nrho, t_begin == 0, RU);
+    const IterScalars sc = iteration_scalars<256>(a.st, k, a.rho_cur, a.nrho, t_begin == 0, RU,
+                                                  a.res_cur);
     if (sc.stop) return;
     beta = (T)sc.beta;
     if (FUSE == 2) {

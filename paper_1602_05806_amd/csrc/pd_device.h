@@ -38,6 +38,8 @@ struct CgState {
   double scale;      // batched refinement: the FP32 vectors hold r / scale
   double ref;        // batched refinement: FP64 residual / scale at the last replacement
   double best;       // batched refinement: smallest FP64 residual / scale so far
+  double res2;       // <r_k, r_k> of the current iterate (the stopping test); equals rho unless
+                     // the run is preconditioned (then rho = <r_k, z_k>, z_k = P r_k)
   int iter;          // iterations completed when done
   int maxit;
   int done;          // 1 once converged, out of iterations or broken down (batched refinement:
@@ -167,22 +169,27 @@ struct IterScalars {
 
 // `writer`: the one block of the problem that mirrors the scalars into st.
 // `one`: one kernel per iteration (the next launch is the apply kernel of iteration k + 1).
+// res_cur: partials of <r_k, r_k> when the run is preconditioned (rho_cur then holds those of
+// <r_k, z_k>); null otherwise.
 template <int NT>
 __device__ __forceinline__ IterScalars iteration_scalars(CgState* st, int k,
                                                          const double* rho_cur, int nrho,
-                                                         bool writer, bool one = false) {
+                                                         bool writer, bool one = false,
+                                                         const double* res_cur = nullptr) {
   IterScalars r;
   r.rho = sum_partials<NT>(rho_cur, nrho);
+  const double res2 = res_cur ? sum_partials<NT>(res_cur, nrho) : r.rho;
   const double rho_old = k > 0 ? st->rho_hist[(k + 1) & 1] : 0.0;
   r.beta = (k > 0 && k != st->restart_k && !st->fresh) ? r.rho / rho_old : 0.0;
   int status = 1;                               // 1 = keep iterating
-  if (!isfinite(r.rho)) status = -5;
-  else if (r.rho <= st->tol2 && !(st->even_stop && (k & 1))) status = 0;
+  if (!isfinite(r.rho) || !isfinite(res2)) status = -5;
+  else if (res2 <= st->tol2 && !(st->even_stop && (k & 1))) status = 0;
   else if (k - st->idle >= st->maxit) status = -4;   // iterations run (batched: idle excluded)
   r.stop = status != 1;
   if (threadIdx.x == 0 && writer) {
     st->rho_hist[k & 1] = r.rho;
     st->rho = r.rho;
+    st->res2 = res2;
     st->beta = r.beta;
     st->iter = k;
     if (r.stop) {
@@ -276,6 +283,7 @@ __device__ __forceinline__ FusedScalars fused_scalars(CgState* st, int k,
     st->rho_hist[(k + 1) & 1] = rho_prev;
     st->rho_hist[k & 1] = rho;
     st->rho = rho;
+    st->res2 = rho;
     st->beta = f.beta;
     st->iter = k;
     if (f.stop) {

@@ -28,6 +28,7 @@ struct ApplyLaunch {
   CgState* st = nullptr;
   int k = 0;
   const double* rho_cur = nullptr;
+  const double* res_cur = nullptr;   // preconditioned: partials of <r, r> (x = z = P r)
   int nrho = 0;
   double* sigpart = nullptr;
   void* xsol = nullptr;      // fuse = 2, 3: the CG iterate x (updated in place for owned cells)
@@ -66,6 +67,21 @@ hipError_t launch_finalize(const double* partials, int nparts, CgState* st, int 
 hipError_t launch_cg_update(bool fp32, void* x, const void* p, const void* q, void* r,
                             long long n, CgState* st, int k, const double* sigpart, int nsig,
                             double* rho_next, hipStream_t s);
+// Cell-block Jacobi preconditioner of alpha M + sum_d coef[d] (M on the other directions) (x) C
+// (the diagonal cell blocks of the operator; see pdh::Table1D::PV).
+struct PrecTables {
+  double V[81], lam[9];
+  double alpha = 0.0, coef[3] = {0, 0, 0};
+};
+// Preconditioned CG, second half of iteration k (upd = true): alpha_k from the sigma partials,
+// r -= alpha_k q, z = P r, partials of <r, z> (rz_next) and <r, r> (rr_next); publishes alpha_k
+// and xk for the deferred x update and the stamp of the next apply. upd = false: z = P r and
+// the partials only (start of a run or after a residual replacement; no stamp check). Partials:
+// pcg_grid(...) of each.
+hipError_t launch_pcg_update(bool fp32, int dim, int N, bool upd, const void* q, void* r, void* z,
+                             long long ncells, CgState* st, int k, const double* sigpart, int nsig,
+                             double* rz_next, double* rr_next, const PrecTables& P, hipStream_t s);
+unsigned pcg_grid(long long ncells, int dim, int N);
 // the x update still pending when a run stopped (see k_x_flush)
 hipError_t launch_x_flush(bool fp32, void* x, const void* pa, const void* pb, long long n,
                           const CgState* st, hipStream_t s);

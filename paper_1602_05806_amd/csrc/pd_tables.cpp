@@ -168,6 +168,16 @@ bool build_table(int N, Table1D* t, std::string* err) {
       for (int j = 0; j < n; ++j) a += t->Kv[k * n + j] * dlag(xi, n, m, xi[j]);
       t->KD[k * n + m] = a;
     }
+  {
+    // block-Jacobi tables: S = M^-1/2 C M^-1/2 = U diag(lam) U^T, V = M^-1/2 U
+    double Sm[kMaxn * kMaxn], U[kMaxn * kMaxn];
+    for (int p = 0; p < n; ++p)
+      for (int q = 0; q < n; ++q)
+        Sm[p * n + q] = t->Cb[p * n + q] / std::sqrt(t->w[p] * t->w[q]);
+    jacobi_eig(n, Sm, U, t->Plam);
+    for (int p = 0; p < n; ++p)
+      for (int l = 0; l < n; ++l) t->PV[p * n + l] = U[p * n + l] / std::sqrt(t->w[p]);
+  }
   // Null space of (R~ - L~): the cell-periodic solutions of D P = 0. Eigenvectors of
   // S = (R~-L~)^T (R~-L~) whose eigenvalue (a squared singular value of R~-L~) is below
   // (1e-8 ||(R~, L~)||_F)^2. The scale is that of R~ and L~ themselves, not of S: for N = 1,

@@ -24,6 +24,12 @@ struct Table1D {
   double dphi0[kMaxn], dphi1[kMaxn];     // phi_p'(0), phi_p'(1)
   double KD[kMaxn * kMaxn];              // KD[k][m] = sum_j Kv[k][j] phi_m'(xi_j): volume term of
                                          // the broken gradient (explicit viscous flux)
+  // Generalised eigenvectors of the diagonal block: C V = M V diag(lam), V^T M V = I (C is SPD).
+  // The cell-diagonal block of alpha M^{xyz} + sum_d c_d (M on the other directions) (x) C is
+  // then (V^-T (x) ..) diag(alpha + sum_d c_d lam_{l_d}) (V^-1 (x) ..): the block-Jacobi
+  // preconditioner is (V (x) ..) diag(1 / (alpha + sum_d c_d lam_{l_d})) (V^T (x) ..).
+  double PV[kMaxn * kMaxn];              // PV[m][l]: component m of eigenvector l
+  double Plam[kMaxn];
   int nnull = 0;                         // dimension of null(R~ - L~) (1 for even N, 2 for odd N)
   double Pnull[kMaxn * kMaxn];           // orthogonal projector onto null(R~ - L~)
 };

@@ -333,6 +333,121 @@ __global__ __launch_bounds__(kBlock) void k_mass(W9 W, int n, const double* __re
   }
 }
 
+// ---- cell-block Jacobi preconditioner (the preconditioning the paper names as future work for
+// its matrix-free CG, end of Section 2.1): z = P r with P the inverse of the diagonal cell block
+// of alpha M + sum_d c_d (M on the other directions) (x) C, applied per cell in the generalised
+// eigenbasis of (C, M): z = (V (x) ..) diag(1 / (alpha + sum_d c_d lam_{l_d})) (V^T (x) ..) r.
+template <int N>
+struct PrecArgs {
+  double V[(N + 1) * (N + 1)];   // V[m][l]: component m of eigenvector l
+  double lam[N + 1];
+  double alpha, c0, c1, c2;
+};
+
+// UPD = 1: second half of a preconditioned CG iteration k (r -= alpha_k q first, alpha_k from
+// the sigma partials); UPD = 0: z = P r only. Partials of <r, z> and <r, r> per block. Each
+// block takes groups of CPB whole cells (grid-stride over the groups); the 1D transforms run
+// through LDS, one direction at a time, in FP64.
+template <typename T, int N, int DIM, int UPD>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(PrecArgs<N> P, const T* __restrict__ q,
+                                                       T* __restrict__ r, T* __restrict__ z,
+                                                       long long ncells, CgState* st, int k,
+                                                       const double* __restrict__ sigpart,
+                                                       int nsig, double* __restrict__ rz_next,
+                                                       double* __restrict__ rr_next) {
+  constexpr int n = N + 1, NC = DIM == 3 ? n * n * n : n * n;
+  constexpr int CPB = NC >= kBlock ? 1 : kBlock / NC;
+  constexpr int E = CPB * NC;
+  __shared__ double br[E], b0[E], b1[E];
+  T a = T(0);
+  if (UPD) {
+    if (st->run_u != k) return;        // the apply kernel of iteration k stopped the run
+    const double sigma = sum_partials<kBlock>(sigpart, nsig);
+    const double alpha = st->rho / sigma;
+    if (!(sigma > 0.0) || !isfinite(alpha)) {
+      if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->sigma = sigma;
+        st->status = -5;
+        st->iter = k;
+        st->done = 1;
+      }
+      return;
+    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+      st->sigma = sigma;
+      st->alpha = alpha;
+      st->xk = k;
+      st->run_a[(k + 1) & 1] = k + 1;
+    }
+    a = (T)alpha;
+  }
+  auto transform = [&](const double* in, double* out, int ecount, int sd, bool fwd) {
+    for (int e = threadIdx.x; e < ecount; e += kBlock) {
+      const int l = e % NC;
+      const int ld = (l / sd) % n;
+      const int b = e - ld * sd;
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < n; ++m) acc += (fwd ? P.V[m * n + ld] : P.V[ld * n + m]) * in[b + m * sd];
+      out[e] = acc;
+    }
+    __syncthreads();
+  };
+  double rr = 0.0, rz = 0.0;
+  const long long ngroups = (ncells + CPB - 1) / CPB;
+  for (long long grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const long long c0 = grp * CPB;
+    const long long base = c0 * NC;
+    const int ecount = (int)((ncells - c0 < CPB ? ncells - c0 : CPB) * NC);
+    for (int e = threadIdx.x; e < ecount; e += kBlock) {
+      T rv = r[base + e];
+      if (UPD) {
+        rv = rv - a * q[base + e];
+        r[base + e] = rv;
+      }
+      rr += (double)rv * (double)rv;
+      br[e] = (double)rv;
+    }
+    __syncthreads();
+    transform(br, b0, ecount, 1, true);
+    transform(b0, b1, ecount, n, true);
+    double* cur = b1;
+    double* oth = b0;
+    if (DIM == 3) {
+      transform(b1, b0, ecount, n * n, true);
+      cur = b0;
+      oth = b1;
+    }
+    for (int e = threadIdx.x; e < ecount; e += kBlock) {
+      const int l = e % NC;
+      double d = P.alpha + P.c0 * P.lam[l % n] + P.c1 * P.lam[(l / n) % n];
+      if (DIM == 3) d += P.c2 * P.lam[l / (n * n)];
+      cur[e] = cur[e] / d;
+    }
+    __syncthreads();
+    transform(cur, oth, ecount, 1, false);
+    transform(oth, cur, ecount, n, false);
+    if (DIM == 3) {
+      transform(cur, oth, ecount, n * n, false);
+      double* t = cur;
+      cur = oth;
+      oth = t;
+    }
+    for (int e = threadIdx.x; e < ecount; e += kBlock) {
+      const T zv = (T)cur[e];
+      z[base + e] = zv;
+      rz += br[e] * (double)zv;
+    }
+    __syncthreads();
+  }
+  rr = block_sum_all<kBlock>(rr);
+  rz = block_sum_all<kBlock>(rz);
+  if (threadIdx.x == 0) {
+    rr_next[blockIdx.x] = rr;
+    rz_next[blockIdx.x] = rz;
+  }
+}
+
 // Mean kinetic energy of a dual velocity field: partials of sum_i W_i sum_d u_d,i^2 (W_i = product
 // of the GL weights of node i); with g[0] non-null also g_d = gs W u_d for every component.
 struct Vel3 {
@@ -616,6 +731,78 @@ hipError_t launch_energy(int dim, int N, const double* w, const double* const u[
   else
     hipLaunchKernelGGL(k_energy<2>, dim3(G), dim3(kBlock), 0, s, W, n, v, gs, ncells, partials);
   return hipGetLastError();
+}
+
+unsigned pcg_grid(long long ncells, int dim, int N) {
+  const int n = N + 1, NC = dim == 3 ? n * n * n : n * n;
+  const int CPB = NC >= kBlock ? 1 : kBlock / NC;
+  long long g = (ncells + CPB - 1) / CPB;
+  if (g < 1) g = 1;
+  if (g > kMaxStreamPartials) g = kMaxStreamPartials;
+  return (unsigned)g;
+}
+
+template <typename T, int N, int DIM>
+static hipError_t pcg_launch_NT(bool upd, const void* q, void* r, void* z, long long ncells,
+                                CgState* st, int k, const double* sigpart, int nsig,
+                                double* rz_next, double* rr_next, const PrecTables& tb,
+                                hipStream_t s) {
+  PrecArgs<N> P;
+  constexpr int n = N + 1;
+  for (int i = 0; i < n * n; ++i) P.V[i] = tb.V[i];
+  for (int i = 0; i < n; ++i) P.lam[i] = tb.lam[i];
+  P.alpha = tb.alpha;
+  P.c0 = tb.coef[0];
+  P.c1 = tb.coef[1];
+  P.c2 = tb.coef[2];
+  const dim3 G(pcg_grid(ncells, DIM, N)), B(kBlock);
+  if (upd)
+    hipLaunchKernelGGL((k_pcg_update<T, N, DIM, 1>), G, B, 0, s, P, (const T*)q, (T*)r, (T*)z,
+                       ncells, st, k, sigpart, nsig, rz_next, rr_next);
+  else
+    hipLaunchKernelGGL((k_pcg_update<T, N, DIM, 0>), G, B, 0, s, P, (const T*)q, (T*)r, (T*)z,
+                       ncells, st, k, sigpart, nsig, rz_next, rr_next);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t pcg_launch_N(int dim, bool upd, const void* q, void* r, void* z,
+                               long long ncells, CgState* st, int k, const double* sigpart,
+                               int nsig, double* rz_next, double* rr_next, const PrecTables& tb,
+                               hipStream_t s) {
+  return dim == 3 ? pcg_launch_NT<T, N, 3>(upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next,
+                                             rr_next, tb, s)
+                  : pcg_launch_NT<T, N, 2>(upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next,
+                                             rr_next, tb, s);
+}
+
+template <typename T>
+static hipError_t pcg_launch_T(int dim, int N, bool upd, const void* q, void* r, void* z,
+                               long long ncells, CgState* st, int k, const double* sigpart,
+                               int nsig, double* rz_next, double* rr_next, const PrecTables& tb,
+                               hipStream_t s) {
+  switch (N) {
+    case 0: return pcg_launch_N<T, 0>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    case 1: return pcg_launch_N<T, 1>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    case 2: return pcg_launch_N<T, 2>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    case 3: return pcg_launch_N<T, 3>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    case 4: return pcg_launch_N<T, 4>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    case 5: return pcg_launch_N<T, 5>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    case 6: return pcg_launch_N<T, 6>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    case 7: return pcg_launch_N<T, 7>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    case 8: return pcg_launch_N<T, 8>(dim, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next, rr_next, tb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_pcg_update(bool fp32, int dim, int N, bool upd, const void* q, void* r, void* z,
+                             long long ncells, CgState* st, int k, const double* sigpart, int nsig,
+                             double* rz_next, double* rr_next, const PrecTables& P, hipStream_t s) {
+  if (fp32)
+    return pcg_launch_T<float>(dim, N, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next,
+                               rr_next, P, s);
+  return pcg_launch_T<double>(dim, N, upd, q, r, z, ncells, st, k, sigpart, nsig, rz_next,
+                              rr_next, P, s);
 }
 
 hipError_t launch_time_mix(const TimeMix& X, long long n, hipStream_t s) {
