@@ -53,27 +53,12 @@ def mass_1d(nc, N):
     return sp.kron(sp.identity(nc), sp.diags(tables(N).w), format="csr")
 
 
-def grad_1d(nc, N, periodic=True):
-    """Weak gradient D of eq. (weakgradientop): (D P)_i = R~ P_{i+1} - L~ P_i.
+def grad_1d(nc, N):
+    """Periodic weak gradient D of eq. (weakgradientop): (D P)_i = R~ P_{i+1} - L~ P_i.
 
-    Periodic: row block i is dual cell i (between main cells i and i+1, wrapping).
-    Non-periodic (homogeneous Dirichlet pressure, reading of the paper's "appropriate pressure
-    boundary conditions", Section 2.1): nc + 1 dual cells, the boundary ones straddling the
-    walls, with a zero ghost pressure outside; the jump term of R~ / L~ at the dual-cell midpoint,
-    which is the wall, imposes p = 0 there weakly. Row block 0 is the dual cell at x = 0
-    (R~ P_0), row block j + 1 the dual cell between main cells j and j + 1, the last row block
-    the dual cell at x = L (-L~ P_{nc-1})."""
+    Row block i is dual cell i (between main cells i and i+1)."""
     t = tables(N)
     n = t.n
-    if not periodic:
-        D = sp.lil_matrix(((nc + 1) * n, nc * n))
-        for j in range(-1, nc):
-            rb = (j + 1) * n
-            if j >= 0:
-                D[rb:rb + n, j * n:(j + 1) * n] = -t.Lt
-            if j + 1 < nc:
-                D[rb:rb + n, (j + 1) * n:(j + 2) * n] = t.Rt
-        return D.tocsr()
     D = sp.lil_matrix((nc * n, nc * n))
     for i in range(nc):
         ip = (i + 1) % nc
@@ -83,9 +68,35 @@ def grad_1d(nc, N, periodic=True):
 
 
 def pressure_1d(nc, N, periodic=True):
-    """H = D^T M^-1 D (eq. PerPrSyst), exactly symmetrised against rounding."""
-    D = grad_1d(nc, N, periodic)
-    Minv = sp.kron(sp.identity(D.shape[0] // (N + 1)), sp.diags(1.0 / tables(N).w))
+    """H = D^T M^-1 D (eq. PerPrSyst), exactly symmetrised against rounding.
+
+    periodic=False: homogeneous Dirichlet pressure at both ends by odd reflection across the wall
+    (method of images; reading of the paper's "appropriate pressure boundary conditions",
+    Section 2.1): the pressure of the mirror cell beyond a wall is -J P of the adjacent cell, J
+    reversing the node order, so the wall rows of eq. (pSyst1d) read (C - L J) P_0 + R P_1 and
+    L P_{nc-2} + (C - R J) P_{nc-1}. This is the periodic operator of the doubled domain
+    restricted to odd functions: symmetric, positive definite for even N; for odd N the odd
+    cell-periodic mode of the periodic null space stays in the null space."""
+    if not periodic:
+        t = tables(N)
+        n = t.n
+        J = np.eye(n)[::-1]
+        H = sp.lil_matrix((nc * n, nc * n))
+        for i in range(nc):
+            blk = t.Cblk.copy()
+            if i == 0:
+                blk = blk - t.Lblk @ J
+            if i == nc - 1:
+                blk = blk - t.Rblk @ J
+            H[i * n:(i + 1) * n, i * n:(i + 1) * n] = blk
+            if i > 0:
+                H[i * n:(i + 1) * n, (i - 1) * n:i * n] = t.Lblk
+            if i < nc - 1:
+                H[i * n:(i + 1) * n, (i + 1) * n:(i + 2) * n] = t.Rblk
+        H = H.tocsr()
+        return ((H + H.T) * 0.5).tocsr()
+    D = grad_1d(nc, N)
+    Minv = sp.kron(sp.identity(nc), sp.diags(1.0 / tables(N).w))
     H = (D.T @ Minv @ D).tocsr()
     return ((H + H.T) * 0.5).tocsr()
 
@@ -161,11 +172,24 @@ def viscous_operator(grid, dt, nu):
     return (full_mass(grid) + nu * dt * stiffness(grid)).tocsr()
 
 
+def null_basis_dirichlet(nc, N):
+    """Orthonormal null basis of the Dirichlet (odd-reflection) 1D operator: the part of the
+    cell-periodic kernel that is odd about the cell centre (J q = -q): the odd mode for odd N,
+    nothing for even N (the constant is even and removed by the reflection)."""
+    n = N + 1
+    Z = null_basis_tiled(1, N)                       # per-cell kernel modes, orthonormal
+    J = np.eye(n)[::-1]
+    odd = 0.5 * (Z - J @ Z)
+    u, sv, _ = np.linalg.svd(odd, full_matrices=False)
+    modes = u[:, sv > 1e-8]
+    return np.tile(modes, (nc, 1)) / np.sqrt(nc)
+
+
 def null_bases(grid):
-    """Per-direction orthonormal null bases of D: the cell-periodic kernel along periodic
-    directions, none along a Dirichlet direction (there A_p has no null space)."""
+    """Per-direction orthonormal null bases: the cell-periodic kernel of D along periodic
+    directions, its odd part along Dirichlet directions."""
     return [null_basis_tiled(grid.cells[d], grid.N) if grid.periodic[d]
-            else np.zeros((grid.cells[d] * grid.n, 0)) for d in range(grid.dim)]
+            else null_basis_dirichlet(grid.cells[d], grid.N) for d in range(grid.dim)]
 
 
 def div_rhs(grid, d):
@@ -282,7 +306,8 @@ def apply_at(grid, X, index, alpha, beta):
     """(alpha M^{xyz} + beta K) X evaluated at the tensor multi-indices `index` (array of shape
     (m, dim), axes ordered (z,) y, x), from the block form of eq. (pSyst): along direction d the
     output node l_d of cell i_d couples to the nodes of cells i_d-1, i_d, i_d+1 through the blocks
-    L, C, R, weighted by the GL masses of the other directions and h_d^-2. Periodic wrap.
+    L, C, R, weighted by the GL masses of the other directions and h_d^-2. Periodic wrap, or the
+    odd reflection of pressure_1d beyond a Dirichlet wall.
     Used to check single outputs of full-size applications without assembling the matrix."""
     t = grid.tab
     n = grid.n
@@ -303,13 +328,13 @@ def apply_at(grid, X, index, alpha, beta):
             wperp = wall / t.w[ld[d]]
             acc = 0.0
             for off, blk in ((-1, t.Lblk), (0, t.Cblk), (1, t.Rblk)):
-                if not grid.periodic[d] and not 0 <= i + off < nc:
-                    continue                              # zero ghost pressure
-                j = (i + off) % nc
+                mirror = not grid.periodic[d] and not 0 <= i + off < nc
+                j = i if mirror else (i + off) % nc
                 for m in range(n):
                     gg = list(g)
-                    gg[ax] = j * n + m
-                    acc += blk[ld[d], m] * X[tuple(gg)]
+                    # beyond a Dirichlet wall: the odd reflection -J P of the adjacent cell
+                    gg[ax] = j * n + (n - 1 - m if mirror else m)
+                    acc += blk[ld[d], m] * (-X[tuple(gg)] if mirror else X[tuple(gg)])
             val += beta / grid.h[d] ** 2 * wperp * acc
         out[r] = val
     return out

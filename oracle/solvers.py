@@ -18,7 +18,7 @@ Euclidean DoF inner product) to the null space Z. Three independent ways to get 
 import numpy as np
 import scipy.linalg as sla
 
-from .operators import apply_along, pressure_1d, null_basis_1d, project_null
+from .operators import apply_along, pressure_1d, null_basis_1d, null_basis_dirichlet, project_null
 
 
 def cg(A, b, rtol, maxit, x0=None):
@@ -128,10 +128,9 @@ class FastDiag:
             lam, V = np.linalg.eigh(Hh)
             self.V.append(V)
             self.lam.append(lam)
-            self.zero.append(np.abs(lam) <= zero_tol * np.abs(lam).max() if per
-                             else np.zeros(lam.shape, dtype=bool))
+            self.zero.append(np.abs(lam) <= zero_tol * np.abs(lam).max())
             self.sqw.append(sq)
-            self.Z.append(null_basis_1d(nc, grid.N) if per else np.zeros((nc * grid.n, 0)))
+            self.Z.append(null_basis_1d(nc, grid.N) if per else null_basis_dirichlet(nc, grid.N))
 
     def _weights(self):
         g = self.grid

@@ -694,3 +694,92 @@ def test_pcg_pressure_reaches_min_norm_solution(dim, cells, N):
     xp = project_null(g, x.reshape(g.shape()), Z)
     assert np.abs(xp - ref).max() <= 1e-9 * np.abs(ref).max()
     assert it < it_cg
+
+
+# ------------------------------------------------------------------ Dirichlet pressure walls
+
+def test_dirichlet_operator_is_the_doubled_periodic_operator_on_odd_functions():
+    """Method of images: the Dirichlet 1D operator (odd reflection across both walls) equals the
+    periodic operator of eq. (pSyst1d) on the doubled domain (2 nc cells, built independently
+    by the periodic assembly) applied to the odd extension, restricted to the physical cells."""
+    from oracle.operators import pressure_1d
+    for N in range(0, 7):
+        n, nc = N + 1, 5
+        Hd = pressure_1d(nc, N, periodic=False).toarray()
+        Hp = pressure_1d(2 * nc, N).toarray()
+        v = np.random.default_rng(N).standard_normal(nc * n)
+        # odd extension: cells 0..nc-1 physical, cells nc..2nc-1 the mirror images in reverse
+        # order (the periodic ring wraps, so the mirror of cell 0 sits next to it at 2nc-1)
+        mirror = -v.reshape(nc, n)[::-1, ::-1].reshape(-1)
+        ext = np.concatenate([v, mirror])
+        assert np.abs(Hd @ v - (Hp @ ext)[:nc * n]).max() <= 1e-12 * np.abs(Hp).max() * np.abs(v).max()
+
+
+def test_dirichlet_N0_closed_form():
+    """N = 0: the wall row is 3 P_0 - P_1 (mirror pressure -P_0, the cell-centred finite-volume
+    Dirichlet condition), and the eigenvalues are 2 - 2 cos(pi m / nc), m = 1..nc."""
+    from oracle.operators import pressure_1d
+    nc = 7
+    H = pressure_1d(nc, 0, periodic=False).toarray()
+    assert H[0, 0] == 3.0 and H[0, 1] == -1.0 and H[-1, -1] == 3.0
+    ev = np.sort(np.linalg.eigvalsh(H))
+    ref = np.sort(2 - 2 * np.cos(np.pi * np.arange(1, nc + 1) / nc))
+    assert np.abs(ev - ref).max() <= 1e-13
+
+
+@pytest.mark.parametrize("cells,N,per", [((4, 3), 2, (False, False)), ((3, 4), 3, (True, False)),
+                                         ((3, 3), 3, (False, False)), ((3, 2, 3), 2, (True, False, True)),
+                                         ((2, 3, 2), 1, (False, True, False))])
+def test_dirichlet_symmetry_and_nullity(cells, N, per):
+    """Symmetric; null space = tensor products of the per-direction kernels: the cell-periodic
+    kernel (1 or 2 modes) along periodic directions, its odd mode along Dirichlet directions for
+    odd N and none for even N (SPD whenever a Dirichlet direction has even N)."""
+    from oracle.operators import null_bases
+    g = Grid(cells, (1.0, 0.8, 1.1)[:len(cells)], N, periodic=per)
+    A = pressure_operator(g, 1e-3).toarray()
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    ev = np.linalg.eigvalsh(A)
+    zero = np.abs(ev) <= 1e-10 * np.abs(ev).max()
+    expect = int(np.prod([z.shape[1] for z in null_bases(g)]))
+    assert int(zero.sum()) == expect
+    assert ev[~zero].min() > 0
+
+
+@pytest.mark.parametrize("N,order,per", [(0, 1.7, (False, False)), (1, 0.7, (False, False)),
+                                         (2, 2.7, (False, False)), (3, 2.7, (False, False)),
+                                         (4, 4.7, (False, False)), (2, 2.7, (True, False)),
+                                         (4, 4.7, (True, False))])
+def test_dirichlet_manufactured_convergence(N, order, per):
+    """Manufactured pressure vanishing on the Dirichlet walls (sin pi y, and sin pi x or
+    cos 2 pi x along x): the same orders as the periodic operator (N + 1 for even N, about N for
+    odd N), so the reflection imposes the wall condition without losing accuracy."""
+    def err(nx):
+        g = Grid((nx, nx), (1.0, 1.0), N, periodic=per)
+        fd = FastDiag(g)
+        dt = 1e-3
+        mc = synthetic.main_coords(g.cells, g.lengths, g.tab.xi)
+        if per[0]:
+            px, lap = np.cos(2 * np.pi * mc[0]), 5 * np.pi ** 2
+        else:
+            px, lap = np.sin(np.pi * mc[0]), 2 * np.pi ** 2
+        p = px[None, :] * np.sin(np.pi * mc[1])[:, None]
+        W = np.outer(np.tile(g.tab.w, nx), np.tile(g.tab.w, nx))
+        P = fd.solve(dt * W * lap * p, 0.0, dt)
+        pp = project_null(g, p, fd.Z)
+        return np.sqrt(np.sum(W * (P - pp) ** 2) * g.h[0] * g.h[1])
+    e8, e16 = err(8), err(16)
+    assert np.log2(e8 / e16) >= order
+
+
+def test_dirichlet_apply_at_and_matrix_free_match_assembled():
+    """The single-output and matrix-free evaluations follow the same reflection as the
+    assembled operator."""
+    g = Grid((4, 3, 3), (1.0, 0.9, 1.2), 2, periodic=(False, True, False))
+    dt = 1e-3
+    A = viscous_operator(g, dt, 0.7)
+    X = np.random.default_rng(3).standard_normal(g.shape())
+    ref = (A @ X.reshape(-1)).reshape(g.shape())
+    assert np.abs(apply_operator(g, X, 1.0, 0.7 * dt) - ref).max() <= 1e-12 * np.abs(ref).max()
+    idx = np.array([[0, 0, 0], [8, 8, 11], [4, 2, 0], [0, 5, 11], [8, 0, 6]])
+    got = apply_at(g, X, idx, 1.0, 0.7 * dt)
+    assert np.abs(got - ref[tuple(idx.T)]).max() <= 1e-12 * np.abs(ref).max()
