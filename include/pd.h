@@ -81,9 +81,17 @@ typedef struct {
 /* Create a context: computes the 1D tables of eq. (matrices), eq. (pSyst) and eq. (l2forward) in
  * FP64 on the host for degree N (0 <= N <= 8), uploads FP64 and FP32 copies, and allocates the
  * solver workspace. dim is 2 or 3; ncell[d] >= 1 and len[d] > 0 for d < dim; dt > 0;
- * 0.5 <= theta <= 1 (theta of eq. uSDG1); nu >= 0. periodic_mask: bit d set = periodic along d;
- * only fully periodic grids are supported (PD_EINVAL otherwise). On error *out is NULL and the
- * message is available from pd_last_error(NULL). */
+ * 0.5 <= theta <= 1 (theta of eq. uSDG1); nu >= 0. periodic_mask: bit d set = periodic along d
+ * (bits at or above dim: PD_EINVAL). A clear bit puts homogeneous Dirichlet pressure walls at
+ * both ends of direction d (p = 0 on the wall, the boundary case of eq. (pSyst)): the ghost
+ * cell beyond a wall holds the adjacent cell's pressure reflected about the wall with its sign
+ * flipped, so the wall rows of the 1D operator are (C - L J) P_0 + R P_1 and
+ * L P_{m-2} + (C - R J) P_{m-1}, J reversing the node order. Along such a direction the null
+ * space of A_p shrinks to the part of the cell-periodic kernel that is odd about the cell centre
+ * (none for even N, so A_p is then definite). Walls cover pd_apply, pd_cg_solve,
+ * pd_project_null and pd_project_null_noalloc; every velocity, step, adjoint and loss entry
+ * point and PD_CFG_PRECOND require a fully periodic context (PD_EINVAL otherwise). On error
+ * *out is NULL and the message is available from pd_last_error(NULL). */
 int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int N,
              double dt, double theta, double nu, unsigned periodic_mask, void* hip_stream);
 
@@ -103,10 +111,12 @@ int pd_nodes(const pd_ctx* ctx, double* xi, double* w);
  * which = PD_TAB_NODES (N+1 Gauss-Legendre nodes on [0,1]), PD_TAB_WEIGHTS (N+1 weights),
  * PD_TAB_L / PD_TAB_C / PD_TAB_R ((N+1)^2 entries, row-major: the blocks L, C, R of the 1D
  * pressure operator of eq. (pSyst) / (PerPrSyst)), PD_TAB_PNULL ((N+1)^2: orthogonal projector
- * onto the cell-periodic kernel of the weak gradient, null(R~ - L~)). out must hold that many
+ * onto the cell-periodic kernel of the weak gradient, null(R~ - L~)), PD_TAB_PNULL_ODD
+ * ((N+1)^2: orthogonal projector onto the part of that kernel odd about the cell centre, the
+ * 1D null space along a Dirichlet direction; all zeros for even N). out must hold that many
  * doubles. Returns the number of values written, or PD_EINVAL. */
 enum { PD_TAB_NODES = 0, PD_TAB_WEIGHTS = 1, PD_TAB_L = 2, PD_TAB_C = 3, PD_TAB_R = 4,
-       PD_TAB_PNULL = 5 };
+       PD_TAB_PNULL = 5, PD_TAB_PNULL_ODD = 6 };
 int pd_table_1d(int N, int which, double* out);
 
 /* y = A x for op PD_OP_PRESSURE or PD_OP_VISCOUS; x, y: ndof elements of precision prec
@@ -141,7 +151,8 @@ int pd_project_velocity(pd_ctx* ctx, const void* q, void* const u[3], void* hip_
 
 /* Null-space projection v <- v - Z Z^T v of an FP64 (prec = PD_FP64) or FP32 main-grid field,
  * Z = orthonormal basis of null(A_p) (tensor products of the cell-periodic null vectors of the
- * 1D weak gradient: 1 per direction for even N, 2 for odd N). In place. */
+ * 1D weak gradient: 1 per direction for even N, 2 for odd N; along a Dirichlet direction only the
+ * odd one, so no projection at all when N is even and a wall exists). In place. */
 int pd_project_null(pd_ctx* ctx, int prec, void* v, void* hip_stream);
 
 /* Allocation-free variant of pd_project_null, for callers that cannot allocate device memory

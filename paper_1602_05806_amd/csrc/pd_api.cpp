@@ -20,6 +20,8 @@ using pdk::CgState;
 struct pd_ctx {
   int dim = 2, N = 0, n = 1, NC = 1;
   int nc[3] = {1, 1, 1};
+  int per[3] = {1, 1, 1};      // 0: homogeneous Dirichlet pressure walls across direction d
+  bool periodic = true;        // every direction periodic
   double len[3] = {1, 1, 1}, h[3] = {1, 1, 1};
   double dt = 0, theta = 1, nu = 0;
   long long ncells = 0, ndof = 0;
@@ -129,6 +131,7 @@ pdk::ApplyLaunch base_launch(const pd_ctx* c, int op, bool fp32) {
   L.tiles_per_wg = c->tiles_per_wg;
   L.prefetch = c->prefetch;
   L.tile_variant = c->tile_variant;
+  for (int d = 0; d < c->dim; ++d) L.mir[d] = c->per[d] ? 0 : 1;
   return L;
 }
 
@@ -140,10 +143,32 @@ int plain_apply(pd_ctx* c, int op, bool fp32, const void* x, void* y, hipStream_
   return PD_OK;
 }
 
+// Per-direction projectors onto the 1D null space: the cell-periodic kernel of D along periodic
+// directions, its odd part along Dirichlet directions. false when a direction has none (then
+// the operator has no null space and the projection is the identity).
+bool null_projectors(const pd_ctx* c, const double* P[3]) {
+  for (int d = 0; d < 3; ++d) {
+    P[d] = c->tab.Pnull;
+    if (d < c->dim && !c->per[d]) {
+      if (c->tab.nnull_odd == 0) return false;
+      P[d] = c->tab.PnullOdd;
+    }
+  }
+  return true;
+}
+
 int project_null(pd_ctx* c, bool fp32, void* v, hipStream_t s) {
-  PD_HIP(c, pdk::launch_project_null(fp32, v, c->ncells, c->dim, c->n, c->tab.Pnull,
-                                     c->null_part, c->null_corr, s));
+  const double* P[3];
+  if (!null_projectors(c, P)) return PD_OK;
+  PD_HIP(c, pdk::launch_project_null(fp32, v, c->ncells, c->dim, c->n, P, c->null_part,
+                                     c->null_corr, s));
   return PD_OK;
+}
+
+int require_periodic(pd_ctx* c, const char* what) {
+  if (c->periodic) return PD_OK;
+  return fail(c, PD_EINVAL, std::string(what) + ": fully periodic grids only (the Dirichlet "
+                            "walls cover the pressure and viscous operators and their solves)");
 }
 
 // <a, b> -> st->aux (FIN_AUX) or bnorm2/tol2 (FIN_BNORM), on the stream.
@@ -226,6 +251,9 @@ int pcg_init(pd_ctx* c, const struct CgRun* R, int slot, hipStream_t s);
 // whose CG state holds tol2 / maxit.
 int cg_prepare(pd_ctx* c, CgRun* R) {
   R->pc = c->precond != 0;
+  if (R->pc && !c->periodic)
+    return fail(c, PD_EINVAL, "PD_CFG_PRECOND: fully periodic grids only (the wall cells' "
+                              "diagonal blocks differ from the interior block)");
   R->nrho = R->pc ? (int)pdk::pcg_grid(c->ncells, c->dim, c->N) : (int)pdk::stream_grid(c->ndof);
   R->rho[0] = c->rhopart;
   R->rho[1] = c->rhopart + pdk::kMaxStreamPartials;
@@ -986,8 +1014,8 @@ int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int
   if (!(theta >= 0.5 && theta <= 1.0)) return fail(nullptr, PD_EINVAL, "theta must be in [0.5, 1]");
   if (!(nu >= 0.0)) return fail(nullptr, PD_EINVAL, "nu must be >= 0");
   const unsigned need = (1u << dim) - 1u;
-  if ((periodic_mask & need) != need)
-    return fail(nullptr, PD_EINVAL, "only fully periodic grids are supported");
+  if (periodic_mask & ~need)
+    return fail(nullptr, PD_EINVAL, "periodic_mask has bits beyond dim");
   pd_ctx* c = new pd_ctx();
   std::string e;
   if (!pdh::build_table(N, &c->tab, &e)) {
@@ -997,6 +1025,8 @@ int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int
   c->dim = dim;
   c->N = N;
   c->n = N + 1;
+  for (int d = 0; d < 3; ++d) c->per[d] = d < dim ? (int)((periodic_mask >> d) & 1u) : 1;
+  c->periodic = (periodic_mask & need) == need;
   c->NC = dim == 3 ? c->n * c->n * c->n : c->n * c->n;
   c->ncells = 1;
   for (int d = 0; d < dim; ++d) {
@@ -1132,7 +1162,7 @@ int pd_nodes(const pd_ctx* c, double* xi, double* w) {
 }
 
 int pd_table_1d(int N, int which, double* out) {
-  if (!out || which < PD_TAB_NODES || which > PD_TAB_PNULL) return PD_EINVAL;
+  if (!out || which < PD_TAB_NODES || which > PD_TAB_PNULL_ODD) return PD_EINVAL;
   pdh::Table1D t;
   std::string e;
   if (!pdh::build_table(N, &t, &e)) return PD_EINVAL;
@@ -1145,6 +1175,7 @@ int pd_table_1d(int N, int which, double* out) {
     case PD_TAB_L: src = t.Lb; break;
     case PD_TAB_C: src = t.Cb; break;
     case PD_TAB_R: src = t.Rb; break;
+    case PD_TAB_PNULL_ODD: src = t.PnullOdd; break;
     default: src = t.Pnull; break;
   }
   for (int i = 0; i < cnt; ++i) out[i] = src[i];
@@ -1169,6 +1200,7 @@ int pd_cg_solve(pd_ctx* c, int op, int prec, const void* b, void* x, double rtol
 
 int pd_rhs_div(pd_ctx* c, void* const u[3], void* b, void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_rhs_div")) return rc0;
   if (!u || !b) return fail(c, PD_EINVAL, "null array");
   c->last_stream = S(hip_stream);
   return rhs_div(c, u, (double*)b, S(hip_stream));
@@ -1176,6 +1208,7 @@ int pd_rhs_div(pd_ctx* c, void* const u[3], void* b, void* hip_stream) {
 
 int pd_project_velocity(pd_ctx* c, const void* q, void* const u[3], void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_project_velocity")) return rc0;
   if (!q || !u) return fail(c, PD_EINVAL, "null array");
   c->last_stream = S(hip_stream);
   return project_velocity(c, (const double*)q, u, S(hip_stream));
@@ -1196,13 +1229,16 @@ int pd_project_null_noalloc(pd_ctx* c, int prec, void* v, void* hip_stream) {
   if ((size_t)(256 + 1) * c->NC * sizeof(double) > pdk::noalloc_scratch_bytes())
     return fail(c, PD_EINVAL, "pd_project_null_noalloc: (N+1)^dim exceeds the fixed scratch");
   c->last_stream = S(hip_stream);
-  PD_HIP(c, pdk::launch_project_null_noalloc(prec == PD_FP32, v, c->ncells, c->dim, c->n,
-                                             c->tab.Pnull, S(hip_stream)));
+  const double* P[3];
+  if (!null_projectors(c, P)) return PD_OK;
+  PD_HIP(c, pdk::launch_project_null_noalloc(prec == PD_FP32, v, c->ncells, c->dim, c->n, P,
+                                             S(hip_stream)));
   return PD_OK;
 }
 
 int pd_l2_project(pd_ctx* c, int d, int dir, const void* in, void* out, void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_l2_project")) return rc0;
   if (d < 0 || d >= c->dim || (dir != 0 && dir != 1)) return fail(c, PD_EINVAL, "bad direction");
   if (!in || !out || in == out) return fail(c, PD_EINVAL, "null or aliased array");
   c->last_stream = S(hip_stream);
@@ -1211,6 +1247,7 @@ int pd_l2_project(pd_ctx* c, int d, int dir, const void* in, void* out, void* hi
 
 int pd_convect(pd_ctx* c, void* const um[3], void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_convect")) return rc0;
   if (!um) return fail(c, PD_EINVAL, "null array");
   for (int d = 0; d < c->dim; ++d)
     if (!um[d]) return fail(c, PD_EINVAL, "null velocity component");
@@ -1223,6 +1260,7 @@ int pd_convect(pd_ctx* c, void* const um[3], void* hip_stream) {
 
 int pd_step(pd_ctx* c, void* const u[3], void* p, pd_solve_info info[4], void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_step")) return rc0;
   if (!u || !p) return fail(c, PD_EINVAL, "null array");
   for (int d = 0; d < c->dim; ++d)
     if (!u[d]) return fail(c, PD_EINVAL, "null velocity component");
@@ -1273,6 +1311,7 @@ int pd_step(pd_ctx* c, void* const u[3], void* p, pd_solve_info info[4], void* h
 int pd_step_st(pd_ctx* c, int M, void* const u[3], void* p_nodes, pd_solve_info* info,
                void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_step_st")) return rc0;
   if (!u || !p_nodes) return fail(c, PD_EINVAL, "null array");
   for (int d = 0; d < c->dim; ++d) {
     if (!u[d] || u[d] == p_nodes) return fail(c, PD_EINVAL, "null or aliased velocity component");
@@ -1433,6 +1472,7 @@ int pd_time_table(int M, int which, double* out) {
 int pd_l2_project_adjoint(pd_ctx* c, int d, int dir, const void* in, void* out,
                           void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_l2_project_adjoint")) return rc0;
   if (d < 0 || d >= c->dim || (dir != 0 && dir != 1)) return fail(c, PD_EINVAL, "bad direction");
   if (!in || !out || in == out) return fail(c, PD_EINVAL, "null or aliased array");
   c->last_stream = S(hip_stream);
@@ -1441,6 +1481,7 @@ int pd_l2_project_adjoint(pd_ctx* c, int d, int dir, const void* in, void* out,
 
 int pd_rhs_div_adjoint(pd_ctx* c, const void* bbar, void* const ubar[3], void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_rhs_div_adjoint")) return rc0;
   if (!bbar || !ubar) return fail(c, PD_EINVAL, "null array");
   c->last_stream = S(hip_stream);
   return rhs_div_T(c, (const double*)bbar, ubar, 0.0, S(hip_stream));
@@ -1448,6 +1489,7 @@ int pd_rhs_div_adjoint(pd_ctx* c, const void* bbar, void* const ubar[3], void* h
 
 int pd_project_velocity_adjoint(pd_ctx* c, void* const ubar[3], void* qbar, void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_project_velocity_adjoint")) return rc0;
   if (!ubar || !qbar) return fail(c, PD_EINVAL, "null array");
   c->last_stream = S(hip_stream);
   return project_velocity_T(c, ubar, (double*)qbar, S(hip_stream));
@@ -1455,6 +1497,7 @@ int pd_project_velocity_adjoint(pd_ctx* c, void* const ubar[3], void* qbar, void
 
 int pd_convect_adjoint(pd_ctx* c, void* const um[3], void* const ubar[3], void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_convect_adjoint")) return rc0;
   if (c->explicit_visc)
     return fail(c, PD_EINVAL, "the adjoint covers the convective flux only (PD_CFG_EXPLICIT_VISC set)");
   if (!um || !ubar) return fail(c, PD_EINVAL, "null array");
@@ -1477,6 +1520,7 @@ int pd_convect_adjoint(pd_ctx* c, void* const um[3], void* const ubar[3], void* 
 int pd_step_adjoint(pd_ctx* c, void* const u[3], void* const ubar[3], pd_solve_info info[4],
                     void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_step_adjoint")) return rc0;
   if (!u || !ubar) return fail(c, PD_EINVAL, "null array");
   for (int d = 0; d < c->dim; ++d)
     if (!u[d] || !ubar[d] || u[d] == ubar[d]) return fail(c, PD_EINVAL, "null or aliased component");
@@ -1548,6 +1592,7 @@ int pd_step_adjoint(pd_ctx* c, void* const u[3], void* const ubar[3], pd_solve_i
 int pd_kinetic_energy(pd_ctx* c, void* const u[3], double gscale, void* const grad[3],
                       double* energy, void* hip_stream) {
   if (!c) return PD_EINVAL;
+  if (int rc0 = require_periodic(c, "pd_kinetic_energy")) return rc0;
   if (!u || !energy) return fail(c, PD_EINVAL, "null argument");
   if (!std::isfinite(gscale)) return fail(c, PD_EINVAL, "gscale must be finite");
   for (int d = 0; d < c->dim; ++d) {

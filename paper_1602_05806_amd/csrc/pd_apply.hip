@@ -66,6 +66,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   __shared__ T xs[NS * NC];
   __shared__ T ys[NT * NC];
   __shared__ int hbase[NS];     // in-plane cell index (j*nx + i, wrapped) of every halo slot
+  __shared__ int hmir[NS];      // bit 0 / 1: the slot is the odd reflection across an x / y wall
   // launches queued after the run stopped exit before loading anything
   const int kit = FUSE ? (a.kbase ? *a.kbase + a.k : a.k) : 0;
   if (FUSE) {
@@ -86,7 +87,17 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     else if (s < S_YL) { hi = TX; hj = s - S_XR; }
     else if (s < S_YR) { hi = s - S_YL; hj = -1; }
     else { hi = s - S_YR; hj = TY; }
-    hbase[s] = wrapi(ty0 + hj, a.ny) * a.nx + wrapi(tx0 + hi, a.nx);
+    int ri = tx0 + hi, rj = ty0 + hj, m = 0;
+    if (a.mir[0] && (ri < 0 || ri >= a.nx)) {
+      ri = mirror_index(ri, a.nx);
+      m |= 1;
+    }
+    if (a.mir[1] && (rj < 0 || rj >= a.ny)) {
+      rj = mirror_index(rj, a.ny);
+      m |= 2;
+    }
+    hbase[s] = wrapi(rj, a.ny) * a.nx + wrapi(ri, a.nx);
+    hmir[s] = m;
   }
   __syncthreads();   // hbase ready
 
@@ -95,15 +106,31 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   const int ci = c % TX, cj = c / TX;
   const int ui = tx0 + ci, uj = ty0 + cj;
   const bool valid = ui < a.nx && uj < a.ny;
-  const int gi = wrapi(ui, a.nx), gj = wrapi(uj, a.ny);
+  // a ragged tile's cells beyond a Dirichlet wall hold the odd reflection of the cells inside
+  // (they are the x / y neighbours of the last valid cells); their z-lines read the mirrored
+  // source line with the sign flipped
+  int si = ui, sj = uj, slp = lp;
+  T sgn = T(1);
+  if (a.mir[0] && ui >= a.nx) {
+    si = mirror_index(ui, a.nx);
+    slp = (slp / n) * n + (n - 1 - slp % n);
+    sgn = -sgn;
+  }
+  if (a.mir[1] && uj >= a.ny) {
+    sj = mirror_index(uj, a.ny);
+    slp = (n - 1 - slp / n) * n + slp % n;
+    sgn = -sgn;
+  }
+  const int gi = wrapi(si, a.nx), gj = wrapi(sj, a.ny);
   const size_t plane = (size_t)a.nx * a.ny;
   T beta = T(0);
   bool xupd = false;   // FUSE = 2: x += xalpha p_old on the owned z-line
   T xalpha = T(0);
 
   auto zbase = [&](int k) -> size_t {
-    return (((size_t)wrap_small(k, a.nz) * a.ny + gj) * a.nx + gi) * NC + lp;
+    return (((size_t)wrap_small(k, a.nz) * a.ny + gj) * a.nx + gi) * NC + slp;
   };
+
   T zp[n], zc[n], zn[n];
   {
     // first two planes of this thread's z-line; the CG scalars are reduced while they load
@@ -111,11 +138,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     T pp[n], pc[n], xc[FUSE == 2 ? n : 1];
 #pragma unroll
     for (int l3 = 0; l3 < n; ++l3) {
-      zp[l3] = xg[bp + l3 * NP];
-      zc[l3] = xg[bc + l3 * NP];
+      zp[l3] = sgn * xg[bp + l3 * NP];
+      zc[l3] = sgn * xg[bc + l3 * NP];
       if (FUSE) {
-        pp[l3] = pg[bp + l3 * NP];
-        pc[l3] = pg[bc + l3 * NP];
+        pp[l3] = sgn * pg[bp + l3 * NP];
+        pc[l3] = sgn * pg[bc + l3 * NP];
       }
       if (FUSE == 2) xc[l3] = a.xsol[bc + l3 * NP];
     }
@@ -139,6 +166,12 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
           if (FUSE == 2 && xupd) a.xsol[bc + l3 * NP] = xc[l3] + xalpha * pc[l3];
         }
       }
+    }
+    // the plane below a Dirichlet wall at z = 0: odd reflection of plane 0 (stores are valid
+    // cells' own planes only, so valid stores are unaffected)
+    if (a.mir[2] && k0 == 0) {
+#pragma unroll
+      for (int l3 = 0; l3 < n; ++l3) zp[l3] = -zc[n - 1 - l3];
     }
   }
   // per-thread x-line and y-line coordinates (one line per thread in each direction)
@@ -166,6 +199,21 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lane = t & 63;
   T hv[HR][LR], hp[HR][LR];
+  // source element of halo element l of slot s (odd reflection across x / y walls)
+  auto hsrc = [&](int s, int l, T& sg) -> int {
+    const int m = hmir[s];
+    sg = T(1);
+    if (m & 1) {
+      l = l - l % n + (n - 1 - l % n);
+      sg = -sg;
+    }
+    if (m & 2) {
+      const int l2 = (l / n) % n;
+      l = l + (n - 1 - 2 * l2) * n;
+      sg = -sg;
+    }
+    return l;
+  };
   auto halo_load = [&](int k) {
     const size_t pb = (size_t)wrap_small(k, a.nz) * plane;
 #pragma unroll
@@ -177,8 +225,10 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
         for (int r = 0; r < LR; ++r) {
           const int l = lane + 64 * r;
           if (l < NC) {
-            hv[i][r] = xg[g + l];
-            if (FUSE) hp[i][r] = pg[g + l];
+            T sg;
+            const int ls = hsrc(s, l, sg);
+            hv[i][r] = sg * xg[g + ls];
+            if (FUSE) hp[i][r] = sg * pg[g + ls];
           }
         }
       }
@@ -204,8 +254,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
       const int s = NT + wave + NWV * i;
       if (wave < NWV && s < NS) {
         const size_t g = (pb + (size_t)hbase[s]) * NC;
-        for (int l = lane; l < NC; l += 64)
-          xs[s * NC + l] = FUSE ? (T)(xg[g + l] + beta * pg[g + l]) : xg[g + l];
+        for (int l = lane; l < NC; l += 64) {
+          T sg;
+          const int ls = hsrc(s, l, sg);
+          xs[s * NC + l] = sg * (FUSE ? (T)(xg[g + ls] + beta * pg[g + ls]) : xg[g + ls]);
+        }
       }
     }
   };
@@ -223,8 +276,8 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     T pn[n], xn[FUSE == 2 ? n : 1];
 #pragma unroll
     for (int l3 = 0; l3 < n; ++l3) {
-      zn[l3] = xg[bn + l3 * NP];
-      if (FUSE) pn[l3] = pg[bn + l3 * NP];
+      zn[l3] = sgn * xg[bn + l3 * NP];
+      if (FUSE) pn[l3] = sgn * pg[bn + l3 * NP];
       if (FUSE == 2 && xupd && own_next) xn[l3] = a.xsol[bn + l3 * NP];
     }
     if constexpr (PREF) {
@@ -262,6 +315,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
           if (FUSE == 2 && xupd) a.xsol[bn + l3 * NP] = xn[l3] + xalpha * pn[l3];
         }
       }
+    }
+    // the plane above a Dirichlet wall at z = L: odd reflection of the last plane
+    if (a.mir[2] && k + 1 == a.nz) {
+#pragma unroll
+      for (int l3 = 0; l3 < n; ++l3) zn[l3] = -zc[n - 1 - l3];
     }
     {  // own z-line (l1, l2) from registers; final values
       const size_t bc = zbase(k);
@@ -461,6 +519,7 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   a.kbase = nullptr;
   a.rho_cur = L.rho_cur;
   a.res_cur = L.res_cur;
+  for (int d = 0; d < 3; ++d) a.mir[d] = L.mir[d];
   a.nrho = L.nrho;
   a.sigpart = L.sigpart;
   a.xsol = (T*)L.xsol;

@@ -40,7 +40,16 @@ struct ApplyArgs {
   int npart;
   int first;
   int remap;          // single-problem 2D launch: 1 = XCD-contiguous tile ranges (xcd_remap)
+  // mir[d] = 1: homogeneous Dirichlet pressure walls across direction d (the cells beyond a
+  // wall hold the odd reflection -J of the adjacent cell: index mirrored, node order reversed
+  // along d, sign flipped); 0: periodic wrap
+  int mir[3];
 };
+
+// Mirror a cell index beyond a Dirichlet wall onto the domain: -1 -> 0, m -> m - 1, ...
+__device__ __forceinline__ int mirror_index(int i, int m) {
+  return i < 0 ? -1 - i : 2 * m - 1 - i;
+}
 
 __device__ __forceinline__ int wrapi(int i, int m) {
   i %= m;
@@ -144,33 +153,55 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
   T rki[RU ? TY : 1][RU ? JI : 1];              // r_k of the owned cells (for <r_k, A p_k>)
   const bool rupd = RU && !a.first;
 
-  // global element index of box element e of box row bj (bj in 0..TY+1) of the tile at (tx0, ty0)
-  auto gindex = [&](int tx0, int ty0, int bj, int e) -> size_t {
+  // global element index of box element e of box row bj (bj in 0..TY+1) of the tile at (tx0, ty0);
+  // neg: the element is the odd reflection of that source across a Dirichlet wall
+  auto gindex = [&](int tx0, int ty0, int bj, int e, bool& neg) -> size_t {
     const int first = (bj == 0 || bj == TY + 1) ? 0 : -1;   // first tile column of the row
-    const int cr = e / NC, l = e - cr * NC;
-    const int gi = wrap_small(tx0 + first + cr, a.nx);
-    const int gj = wrap_small(ty0 + bj - 1, a.ny);
+    const int cr = e / NC;
+    int l = e - cr * NC;
+    int ri = tx0 + first + cr, rj = ty0 + bj - 1;
+    neg = false;
+    if (a.mir[0] && (ri < 0 || ri >= a.nx)) {
+      ri = mirror_index(ri, a.nx);
+      l = (l / n) * n + (n - 1 - l % n);
+      neg = !neg;
+    }
+    if (a.mir[1] && (rj < 0 || rj >= a.ny)) {
+      rj = mirror_index(rj, a.ny);
+      l = (n - 1 - l / n) * n + l % n;
+      neg = !neg;
+    }
+    const int gi = wrap_small(ri, a.nx);
+    const int gj = wrap_small(rj, a.ny);
     return ((size_t)gj * a.nx + gi) * NC + l;
   };
   // box rows [bj_lo, bj_hi) of a tile into registers
   auto stage_load = [&](int tile, int bj_lo, int bj_hi) {
     const int tx0 = (tile % a.ntx) * TX, ty0 = (tile / a.ntx) * TY;
-    const bool flat = tx0 >= 1 && tx0 + TX + 1 <= a.nx;        // no row crosses the x seam
+    const bool flat = tx0 >= 1 && tx0 + TX + 1 <= a.nx;        // no row crosses the x seam / a wall
 #pragma unroll
     for (int bj = 0; bj < TY + 2; ++bj) {
       if (bj < bj_lo || bj >= bj_hi) continue;
       const bool halo = bj == 0 || bj == TY + 1;
-      const int gj = wrap_small(ty0 + bj - 1, a.ny);
+      const int rj = ty0 + bj - 1;
+      const bool rowflat = flat && !(a.mir[1] && (rj < 0 || rj >= a.ny));
+      const int gj = wrap_small(rj, a.ny);
       const size_t row0 = ((size_t)gj * a.nx + (halo ? tx0 : tx0 - 1)) * NC;
       constexpr int J = JI > JH ? JI : JH;
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         const int e = tid + 256 * j;
         if (e < (halo ? RH : RI)) {
-          const size_t g = flat ? row0 + e : gindex(tx0, ty0, bj, e);
+          bool neg = false;
+          const size_t g = rowflat ? row0 + e : gindex(tx0, ty0, bj, e, neg);
           T rv = xg[g], pv = T(0), qv = T(0);
           if (FUSE) pv = pg[g];
           if (rupd) qv = a.qprev[g];
+          if (neg) {
+            rv = -rv;
+            pv = -pv;
+            qv = -qv;
+          }
           if (halo) {
             if (j < JH) {
               rvh[bj ? 1 : 0][j] = rv;

@@ -199,6 +199,7 @@ __global__ __launch_bounds__(256) void k_apply2d_batch(BatchIter it, const int* 
   a.kbase = it.kbase;
   a.rho_cur = rho_slot(it, j, it.koff);
   a.res_cur = nullptr;
+  a.mir[0] = a.mir[1] = a.mir[2] = 0;
   a.nrho = P.nupd;
   a.sigpart = it.sig + P.sig_off;
   a.xsol = FUSE == 2 ? xsol + P.dof_off : nullptr;

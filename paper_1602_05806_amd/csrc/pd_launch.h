@@ -46,6 +46,7 @@ struct ApplyLaunch {
   int tiles_per_wg = 0;      // 2D: tiles per persistent workgroup (0 = automatic)
   int prefetch = 1;          // prefetch the next tile (2D) / next plane's halo (3D) into registers
   int tile_variant = 0;      // 2D tile shape (0 = largest fitting, 1 / 2 = one / two sizes smaller)
+  int mir[3] = {0, 0, 0};    // 1: homogeneous Dirichlet pressure walls across direction d
   const OpTables* tab = nullptr;
   hipEvent_t ev_start = nullptr;   // optional events stamped at the kernel's start and end
   hipEvent_t ev_stop = nullptr;
@@ -114,17 +115,18 @@ hipError_t launch_energy(int dim, int N, const double* w, const double* const u[
                          hipStream_t s);
 
 // ---- null-space projection (pd_vec.hip)
-// corr = (P (x) P (x) P) (sum over cells of v) / ncells, then v -= corr per cell.
+// corr = (P_z (x) P_y (x) P_x) (sum over cells of v) / ncells, then v -= corr per cell; Pdir[d]:
+// host (N+1)^2 projector onto the 1D null space of direction d.
 // part: 256 * (N+1)^dim doubles; corr: (N+1)^dim doubles.
 hipError_t launch_project_null(bool fp32, void* v, long long ncells, int dim, int n,
-                               const double* Pnull_host, double* part, double* corr,
+                               const double* const Pdir[3], double* part, double* corr,
                                hipStream_t s);
 
 // The same projection with its scratch (node-sum partials and correction) in a fixed device
 // array of the library instead of caller- or context-owned memory: no allocation. Calls that
 // overlap on one device race on that array.
 hipError_t launch_project_null_noalloc(bool fp32, void* v, long long ncells, int dim, int n,
-                                       const double* Pnull_host, hipStream_t s);
+                                       const double* const Pdir[3], hipStream_t s);
 // device address of the fixed scratch array on the current device (looked up once per device)
 hipError_t noalloc_scratch(double** out);
 size_t noalloc_scratch_bytes();

@@ -203,6 +203,20 @@ bool build_table(int N, Table1D* t, std::string* err) {
         for (int q = 0; q < n; ++q) t->Pnull[p * n + q] += V[p * n + i] * V[q * n + i];
     }
   }
+  // The part of that kernel that is odd about the cell centre: the kernel is invariant under the
+  // node reversal J (GL nodes are symmetric), so the projector onto its odd part is
+  // Pnull (I - J) / 2. It spans the null space of a direction with Dirichlet pressure walls
+  // (odd reflection): the odd mode for odd N, nothing for even N.
+  t->nnull_odd = 0;
+  double tr = 0.0;
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      const double v = 0.5 * (t->Pnull[p * n + q] - t->Pnull[p * n + (n - 1 - q)]);
+      t->PnullOdd[p * n + q] = v;
+      if (p == q) tr += v;
+    }
+  t->nnull_odd = (int)std::lround(tr);
+  if (t->nnull_odd == 0) std::memset(t->PnullOdd, 0, sizeof(t->PnullOdd));
   return true;
 }
 

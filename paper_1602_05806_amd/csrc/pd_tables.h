@@ -32,6 +32,8 @@ struct Table1D {
   double Plam[kMaxn];
   int nnull = 0;                         // dimension of null(R~ - L~) (1 for even N, 2 for odd N)
   double Pnull[kMaxn * kMaxn];           // orthogonal projector onto null(R~ - L~)
+  int nnull_odd = 0;                     // dimension of its part odd about the cell centre
+  double PnullOdd[kMaxn * kMaxn];        // projector onto that part (Dirichlet directions)
 };
 
 // Fills t for degree N. Returns false (with a message) for unsupported N.

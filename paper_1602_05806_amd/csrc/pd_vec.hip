@@ -506,8 +506,9 @@ __global__ __launch_bounds__(kBlock) void k_time_mix(TimeMix X, long long n) {
 // ---- null-space projection: per-node sums over cells, then correction per node
 constexpr int kNullBlocks = 256;
 
+// per-direction projectors onto the 1D null space ((N+1)^2 each)
 struct P81 {
-  double P[81];
+  double P[3][81];
 };
 
 // part[b][l] = sum over the cells of block b of v(cell, l)
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_null_finalize(const double* __restri
       const int ld = (l / stride) % n;
       const int base = l - ld * stride;
       double s = 0.0;
-      for (int m = 0; m < n; ++m) s += P.P[ld * n + m] * S[base + m * stride];
+      for (int m = 0; m < n; ++m) s += P.P[d][ld * n + m] * S[base + m * stride];
       U[l] = s;
     }
     __syncthreads();
@@ -593,13 +594,13 @@ hipError_t noalloc_scratch(double** out) {
 size_t noalloc_scratch_bytes() { return kNoAllocDoubles * sizeof(double); }
 
 hipError_t launch_project_null_noalloc(bool fp32, void* v, long long ncells, int dim, int n,
-                                       const double* Pnull_host, hipStream_t s) {
+                                       const double* const Pdir[3], hipStream_t s) {
   const int NC = dim == 3 ? n * n * n : n * n;
   if (NC > kMaxNC) return hipErrorInvalidValue;
   double* base = nullptr;
   hipError_t e = noalloc_scratch(&base);
   if (e != hipSuccess) return e;
-  return launch_project_null(fp32, v, ncells, dim, n, Pnull_host, base, base + kNoAllocParts, s);
+  return launch_project_null(fp32, v, ncells, dim, n, Pdir, base, base + kNoAllocParts, s);
 }
 
 unsigned stream_grid(long long n) { return stream_blocks(n, 4); }
@@ -827,10 +828,11 @@ hipError_t launch_mass(int dim, int N, const double* w, const double* x, double*
 }
 
 hipError_t launch_project_null(bool fp32, void* v, long long ncells, int dim, int n,
-                               const double* Pnull_host, double* part, double* corr,
+                               const double* const Pdir[3], double* part, double* corr,
                                hipStream_t s) {
   P81 P;
-  for (int i = 0; i < 81; ++i) P.P[i] = i < n * n ? Pnull_host[i] : 0.0;
+  for (int d = 0; d < 3; ++d)
+    for (int i = 0; i < 81; ++i) P.P[d][i] = (d < dim && i < n * n) ? Pdir[d][i] : 0.0;
   const int NC = dim == 3 ? n * n * n : n * n;
   const unsigned G = ncells < kNullBlocks ? (unsigned)ncells : (unsigned)kNullBlocks;
   if (fp32)

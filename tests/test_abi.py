@@ -46,8 +46,9 @@ def test_setup_rejects_bad_arguments_without_touching_the_device(pd):
         with pytest.raises(pd.PdError) as e:
             pd.pd_setup(*args, stream=0)
         assert e.value.code == pd.PD_EINVAL
+    # periodic_mask bits at or above dim (clear bits below dim are Dirichlet walls)
     with pytest.raises(pd.PdError) as e:
-        pd.pd_setup(2, (4, 4), (1.0, 1.0), 2, 1e-3, 0.6, 0.0, periodic_mask=1, stream=0)
+        pd.pd_setup(2, (4, 4), (1.0, 1.0), 2, 1e-3, 0.6, 0.0, periodic_mask=0b111, stream=0)
     assert e.value.code == pd.PD_EINVAL
 
 
@@ -58,11 +59,11 @@ def test_host_tables_match_oracle(pd):
     projector is the identity."""
     import numpy as np
     from oracle.basis import tables
-    from oracle.operators import null_basis_tiled
+    from oracle.operators import null_basis_dirichlet, null_basis_tiled
     for N in range(9):
         t = tables(N)
         n = N + 1
-        got = {w: np.array(pd.pd_table_1d(N, w)) for w in range(6)}
+        got = {w: np.array(pd.pd_table_1d(N, w)) for w in range(7)}
         assert np.abs(got[pd.PD_TAB_NODES] - t.xi).max() <= 1e-15
         assert np.abs(got[pd.PD_TAB_WEIGHTS] - t.w).max() <= 1e-15
         for which, blk in ((pd.PD_TAB_L, t.Lblk), (pd.PD_TAB_C, t.Cblk), (pd.PD_TAB_R, t.Rblk)):
@@ -70,6 +71,11 @@ def test_host_tables_match_oracle(pd):
         Z = null_basis_tiled(1, N)
         assert np.abs(got[pd.PD_TAB_PNULL].reshape(n, n) - Z @ Z.T).max() <= 1e-12
         assert round(float(np.trace(got[pd.PD_TAB_PNULL].reshape(n, n)))) == (1 if N % 2 == 0 else 2)
+        # the 1D null space along a Dirichlet direction: the odd part of that kernel
+        Zo = null_basis_dirichlet(1, N)
+        podd = np.array(pd.pd_table_1d(N, pd.PD_TAB_PNULL_ODD)).reshape(n, n)
+        assert np.abs(podd - Zo @ Zo.T).max() <= 1e-12
+        assert round(float(np.trace(podd))) == (0 if N % 2 == 0 else 1)
     import pytest
     with pytest.raises(pd.PdError):
         pd.pd_table_1d(9, 0)
