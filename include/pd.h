@@ -287,7 +287,8 @@ int pd_kinetic_energy(pd_ctx* ctx, void* const u[3], double gscale, void* const 
  *   PD_CFG_PREFETCH      1 (default) = the operator kernel prefetches the next tile (2D) or the
  *                        next plane's halo (3D) into registers during compute, 0 = no prefetch
  *   PD_CFG_TILE_VARIANT  2D operator kernel tile shape: 0 (default) = the largest tile of cells
- *                        whose LDS box fits, 1 / 2 = one / two sizes smaller (more workgroups)
+ *                        whose LDS box fits, 1 / 2 = one / two sizes smaller (more workgroups);
+ *                        a grid with walls always runs 0 with prefetch (both settings ignored)
  *   PD_CFG_DEFER_X       where CG iteration k's x += alpha_k p_k is made: 1 (default) = in the
  *                        operator kernel of iteration k + 1 (it reads p_k anyway; 9 instead of
  *                        10 vector words per DoF and iteration), 0 = in the update kernel

@@ -132,6 +132,10 @@ pdk::ApplyLaunch base_launch(const pd_ctx* c, int op, bool fp32) {
   L.prefetch = c->prefetch;
   L.tile_variant = c->tile_variant;
   for (int d = 0; d < c->dim; ++d) L.mir[d] = c->per[d] ? 0 : 1;
+  if (!c->periodic) {   // grids with walls run one kernel shape: tile variant 0, prefetch on
+    L.tile_variant = 0;
+    L.prefetch = 1;
+  }
   return L;
 }
 

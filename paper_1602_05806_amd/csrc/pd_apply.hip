@@ -40,11 +40,12 @@ namespace pdk {
 // (a.remap = 0) lw is the dispatch order itself, which deals neighbouring tiles to different
 // XCDs: 256^2 N = 6 FP32 28.6 against 30.3 us, 256^2 N = 3 FP64 16.7 against 17.5 us (with
 // several tiles per workgroup or several waves the XCD-contiguous index is as fast or faster).
-template <typename T, int N, int V, int FUSE, int PF>
+// MIR: Dirichlet walls (a grid with walls runs tile variant 0 with prefetch).
+template <typename T, int N, int V, int FUSE, int PF, bool MIR = false>
 __global__ __launch_bounds__(256) void k_apply2d(ApplyArgs<T> a, Blk<T, N> B) {
   const unsigned lw = a.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int ntiles = a.ntx * a.nty;
-  apply2d_body<T, N, V, FUSE, PF>(a, B, (int)lw, ntiles, (int)gridDim.x, blockIdx.x);
+  apply2d_body<T, N, V, FUSE, PF, MIR>(a, B, (int)lw, ntiles, (int)gridDim.x, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ 3D z-marching kernel
@@ -56,7 +57,8 @@ struct Tile3D {
   static constexpr int NTH = TX * TY * (N + 1) * (N + 1);
 };
 
-template <typename T, int N, int FUSE, int PF>
+// MIR: the grid has Dirichlet walls (a.mir); the periodic kernel carries none of their code.
+template <typename T, int N, int FUSE, int PF, bool MIR>
 __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<T, N> B) {
   constexpr int n = N + 1, NP = n * n, NC = n * n * n;
   constexpr int TX = Tile3D<N>::TX, TY = Tile3D<N>::TY, NT = TX * TY, NTH = Tile3D<N>::NTH;
@@ -88,16 +90,16 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     else if (s < S_YR) { hi = s - S_YL; hj = -1; }
     else { hi = s - S_YR; hj = TY; }
     int ri = tx0 + hi, rj = ty0 + hj, m = 0;
-    if (a.mir[0] && (ri < 0 || ri >= a.nx)) {
+    if (MIR && a.mir[0] && (ri < 0 || ri >= a.nx)) {
       ri = mirror_index(ri, a.nx);
       m |= 1;
     }
-    if (a.mir[1] && (rj < 0 || rj >= a.ny)) {
+    if (MIR && a.mir[1] && (rj < 0 || rj >= a.ny)) {
       rj = mirror_index(rj, a.ny);
       m |= 2;
     }
     hbase[s] = wrapi(rj, a.ny) * a.nx + wrapi(ri, a.nx);
-    hmir[s] = m;
+    if constexpr (MIR) hmir[s] = m;
   }
   __syncthreads();   // hbase ready
 
@@ -111,12 +113,12 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   // source line with the sign flipped
   int si = ui, sj = uj, slp = lp;
   T sgn = T(1);
-  if (a.mir[0] && ui >= a.nx) {
+  if (MIR && a.mir[0] && ui >= a.nx) {
     si = mirror_index(ui, a.nx);
     slp = (slp / n) * n + (n - 1 - slp % n);
     sgn = -sgn;
   }
-  if (a.mir[1] && uj >= a.ny) {
+  if (MIR && a.mir[1] && uj >= a.ny) {
     sj = mirror_index(uj, a.ny);
     slp = (n - 1 - slp / n) * n + slp % n;
     sgn = -sgn;
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     }
     // the plane below a Dirichlet wall at z = 0: odd reflection of plane 0 (stores are valid
     // cells' own planes only, so valid stores are unaffected)
-    if (a.mir[2] && k0 == 0) {
+    if (MIR && a.mir[2] && k0 == 0) {
 #pragma unroll
       for (int l3 = 0; l3 < n; ++l3) zp[l3] = -zc[n - 1 - l3];
     }
@@ -201,8 +203,9 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   T hv[HR][LR], hp[HR][LR];
   // source element of halo element l of slot s (odd reflection across x / y walls)
   auto hsrc = [&](int s, int l, T& sg) -> int {
-    const int m = hmir[s];
     sg = T(1);
+    if constexpr (!MIR) return l;
+    const int m = hmir[s];
     if (m & 1) {
       l = l - l % n + (n - 1 - l % n);
       sg = -sg;
@@ -317,7 +320,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
       }
     }
     // the plane above a Dirichlet wall at z = L: odd reflection of the last plane
-    if (a.mir[2] && k + 1 == a.nz) {
+    if (MIR && a.mir[2] && k + 1 == a.nz) {
 #pragma unroll
       for (int l3 = 0; l3 < n; ++l3) zn[l3] = -zc[n - 1 - l3];
     }
@@ -380,48 +383,75 @@ static const void* kernel_2d(int v, int pf) {
                                : (const void*)k_apply2d<T, N, 0, F, 0>);
 }
 
+// The 2D kernel of fused form `fuse` for a grid with walls (tile variant 0, prefetch on).
+template <typename T, int N>
+static const void* kernel_2d_walls(int fuse) {
+  switch (fuse) {
+    case 3: return (const void*)k_apply2d<T, N, 0, 3, 1, true>;
+    case 2: return (const void*)k_apply2d<T, N, 0, 2, 1, true>;
+    case 1: return (const void*)k_apply2d<T, N, 0, 1, 1, true>;
+    default: return (const void*)k_apply2d<T, N, 0, 0, 0, true>;
+  }
+}
+
 // (fused forms 1, 2 use the form-2 kernel; form 3 its own)
 template <typename T, int N>
-static long long resident_2d(int fuse, int v, int pf) {
+static long long resident_2d(int fuse, int v, int pf, bool mir) {
   constexpr int kDev = 16;
-  static int cache[kDev][2][3][2];
-  static bool init[kDev][2][3][2];
+  static int cache[kDev][2][3][2][2];
+  static bool init[kDev][2][3][2][2];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) return 0;
   const int f3 = fuse == 3 ? 1 : 0;
-  if (!init[dev][f3][v][pf]) {
-    const void* f = f3 ? kernel_2d<T, N, 3>(v, pf) : kernel_2d<T, N, 2>(v, pf);
+  const int w = mir ? 1 : 0;
+  if (!init[dev][f3][v][pf][w]) {
+    const void* f = mir ? kernel_2d_walls<T, N>(fuse)
+                  : f3 ? kernel_2d<T, N, 3>(v, pf) : kernel_2d<T, N, 2>(v, pf);
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 256, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
-    cache[dev][f3][v][pf] = per_cu * cus;
-    init[dev][f3][v][pf] = true;
+    cache[dev][f3][v][pf][w] = per_cu * cus;
+    init[dev][f3][v][pf][w] = true;
   }
-  return cache[dev][f3][v][pf];
+  return cache[dev][f3][v][pf][w];
 }
 
-// Workgroups of the 3D kernel (fused form 0, 1 or 2; prefetch pf) the device holds at once.
+// The 3D kernel of fused form 0, 1 or 2 and prefetch flag pf; a grid with walls (mir) runs the
+// halo-prefetch form.
 template <typename T, int N>
-static long long resident_3d(int fuse, int pf) {
+static const void* kernel_3d(int fuse, int pf, bool mir) {
+  if (mir) {
+    return fuse == 2 ? (const void*)k_apply3d<T, N, 2, 1, true>
+         : fuse == 1 ? (const void*)k_apply3d<T, N, 1, 1, true>
+                     : (const void*)k_apply3d<T, N, 0, 0, true>;
+  }
+  return fuse == 2 ? (pf ? (const void*)k_apply3d<T, N, 2, 1, false> : (const void*)k_apply3d<T, N, 2, 0, false>)
+       : fuse == 1 ? (pf ? (const void*)k_apply3d<T, N, 1, 1, false> : (const void*)k_apply3d<T, N, 1, 0, false>)
+                   : (const void*)k_apply3d<T, N, 0, 0, false>;
+}
+
+// Workgroups of the 3D kernel (fused form 0, 1 or 2; prefetch pf; walls mir) the device holds at
+// once.
+template <typename T, int N>
+static long long resident_3d(int fuse, int pf, bool mir) {
   constexpr int kDev = 16;
-  static int cache[kDev][3][2];
-  static bool init[kDev][3][2];
+  static int cache[kDev][3][2][2];
+  static bool init[kDev][3][2][2];
   int dev = 0;
   if (fuse < 0 || fuse > 2 || hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDev) return 0;
   if (fuse == 0) pf = 0;
-  if (!init[dev][fuse][pf]) {
-    const void* f = fuse == 2 ? (pf ? (const void*)k_apply3d<T, N, 2, 1> : (const void*)k_apply3d<T, N, 2, 0>)
-                  : fuse == 1 ? (pf ? (const void*)k_apply3d<T, N, 1, 1> : (const void*)k_apply3d<T, N, 1, 0>)
-                              : (const void*)k_apply3d<T, N, 0, 0>;
+  const int w = mir ? 1 : 0;
+  if (!init[dev][fuse][pf][w]) {
+    const void* f = kernel_3d<T, N>(fuse, pf, mir);
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, Tile3D<N>::NTH, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return 0;
-    cache[dev][fuse][pf] = per_cu * cus;
-    init[dev][fuse][pf] = true;
+    cache[dev][fuse][pf][w] = per_cu * cus;
+    init[dev][fuse][pf][w] = true;
   }
-  return cache[dev][fuse][pf];
+  return cache[dev][fuse][pf][w];
 }
 
 template <typename T, int N>
@@ -444,7 +474,8 @@ static Geom geometry(const ApplyLaunch& L) {
     if (L.tiles_per_wg > 0) {
       per = L.tiles_per_wg;
     } else if (L.fuse) {
-      res = resident_2d<T, N>(L.fuse, L.tile_variant, L.prefetch != 0);
+      res = resident_2d<T, N>(L.fuse, L.tile_variant, L.prefetch != 0,
+                              L.mir[0] || L.mir[1] || L.mir[2]);
       // (the one-kernel form holds fewer workgroups: 4 tiles each at 256^2 N = 6 FP64)
       const long long cap = L.fuse == 3 ? 4 : 3;
       if (res > 0) per = std::min<long long>(cap, std::max<long long>(1, (ntiles + res - 1) / res));
@@ -470,7 +501,7 @@ static Geom geometry(const ApplyLaunch& L) {
     // 64^3 N = 4: FP64 (one workgroup per CU) 64 planes, FP32 32 (6 % faster than 16 in FP64);
     // 48^3 N = 3 FP64 (144 columns): 85 us per apply against 101 us with one wave of 27-plane
     // segments (the second wave held 32 workgroups).
-    const long long res = resident_3d<T, N>(L.fuse, L.prefetch != 0);
+    const long long res = resident_3d<T, N>(L.fuse, L.prefetch != 0, L.mir[0] || L.mir[1] || L.mir[2]);
     int kz = (int)((cols * nz) / 1024);
     if (res > 0) {
       long long best = -1;
@@ -543,7 +574,14 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   // extended launch: the optional start/stop events are taken from the dispatch itself (no
   // separate marker packets around the kernel)
   hipEvent_t e0 = L.ev_start, e1 = L.ev_stop;
-  if (L.dim == 2) {
+  const bool walls = L.mir[0] || L.mir[1] || L.mir[2];
+  if (L.dim == 2 && walls) {
+    // walls: tile variant 0 with prefetch (pd_api sets both for such grids)
+    if (L.tile_variant != 0 || (L.fuse && !pf)) return hipErrorInvalidValue;
+    const void* f = kernel_2d_walls<T, N>(L.fuse);
+    void* args[] = {&a, (void*)&B};
+    hipExtLaunchKernel(f, dim3(G), dim3(256), args, 0, s, e0, e1, 0);
+  } else if (L.dim == 2) {
 #define PD_A2D(VV)                                                                              \
   if (L.fuse == 3) {                                                                            \
     if (pf) hipExtLaunchKernelGGL((k_apply2d<T, N, VV, 3, 1>), dim3(G), dim3(256), 0, s, e0, e1, 0, a, B); \
@@ -563,14 +601,18 @@ static hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
 #undef PD_A2D
   } else {
     constexpr int NTH = Tile3D<N>::NTH;
-    if (L.fuse == 2) {
-      if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 2, 1>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
-      else hipExtLaunchKernelGGL((k_apply3d<T, N, 2, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+    if (walls) {
+      const void* f = kernel_3d<T, N>(L.fuse, 1, true);
+      void* args[] = {&a, (void*)&B};
+      hipExtLaunchKernel(f, dim3(G), dim3(NTH), args, 0, s, e0, e1, 0);
+    } else if (L.fuse == 2) {
+      if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 2, 1, false>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+      else hipExtLaunchKernelGGL((k_apply3d<T, N, 2, 0, false>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     } else if (L.fuse) {
-      if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 1>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
-      else hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+      if (pf) hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 1, false>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+      else hipExtLaunchKernelGGL((k_apply3d<T, N, 1, 0, false>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     } else {
-      hipExtLaunchKernelGGL((k_apply3d<T, N, 0, 0>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
+      hipExtLaunchKernelGGL((k_apply3d<T, N, 0, 0, false>), dim3(G), dim3(NTH), 0, s, e0, e1, 0, a, B);
     }
   }
   return hipGetLastError();

@@ -125,7 +125,8 @@ struct Tile2D {
 // box cell (bi, bj) = tile cell (bi-1, bj-1). Box row bj is one contiguous run of cells in global
 // memory unless it crosses the periodic seam, so staging is a flat copy per row. The workgroup
 // processes tiles t_begin, t_begin + t_stride, ... below t_end.
-template <typename T, int N, int V, int FUSE, int PF>
+// MIR: the grid has Dirichlet walls (a.mir); the periodic form carries none of their code.
+template <typename T, int N, int V, int FUSE, int PF, bool MIR = false>
 __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T, N>& B,
                                              int t_begin, int t_end, int t_stride, int slot) {
   constexpr bool RU = FUSE == 3;                // residual update folded in
@@ -161,12 +162,12 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
     int l = e - cr * NC;
     int ri = tx0 + first + cr, rj = ty0 + bj - 1;
     neg = false;
-    if (a.mir[0] && (ri < 0 || ri >= a.nx)) {
+    if (MIR && a.mir[0] && (ri < 0 || ri >= a.nx)) {
       ri = mirror_index(ri, a.nx);
       l = (l / n) * n + (n - 1 - l % n);
       neg = !neg;
     }
-    if (a.mir[1] && (rj < 0 || rj >= a.ny)) {
+    if (MIR && a.mir[1] && (rj < 0 || rj >= a.ny)) {
       rj = mirror_index(rj, a.ny);
       l = (n - 1 - l / n) * n + l % n;
       neg = !neg;
@@ -184,7 +185,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
       if (bj < bj_lo || bj >= bj_hi) continue;
       const bool halo = bj == 0 || bj == TY + 1;
       const int rj = ty0 + bj - 1;
-      const bool rowflat = flat && !(a.mir[1] && (rj < 0 || rj >= a.ny));
+      const bool rowflat = flat && !(MIR && a.mir[1] && (rj < 0 || rj >= a.ny));
       const int gj = wrap_small(rj, a.ny);
       const size_t row0 = ((size_t)gj * a.nx + (halo ? tx0 : tx0 - 1)) * NC;
       constexpr int J = JI > JH ? JI : JH;
@@ -197,7 +198,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
           T rv = xg[g], pv = T(0), qv = T(0);
           if (FUSE) pv = pg[g];
           if (rupd) qv = a.qprev[g];
-          if (neg) {
+          if (MIR && neg) {
             rv = -rv;
             pv = -pv;
             qv = -qv;

@@ -80,8 +80,8 @@ def test_apply_with_walls(pd, dim, cells, N, mask, op):
 @pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("cells,N", [((23, 19), 3), ((17, 30), 6)])
 def test_wall_apply_tile_shapes_agree(pd, cells, N, variant):
-    """The smaller 2D tile shapes (PD_CFG_TILE_VARIANT) and several tiles per workgroup give the
-    same wall apply bit for bit as the default shape."""
+    """Several tiles per workgroup give the same wall apply bit for bit as one; a grid with walls
+    runs the default tile shape, so a PD_CFG_TILE_VARIANT setting leaves the result unchanged."""
     import torch
     print(f"wall tile shapes cells={cells} N={N} variant={variant}", flush=True)
     g = Grid(cells, (1.0, 1.0), N, periodic=(False, False))
