@@ -344,10 +344,21 @@ struct PrecArgs {
   double alpha, c0, c1, c2;
 };
 
+// Cells per group of the preconditioner kernel: as many as keep one line of N+1 nodes per
+// direction per thread (n^(d-1) lines per cell and direction, at most kBlock lines).
+__host__ __device__ constexpr int pcg_cells_per_group(int N, int dim) {
+  return (dim == 3 ? kBlock / ((N + 1) * (N + 1)) : kBlock / (N + 1)) < 1
+             ? 1
+             : (dim == 3 ? kBlock / ((N + 1) * (N + 1)) : kBlock / (N + 1));
+}
+
 // UPD = 1: second half of a preconditioned CG iteration k (r -= alpha_k q first, alpha_k from
 // the sigma partials); UPD = 0: z = P r only. Partials of <r, z> and <r, r> per block. Each
-// block takes groups of CPB whole cells (grid-stride over the groups); the 1D transforms run
-// through LDS, one direction at a time, in FP64.
+// block takes groups of CPB whole cells (grid-stride over the groups, the next group's r and q
+// loaded while the current one is transformed). A group is staged in LDS in FP64; each thread
+// takes one line of nodes per direction and applies the 1D transform in registers: forward
+// along x and y (and z), the diagonal scaling and the backward transform along the last
+// direction in one pass, then backward along y (and x). 2d + 2 LDS passes per group, all in FP64.
 template <typename T, int N, int DIM, int UPD>
 __global__ __launch_bounds__(kBlock) void k_pcg_update(PrecArgs<N> P, const T* __restrict__ q,
                                                        T* __restrict__ r, T* __restrict__ z,
@@ -356,9 +367,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(PrecArgs<N> P, const T* _
                                                        int nsig, double* __restrict__ rz_next,
                                                        double* __restrict__ rr_next) {
   constexpr int n = N + 1, NC = DIM == 3 ? n * n * n : n * n;
-  constexpr int CPB = NC >= kBlock ? 1 : kBlock / NC;
+  constexpr int LPC = NC / n;                          // lines per cell and direction
+  constexpr int CPB = pcg_cells_per_group(N, DIM);
   constexpr int E = CPB * NC;
-  __shared__ double br[E], b0[E], b1[E];
+  constexpr int J = (E + kBlock - 1) / kBlock;         // elements per thread in the streaming phases
+  __shared__ double sa[E], sb[E], sinv[NC];
   T a = T(0);
   if (UPD) {
     if (st->run_u != k) return;        // the apply kernel of iteration k stopped the run
@@ -381,64 +394,121 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(PrecArgs<N> P, const T* _
     }
     a = (T)alpha;
   }
-  auto transform = [&](const double* in, double* out, int ecount, int sd, bool fwd) {
-    for (int e = threadIdx.x; e < ecount; e += kBlock) {
-      const int l = e % NC;
-      const int ld = (l / sd) % n;
-      const int b = e - ld * sd;
+  // reciprocals of the diagonal of the transformed cell block
+  for (int l = threadIdx.x; l < NC; l += kBlock) {
+    double d = P.alpha + P.c0 * P.lam[l % n] + P.c1 * P.lam[(l / n) % n];
+    if (DIM == 3) d += P.c2 * P.lam[l / (n * n)];
+    sinv[l] = 1.0 / d;
+  }
+  // 1D transform of the line of `cnt` lines starting at element `b` with stride `sd`
+  auto line = [&](const double* in, double* out, int b, int sd, bool fwd, bool scale) {
+    double v[n], w[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = in[b + m * sd];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
       double acc = 0.0;
 #pragma unroll
-      for (int m = 0; m < n; ++m) acc += (fwd ? P.V[m * n + ld] : P.V[ld * n + m]) * in[b + m * sd];
-      out[e] = acc;
+      for (int m = 0; m < n; ++m) acc += (fwd ? P.V[m * n + i] : P.V[i * n + m]) * v[m];
+      w[i] = acc;
     }
-    __syncthreads();
+    if (scale) {   // the last direction: diagonal scaling, then its backward transform
+      const int l0 = b % NC;
+#pragma unroll
+      for (int i = 0; i < n; ++i) w[i] *= sinv[l0 + i * sd];
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += P.V[i * n + m] * w[m];
+        v[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < n; ++i) out[b + i * sd] = v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < n; ++i) out[b + i * sd] = w[i];
+    }
+  };
+  // first element of line t (t < lines of the group) along direction d
+  auto line_base = [&](int t, int d) -> int {
+    const int c = t / LPC, li = t - c * LPC;
+    int b;
+    if (d == 0) b = li * n;                                          // x-line (l2, l3)
+    else if (d == 1) b = (li / n) * n * n + (li % n);                // y-line (l1, l3)
+    else b = li;                                                     // z-line (l1, l2)
+    return c * NC + b;
   };
   double rr = 0.0, rz = 0.0;
   const long long ngroups = (ncells + CPB - 1) / CPB;
-  for (long long grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+  T rn[J], qn[J];
+  auto load = [&](long long grp) {
     const long long c0 = grp * CPB;
     const long long base = c0 * NC;
     const int ecount = (int)((ncells - c0 < CPB ? ncells - c0 : CPB) * NC);
-    for (int e = threadIdx.x; e < ecount; e += kBlock) {
-      T rv = r[base + e];
-      if (UPD) {
-        rv = rv - a * q[base + e];
-        r[base + e] = rv;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int e = threadIdx.x + kBlock * j;
+      if (e < ecount) {
+        rn[j] = r[base + e];
+        if (UPD) qn[j] = q[base + e];
       }
-      rr += (double)rv * (double)rv;
-      br[e] = (double)rv;
     }
+  };
+  long long grp = blockIdx.x;
+  if (grp < ngroups) load(grp);
+  for (; grp < ngroups; grp += gridDim.x) {
+    const long long c0 = grp * CPB;
+    const long long base = c0 * NC;
+    const int cells = (int)(ncells - c0 < CPB ? ncells - c0 : CPB);
+    const int ecount = cells * NC;
+    const int lines = cells * LPC;
+    double rv[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int e = threadIdx.x + kBlock * j;
+      if (e < ecount) {
+        T x = rn[j];
+        if (UPD) {
+          x = x - a * qn[j];
+          r[base + e] = x;
+        }
+        rv[j] = (double)x;
+        rr += rv[j] * rv[j];
+        sa[e] = rv[j];
+      }
+    }
+    if (grp + gridDim.x < ngroups) load(grp + gridDim.x);   // in flight during the transforms
     __syncthreads();
-    transform(br, b0, ecount, 1, true);
-    transform(b0, b1, ecount, n, true);
-    double* cur = b1;
-    double* oth = b0;
+    const int t = threadIdx.x;
     if (DIM == 3) {
-      transform(b1, b0, ecount, n * n, true);
-      cur = b0;
-      oth = b1;
-    }
-    for (int e = threadIdx.x; e < ecount; e += kBlock) {
-      const int l = e % NC;
-      double d = P.alpha + P.c0 * P.lam[l % n] + P.c1 * P.lam[(l / n) % n];
-      if (DIM == 3) d += P.c2 * P.lam[l / (n * n)];
-      cur[e] = cur[e] / d;
-    }
-    __syncthreads();
-    transform(cur, oth, ecount, 1, false);
-    transform(oth, cur, ecount, n, false);
-    if (DIM == 3) {
-      transform(cur, oth, ecount, n * n, false);
-      double* t = cur;
-      cur = oth;
-      oth = t;
-    }
-    for (int e = threadIdx.x; e < ecount; e += kBlock) {
-      const T zv = (T)cur[e];
-      z[base + e] = zv;
-      rz += br[e] * (double)zv;
+      if (t < lines) line(sa, sb, line_base(t, 0), 1, true, false);
+      __syncthreads();
+      if (t < lines) line(sb, sa, line_base(t, 1), n, true, false);
+      __syncthreads();
+      if (t < lines) line(sa, sa, line_base(t, 2), n * n, true, true);
+      __syncthreads();
+      if (t < lines) line(sa, sb, line_base(t, 1), n, false, false);
+      __syncthreads();
+      if (t < lines) line(sb, sa, line_base(t, 0), 1, false, false);
+    } else {
+      if (t < lines) line(sa, sb, line_base(t, 0), 1, true, false);
+      __syncthreads();
+      if (t < lines) line(sb, sb, line_base(t, 1), n, true, true);
+      __syncthreads();
+      if (t < lines) line(sb, sa, line_base(t, 0), 1, false, false);
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int e = threadIdx.x + kBlock * j;
+      if (e < ecount) {
+        const T zv = (T)sa[e];
+        z[base + e] = zv;
+        rz += rv[j] * (double)zv;
+      }
+    }
+    __syncthreads();   // sa is rewritten by the next group
   }
   rr = block_sum_all<kBlock>(rr);
   rz = block_sum_all<kBlock>(rz);
@@ -735,8 +805,7 @@ hipError_t launch_energy(int dim, int N, const double* w, const double* const u[
 }
 
 unsigned pcg_grid(long long ncells, int dim, int N) {
-  const int n = N + 1, NC = dim == 3 ? n * n * n : n * n;
-  const int CPB = NC >= kBlock ? 1 : kBlock / NC;
+  const int CPB = pcg_cells_per_group(N, dim);
   long long g = (ncells + CPB - 1) / CPB;
   if (g < 1) g = 1;
   if (g > kMaxStreamPartials) g = kMaxStreamPartials;
