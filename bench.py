@@ -40,8 +40,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # the sources of the fused operator-apply kernels (the kernel itself and the device helpers it
 # inlines); a counter summary is used only while they hash to the value recorded in it
-KERNEL_SOURCES = ["paper_1602_05806_amd/csrc/pd_apply.hip", "paper_1602_05806_amd/csrc/pd_apply2d.h",
-                  "paper_1602_05806_amd/csrc/pd_device.h"]
+KERNEL_SOURCES = ["paper_1602_05806_amd/csrc/pd_apply_kernels.h",
+                  "paper_1602_05806_amd/csrc/pd_apply2d.h", "paper_1602_05806_amd/csrc/pd_device.h"]
 # every TIMING_STRIDE-th operator launch of the timed solves carries dispatch events (events on
 # every launch would add a few microseconds to each iteration of the measured solve)
 TIMING_STRIDE = 16
