@@ -173,7 +173,10 @@ def bench_batch(args, pd, torch):
     del parts
     ndofs = [B.offsets[j + 1] - B.offsets[j] for j in range(B.count)]
     res = {}
-    for name, prec in (("fp32_refine64", pd.PD_FP32_REFINE64), ("fp64", pd.PD_FP64)):
+    runs = (("fp32_refine64", pd.PD_FP32_REFINE64, 0), ("fp64", pd.PD_FP64, 0),
+            ("pcg_fp32_refine64", pd.PD_FP32_REFINE64, 1), ("pcg_fp64", pd.PD_FP64, 1))
+    for name, prec, pc in runs:
+        pd.pd_batch_configure(B, pd.PD_BCFG_PRECOND, pc)
         x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
         for _ in range(args.warmup):
             pd.pd_batch_cg_solve(B, prec, b, x, cfg["rtol"], cfg["maxit"])
@@ -191,6 +194,7 @@ def bench_batch(args, pd, torch):
         res[name] = dict(seconds=secs, work=work, infos=infos, bytes_it=bytes_it)
         del x
     r32, r64 = res["fp32_refine64"], res["fp64"]
+    p32, p64 = res["pcg_fp32_refine64"], res["pcg_fp64"]
     value = r32["work"] / r32["seconds"]
     falls = [j for j, i in enumerate(r32["infos"]) if i["fallback_iter"] >= 0]
     line = {
@@ -220,6 +224,18 @@ def bench_batch(args, pd, torch):
                  "algorithmic_gbs_cg": r64["work"] * r64["bytes_it"] / r64["seconds"] / 1e9,
                  "rel_res_true_max": max(i["rel_res_true"] for i in r64["infos"])},
         "speedup_solve_vs_fp64": r64["seconds"] / r32["seconds"],
+        # the same solves with the cell-block Jacobi preconditioner (PD_BCFG_PRECOND)
+        "preconditioned": {
+            "fp64": {"solve_ms": 1e3 * p64["seconds"] / args.steps,
+                     "max_iters": max(i["iters"] for i in p64["infos"]),
+                     "rel_res_true_max": max(i["rel_res_true"] for i in p64["infos"])},
+            "fp32_refine64": {"solve_ms": 1e3 * p32["seconds"] / args.steps,
+                              "max_iters": max(i["iters"] for i in p32["infos"]),
+                              "rel_res_true_max": max(i["rel_res_true"] for i in p32["infos"])},
+            "speedup_fp64_vs_plain_fp64": r64["seconds"] / p64["seconds"],
+            "speedup_fp32_refine64_vs_plain_fp64": r64["seconds"] / p32["seconds"],
+            "speedup_fp32_refine64_vs_fp64": p64["seconds"] / p32["seconds"],
+            "iters_per_problem_fp64": [i["iters"] for i in p64["infos"]]},
         "per_problem": [{"side": p["side"], "N": p["N"], "iters_refine": i["iters"],
                          "fp64_from": i["fallback_iter"], "iters_fp64": k["iters"]}
                         for p, i, k in zip(specs, r32["infos"], r64["infos"])],

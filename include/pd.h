@@ -113,10 +113,12 @@ int pd_nodes(const pd_ctx* ctx, double* xi, double* w);
  * pressure operator of eq. (pSyst) / (PerPrSyst)), PD_TAB_PNULL ((N+1)^2: orthogonal projector
  * onto the cell-periodic kernel of the weak gradient, null(R~ - L~)), PD_TAB_PNULL_ODD
  * ((N+1)^2: orthogonal projector onto the part of that kernel odd about the cell centre, the
- * 1D null space along a Dirichlet direction; all zeros for even N). out must hold that many
- * doubles. Returns the number of values written, or PD_EINVAL. */
+ * 1D null space along a Dirichlet direction; all zeros for even N), PD_TAB_PV ((N+1)^2,
+ * row-major V[m][l]: the generalised eigenvectors of the diagonal block, C V = M V diag(lambda),
+ * V^T M V = I, which the cell-block Jacobi preconditioner uses), PD_TAB_PLAM (N+1: lambda).
+ * out must hold that many doubles. Returns the number of values written, or PD_EINVAL. */
 enum { PD_TAB_NODES = 0, PD_TAB_WEIGHTS = 1, PD_TAB_L = 2, PD_TAB_C = 3, PD_TAB_R = 4,
-       PD_TAB_PNULL = 5, PD_TAB_PNULL_ODD = 6 };
+       PD_TAB_PNULL = 5, PD_TAB_PNULL_ODD = 6, PD_TAB_PV = 7, PD_TAB_PLAM = 8 };
 int pd_table_1d(int N, int which, double* out);
 
 /* y = A x for op PD_OP_PRESSURE or PD_OP_VISCOUS; x, y: ndof elements of precision prec
@@ -390,8 +392,11 @@ int pd_batch_variants(const pd_batch* batch, int prec, int* variants);
  *   PD_BCFG_RU_FACTOR  PD_FP32_REFINE64: a problem's FP32 iterations pause (until the chunk's
  *                  residual replacement) once their residual has dropped by this factor below the
  *                  last replaced one, in (0, 1) (default 1e-2). This keeps fast-converging
- *                  problems from iterating on FP32 rounding noise. */
-enum { PD_BCFG_CHUNK = 0, PD_BCFG_GRAPH = 1, PD_BCFG_RU_FACTOR = 2 };
+ *                  problems from iterating on FP32 rounding noise.
+ *   PD_BCFG_PRECOND  1 = preconditioned CG with the cell-block Jacobi preconditioner of
+ *                  PD_CFG_PRECOND (each problem's own degree and cell sizes), in both precisions;
+ *                  the stopping tests stay on ||r||_2; 0 (default) = plain CG. */
+enum { PD_BCFG_CHUNK = 0, PD_BCFG_GRAPH = 1, PD_BCFG_RU_FACTOR = 2, PD_BCFG_PRECOND = 3 };
 int pd_batch_configure(pd_batch* batch, int key, double value);
 
 /* Solve every problem of the batch: b = packed FP64 right-hand sides (read only; each problem's

@@ -32,8 +32,9 @@ PD_OP_PRESSURE, PD_OP_VISCOUS = 0, 1
  PD_CFG_PREFETCH, PD_CFG_TILE_VARIANT, PD_CFG_DEFER_X, PD_CFG_ONE_KERNEL,
  PD_CFG_EXPLICIT_VISC, PD_CFG_PRECOND) = range(16)
 PD_BATCH_AUTOTUNE, PD_BATCH_RETUNE = 1, 2
-PD_BCFG_CHUNK, PD_BCFG_GRAPH, PD_BCFG_RU_FACTOR = 0, 1, 2
-PD_TAB_NODES, PD_TAB_WEIGHTS, PD_TAB_L, PD_TAB_C, PD_TAB_R, PD_TAB_PNULL, PD_TAB_PNULL_ODD = range(7)
+PD_BCFG_CHUNK, PD_BCFG_GRAPH, PD_BCFG_RU_FACTOR, PD_BCFG_PRECOND = 0, 1, 2, 3
+(PD_TAB_NODES, PD_TAB_WEIGHTS, PD_TAB_L, PD_TAB_C, PD_TAB_R, PD_TAB_PNULL, PD_TAB_PNULL_ODD,
+ PD_TAB_PV, PD_TAB_PLAM) = range(9)
 PD_TTAB_NODES, PD_TTAB_WEIGHTS, PD_TTAB_PSI0, PD_TTAB_PSI1, PD_TTAB_MV, PD_TTAB_AINV = range(6)
 
 EXPORTED = ["pd_setup", "pd_destroy", "pd_last_error", "pd_sizes", "pd_nodes", "pd_table_1d", "pd_apply",

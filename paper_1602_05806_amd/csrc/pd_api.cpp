@@ -454,7 +454,12 @@ int solve_fp64(pd_ctx* c, int op, const double* b, double* x, double rtol, doubl
     const double goal = rtol * bnorm;
     if (res <= goal || res > kTrueGap * goal || (prev_res > 0.0 && res > 0.5 * prev_res)) break;
     prev_res = res;
-    if (!(res <= 4.0 * std::sqrt(fin.res2))) {
+    // preconditioned runs always restart the direction: beta would combine <r, P r> of the
+    // replaced residual with that of the recurrence, and on the ill-conditioned odd-degree
+    // systems (where a replacement happens at all) the kept direction loses conjugacy
+    // (10 x 12 cells of 0.2 x 0.083, N = 7, rtol 1e-12: 48k iterations ending at a true
+    // residual of 0.24 with the direction kept)
+    if (R.pc || !(res <= 4.0 * std::sqrt(fin.res2))) {
       void* buf[2] = {R.B.pa, R.B.pb};
       PD_HIP(c, pdk::launch_zero(false, buf[R.k & 1], c->ndof, s));
       ++inf->restarts;
@@ -1166,7 +1171,7 @@ int pd_nodes(const pd_ctx* c, double* xi, double* w) {
 }
 
 int pd_table_1d(int N, int which, double* out) {
-  if (!out || which < PD_TAB_NODES || which > PD_TAB_PNULL_ODD) return PD_EINVAL;
+  if (!out || which < PD_TAB_NODES || which > PD_TAB_PLAM) return PD_EINVAL;
   pdh::Table1D t;
   std::string e;
   if (!pdh::build_table(N, &t, &e)) return PD_EINVAL;
@@ -1180,6 +1185,8 @@ int pd_table_1d(int N, int which, double* out) {
     case PD_TAB_C: src = t.Cb; break;
     case PD_TAB_R: src = t.Rb; break;
     case PD_TAB_PNULL_ODD: src = t.PnullOdd; break;
+    case PD_TAB_PV: src = t.PV; break;
+    case PD_TAB_PLAM: src = t.Plam; cnt = n; break;
     default: src = t.Pnull; break;
   }
   for (int i = 0; i < cnt; ++i) out[i] = src[i];

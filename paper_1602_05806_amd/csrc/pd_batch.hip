@@ -60,6 +60,11 @@ __device__ __forceinline__ double* rho_slot(const BatchIter& it, int j, int pari
   return it.rho + (size_t)j * 2 * kMaxStreamPartials + (size_t)(parity & 1) * kMaxStreamPartials;
 }
 
+// preconditioned solves: partials of <r, r> (the stopping test), beside those of <r, z> in rho
+__device__ __forceinline__ double* res_slot(const BatchIter& it, int j, int parity) {
+  return it.res + (size_t)j * 2 * kMaxStreamPartials + (size_t)(parity & 1) * kMaxStreamPartials;
+}
+
 // ---- CG update: r -= alpha_j q; partials of <r, r> (next iteration's slot). The matching
 // x += alpha_j p_k is deferred: the apply kernel of iteration k + 1 makes it, or k_xflush_batch at
 // the end of the chunk when the problem has stopped iterating; block 0 of the problem publishes
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(256) void k_apply2d_batch(BatchIter it, const int* 
   a.k = it.koff;
   a.kbase = it.kbase;
   a.rho_cur = rho_slot(it, j, it.koff);
-  a.res_cur = nullptr;
+  a.res_cur = it.res ? res_slot(it, j, it.koff) : nullptr;
   a.mir[0] = a.mir[1] = a.mir[2] = 0;
   a.nrho = P.nupd;
   a.sigpart = it.sig + P.sig_off;
@@ -298,7 +303,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
   if (WHAT == 3 && threadIdx.x == 0) st->xk = -1;   // the deferred x update was flushed before
   if (WHAT == 3 && st->fin) return;
   const double s = sum_partials<kBlock>(it.tmp + (size_t)j * kMaxStreamPartials, P.nupd);
-  const double rec = WHAT == 3 ? sum_partials<kBlock>(rho_slot(it, j, it.koff), P.nupd) : 0.0;
+  // recurrence residual of the chunk's last iteration (preconditioned solves: <r, r>, kept apart
+  // from the <r, z> of the rho slots)
+  const double rec =
+      WHAT == 3 ? sum_partials<kBlock>(it.res ? res_slot(it, j, it.koff) : rho_slot(it, j, it.koff),
+                                       P.nupd)
+                : 0.0;
   if (threadIdx.x != 0) return;
   if (WHAT == 0) {
     st->aux = s;
@@ -365,8 +375,9 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
         }
         st->ref = res;
         // a recurrence that drifted more than 4x below the true residual would make beta huge
-        // and the old direction swamp the new residual: restart the direction then
-        if (!(res <= 4.0 * sqrt(st->rho))) {
+        // and the old direction swamp the new residual: restart the direction then (always in
+        // preconditioned solves, as in the single-problem solve)
+        if (it.res || !(res <= 4.0 * sqrt(st->rho))) {
           st->fresh = 1;
           st->restarts += 1;
         }
@@ -431,6 +442,199 @@ __global__ __launch_bounds__(kBlock) void k_finalize_batch(BatchIter it) {
       st->run_a[k & 1] = k;
       st->status = 0;
     }
+  }
+}
+
+// ---- cell-block Jacobi preconditioner of the listed problems (preconditioned solves)
+// z = P r problem by problem, with P the inverse of each cell's diagonal block in its generalised
+// eigenbasis (the single-problem k_pcg_update, whose notes apply): each block takes groups of
+// cells of its problem (grid-stride over the problem's nupd blocks), one line of nodes per
+// direction and thread, the next group's r and q loaded while the current one is transformed.
+// One launch per degree over the listed problems of that degree (the eigenbasis is the degree's;
+// the diagonal scaling uses each problem's own cell sizes).
+template <int N>
+struct PcgTab {
+  double V[(N + 1) * (N + 1)];   // V[m][l]: component m of eigenvector l
+  double lam[N + 1];
+};
+
+template <typename T, int N, int SEL>
+__global__ __launch_bounds__(kBlock) void k_pcg_update_batch(BatchIter it, PcgTab<N> tab,
+                                                             const T* __restrict__ q,
+                                                             T* __restrict__ r,
+                                                             T* __restrict__ z) {
+  constexpr int n = N + 1, NC = n * n;
+  constexpr int CPB = pcg_cells_per_group(N, 2);
+  constexpr int E = CPB * NC;
+  constexpr int J = (E + kBlock - 1) / kBlock;
+  constexpr bool UPD = SEL == 0;
+  __shared__ double sa[E], sb[E], sinv[NC];
+  const Slot sl = slot_of(it, it.upd_off, blockIdx.x);
+  const BProb& P = it.probs[sl.j];
+  CgState* st = it.st + sl.j;
+  T a = T(0);
+  double alpha = 0.0;
+  int k = 0, parity = it.koff;
+  if (UPD) {
+    k = *it.kbase + it.koff;
+    if (!iterates(it, st, k, false)) return;
+    const double sigma = sum_partials<kBlock>(it.sig + P.sig_off, P.nsig);
+    alpha = st->rho / sigma;
+    if (!(sigma > 0.0) || !isfinite(alpha)) {
+      if (threadIdx.x == 0 && sl.lb == 0) {
+        st->sigma = sigma;
+        st->status = -5;
+        st->iter = k;
+        st->done = 1;
+      }
+      return;
+    }
+    a = (T)alpha;
+    parity = it.koff + 1;
+  } else if (SEL == 2 ? !st->switched : !serves(it, st)) {
+    return;
+  }
+  for (int l = threadIdx.x; l < NC; l += kBlock)
+    sinv[l] = 1.0 / (P.alpha + P.c0 * tab.lam[l % n] + P.c1 * tab.lam[l / n]);
+  // 1D transform of one line (first element b, stride sd); scale: the diagonal scaling and the
+  // backward transform of the last direction in the same pass
+  auto line = [&](const double* in, double* out, int b, int sd, bool fwd, bool scale) {
+    double v[n], w[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) v[m] = in[b + m * sd];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < n; ++m) acc += (fwd ? tab.V[m * n + i] : tab.V[i * n + m]) * v[m];
+      w[i] = acc;
+    }
+    if (scale) {
+      const int l0 = b % NC;
+#pragma unroll
+      for (int i = 0; i < n; ++i) w[i] *= sinv[l0 + i * sd];
+#pragma unroll
+      for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < n; ++m) acc += tab.V[i * n + m] * w[m];
+        v[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < n; ++i) out[b + i * sd] = v[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < n; ++i) out[b + i * sd] = w[i];
+    }
+  };
+  const long long ncells = P.ncells;
+  const long long ngroups = (ncells + CPB - 1) / CPB;
+  T* __restrict__ rj = r + P.dof_off;
+  const T* __restrict__ qj = UPD ? q + P.dof_off : nullptr;
+  T* __restrict__ zj = z + P.dof_off;
+  double rr = 0.0, rz = 0.0;
+  T rn[J], qn[J];
+  auto load = [&](long long grp) {
+    const long long c0 = grp * CPB;
+    const long long base = c0 * NC;
+    const int ecount = (int)((ncells - c0 < CPB ? ncells - c0 : CPB) * NC);
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) {
+      const int e = threadIdx.x + kBlock * jj;
+      if (e < ecount) {
+        rn[jj] = rj[base + e];
+        if (UPD) qn[jj] = qj[base + e];
+      }
+    }
+  };
+  long long grp = sl.lb;
+  if (grp < ngroups) load(grp);
+  for (; grp < ngroups; grp += P.nupd) {
+    const long long c0 = grp * CPB;
+    const long long base = c0 * NC;
+    const int cells = (int)(ncells - c0 < CPB ? ncells - c0 : CPB);
+    const int ecount = cells * NC;
+    const int lines = cells * n;
+    double rv[J];
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) {
+      const int e = threadIdx.x + kBlock * jj;
+      if (e < ecount) {
+        T x = rn[jj];
+        if (UPD) {
+          x = x - a * qn[jj];
+          rj[base + e] = x;
+        }
+        rv[jj] = (double)x;
+        rr += rv[jj] * rv[jj];
+        sa[e] = rv[jj];
+      }
+    }
+    if (grp + P.nupd < ngroups) load(grp + P.nupd);
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < lines) line(sa, sb, (t / n) * NC + (t % n) * n, 1, true, false);   // x-lines
+    __syncthreads();
+    if (t < lines) line(sb, sb, (t / n) * NC + (t % n), n, true, true);         // y-lines
+    __syncthreads();
+    if (t < lines) line(sb, sa, (t / n) * NC + (t % n) * n, 1, false, false);  // x-lines
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj) {
+      const int e = threadIdx.x + kBlock * jj;
+      if (e < ecount) {
+        const T zv = (T)sa[e];
+        zj[base + e] = zv;
+        rz += rv[jj] * (double)zv;
+      }
+    }
+    __syncthreads();   // sa is rewritten by the next group
+  }
+  rr = block_sum_all<kBlock>(rr);
+  rz = block_sum_all<kBlock>(rz);
+  if (threadIdx.x == 0) {
+    rho_slot(it, sl.j, parity)[sl.lb] = rz;
+    res_slot(it, sl.j, parity)[sl.lb] = rr;
+    if (UPD && sl.lb == 0) {
+      st->alpha = alpha;
+      st->xk = k;
+      st->run_a[(k + 1) & 1] = k + 1;
+      st->fresh = 0;
+    }
+  }
+}
+
+template <typename T, int N>
+hipError_t pcg_batch_N(const BatchIter& it, int sel, const double* V, const double* lam,
+                       const void* q, void* r, void* z, hipStream_t s) {
+  PcgTab<N> tab;
+  constexpr int n = N + 1;
+  for (int i = 0; i < n * n; ++i) tab.V[i] = V[i];
+  for (int i = 0; i < n; ++i) tab.lam[i] = lam[i];
+  const dim3 G(it.upd_blocks), B(kBlock);
+  if (sel == 0)
+    hipLaunchKernelGGL((k_pcg_update_batch<T, N, 0>), G, B, 0, s, it, tab, (const T*)q, (T*)r, (T*)z);
+  else if (sel == 1)
+    hipLaunchKernelGGL((k_pcg_update_batch<T, N, 1>), G, B, 0, s, it, tab, (const T*)q, (T*)r, (T*)z);
+  else
+    hipLaunchKernelGGL((k_pcg_update_batch<T, N, 2>), G, B, 0, s, it, tab, (const T*)q, (T*)r, (T*)z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_batch_T(const BatchIter& it, int N, int sel, const double* V, const double* lam,
+                       const void* q, void* r, void* z, hipStream_t s) {
+  switch (N) {
+    case 0: return pcg_batch_N<T, 0>(it, sel, V, lam, q, r, z, s);
+    case 1: return pcg_batch_N<T, 1>(it, sel, V, lam, q, r, z, s);
+    case 2: return pcg_batch_N<T, 2>(it, sel, V, lam, q, r, z, s);
+    case 3: return pcg_batch_N<T, 3>(it, sel, V, lam, q, r, z, s);
+    case 4: return pcg_batch_N<T, 4>(it, sel, V, lam, q, r, z, s);
+    case 5: return pcg_batch_N<T, 5>(it, sel, V, lam, q, r, z, s);
+    case 6: return pcg_batch_N<T, 6>(it, sel, V, lam, q, r, z, s);
+    case 7: return pcg_batch_N<T, 7>(it, sel, V, lam, q, r, z, s);
+    case 8: return pcg_batch_N<T, 8>(it, sel, V, lam, q, r, z, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
@@ -641,6 +845,15 @@ hipError_t launch_finalize_batch(int what, const BatchIter& it, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_pcg_update_batch(const BatchIter& it, int N, bool fp32, int sel,
+                                   const double* V, const double* lam, const void* q, void* r,
+                                   void* z, hipStream_t s) {
+  if (it.count == 0) return hipSuccess;
+  if (!it.res || sel < 0 || sel > 2) return hipErrorInvalidValue;
+  return fp32 ? pcg_batch_T<float>(it, N, sel, V, lam, q, r, z, s)
+              : pcg_batch_T<double>(it, N, sel, V, lam, q, r, z, s);
 }
 
 hipError_t launch_project_null_batch(const BatchIter& it, double* v, hipStream_t s) {

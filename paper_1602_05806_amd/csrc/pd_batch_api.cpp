@@ -52,6 +52,8 @@ struct Plan {
   std::vector<BatchGroup> gallr;   // FP64 residual apply over act32 + act64 (FP64 tile shapes)
   std::vector<BatchGroup> g64;     // FP64 fused iterations over act64
   std::vector<char> in64;          // membership of act64, by problem
+  // the same lists split by degree (preconditioner launches, one per degree)
+  std::vector<std::pair<int, ListDev>> n32, n64, nall;
   long long dofs = 0;              // active DoFs when captured
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -80,6 +82,14 @@ struct pd_batch {
   double *b64 = nullptr, *x64 = nullptr, *r64 = nullptr, *q64 = nullptr, *pa64 = nullptr,
          *pb64 = nullptr;
   float *r32 = nullptr, *pa32 = nullptr, *pb32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+  // cell-block Jacobi preconditioned solves (PD_BCFG_PRECOND): z = P r per precision, partials
+  // of <r, r> beside those of <r, z>, eigenbasis tables by degree (9 x 90)
+  int precond = 0;
+  double *z64 = nullptr, *res = nullptr;
+  float* z32 = nullptr;
+  std::vector<double> pv;                   // eigenbasis tables by degree: V[81], lambda[9]
+  std::vector<std::pair<int, ListDev>> everyone_n;   // every problem, one list per degree
+  int* d_everyone_n = nullptr;
   ListDev everyone;                         // every problem, in order
   int* d_everyone = nullptr;
   std::vector<BatchGroup> g64_all;          // FP64 groups over every problem (final residual)
@@ -178,6 +188,7 @@ BatchIter make_iter(const pd_batch* b, int pi, const ListDev& L, int koff, int w
   it.nsp = b->nsp;
   it.corr = b->corr;
   it.pnull = b->pnull;
+  it.res = b->precond ? b->res : nullptr;
   it.kbase = b->d_kbase;
   it.koff = koff;
   return it;
@@ -276,6 +287,31 @@ void drop_plan(Plan* P) {
   *P = Plan();
 }
 
+// Lists of the problems js split by degree (ascending), table positions appended to h.
+std::vector<std::pair<int, ListHost>> add_lists_by_degree(const pd_batch* b,
+                                                         const std::vector<int>& js,
+                                                         std::vector<int>* h) {
+  std::map<int, std::vector<int>> by;
+  for (int j : js) by[b->N[j]].push_back(j);
+  std::vector<std::pair<int, ListHost>> out;
+  for (const auto& kv : by) out.push_back({kv.first, add_list(b->ps[0].probs, kv.second, h)});
+  return out;
+}
+
+// The preconditioner pass sel (see launch_pcg_update_batch) over per-degree lists, with the
+// descriptors of precision set pi (the sigma partials of that precision for sel 0).
+int pcg_pass(pd_batch* b, const std::vector<std::pair<int, ListDev>>& lists, int pi, int koff,
+             int want, int skip_fin, bool fp32, int sel, const void* q, void* r, void* z,
+             hipStream_t s) {
+  for (const auto& nl : lists) {
+    const int N = nl.first;
+    const BatchIter it = make_iter(b, pi, nl.second, koff, want, skip_fin);
+    BHIP(b, pdk::launch_pcg_update_batch(it, N, fp32, sel, &b->pv[(size_t)N * 90],
+                                         &b->pv[(size_t)N * 90 + 81], q, r, z, s));
+  }
+  return PD_OK;
+}
+
 // Build the device tables of a plan for the given active sets (no graph yet).
 int build_plan(pd_batch* b, const std::vector<int>& act32, const std::vector<int>& act64,
                bool refine, Plan* out) {
@@ -290,6 +326,9 @@ int build_plan(pd_batch* b, const std::vector<int>& act32, const std::vector<int
   const std::vector<GroupHost> g32 = add_groups(b->ps[1], act32, &h);
   const std::vector<GroupHost> gallr = add_groups(b->ps[0], un, &h);
   const std::vector<GroupHost> g64 = add_groups(b->ps[0], act64, &h);
+  const auto h32 = add_lists_by_degree(b, act32, &h);
+  const auto h64 = add_lists_by_degree(b, act64, &h);
+  const auto hall = add_lists_by_degree(b, un, &h);
   int rc = balloc(b, &out->dev, h.size());
   if (rc) return rc;
   BHIP(b, hipMemcpy(out->dev, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -299,6 +338,9 @@ int build_plan(pd_batch* b, const std::vector<int>& act32, const std::vector<int
   out->g32 = groups_dev(g32, out->dev);
   out->gallr = groups_dev(gallr, out->dev);
   out->g64 = groups_dev(g64, out->dev);
+  for (const auto& e : h32) out->n32.push_back({e.first, to_dev(e.second, out->dev)});
+  for (const auto& e : h64) out->n64.push_back({e.first, to_dev(e.second, out->dev)});
+  for (const auto& e : hall) out->nall.push_back({e.first, to_dev(e.second, out->dev)});
   out->in64.assign(b->count, 0);
   for (int j : act64) out->in64[j] = 1;
   out->dofs = 0;
@@ -428,14 +470,23 @@ int enqueue_chunk(pd_batch* b, const Plan& pl, hipStream_t s) {
   for (int i = 0; i < b->chunk; ++i) {
     const BatchIter i32 = make_iter(b, 1, pl.l32, i, 0, 0);
     const BatchIter i64 = make_iter(b, 0, pl.l64, i, 1, 0);
+    // the operand of the fused direction update: z = P r when preconditioned, else r
+    const void* o32 = b->precond ? (const void*)b->z32 : (const void*)b->r32;
+    const void* o64 = b->precond ? (const void*)b->z64 : (const void*)b->r64;
     for (const BatchGroup& g : pl.g32)
-      BHIP(b, pdk::launch_apply_batch(i32, g, true, true, b->r32, p32[i & 1], p32[(i + 1) & 1],
+      BHIP(b, pdk::launch_apply_batch(i32, g, true, true, o32, p32[i & 1], p32[(i + 1) & 1],
                                       b->q32, b->d32, b->tabs[g.N], s));
     for (const BatchGroup& g : pl.g64)
-      BHIP(b, pdk::launch_apply_batch(i64, g, false, true, b->r64, p64[i & 1], p64[(i + 1) & 1],
+      BHIP(b, pdk::launch_apply_batch(i64, g, false, true, o64, p64[i & 1], p64[(i + 1) & 1],
                                       b->q64, b->x64, b->tabs[g.N], s));
-    BHIP(b, pdk::launch_update_batch(i32, true, b->q32, b->r32, s));
-    BHIP(b, pdk::launch_update_batch(i64, false, b->q64, b->r64, s));
+    if (b->precond) {
+      int rc = pcg_pass(b, pl.n32, 1, i, 0, 0, true, 0, b->q32, b->r32, b->z32, s);
+      if (!rc) rc = pcg_pass(b, pl.n64, 0, i, 1, 0, false, 0, b->q64, b->r64, b->z64, s);
+      if (rc) return rc;
+    } else {
+      BHIP(b, pdk::launch_update_batch(i32, true, b->q32, b->r32, s));
+      BHIP(b, pdk::launch_update_batch(i64, false, b->q64, b->r64, s));
+    }
   }
   const int K = b->chunk;
   // the deferred x updates of the problems that stopped inside the chunk (and of those still
@@ -460,12 +511,22 @@ int enqueue_chunk(pd_batch* b, const Plan& pl, hipStream_t s) {
   BHIP(b, pdk::launch_stream_batch(3, chk, nullptr, nullptr, b->r64, nullptr, nullptr, s));
   BHIP(b, pdk::launch_finalize_batch(3, make_iter(b, 0, pl.lall, K, -1, 1), s));
   if (pl.refine) {
-    BHIP(b, pdk::launch_stream_batch(2, make_iter(b, 0, pl.l32, K, 0, 1), nullptr, nullptr,
-                                     b->r64, nullptr, b->r32, s));
+    const BatchIter i32 = make_iter(b, 0, pl.l32, K, 0, 1);
+    BHIP(b, pdk::launch_stream_batch(2, i32, nullptr, nullptr, b->r64, nullptr, b->r32, s));
+    // preconditioned: z32 = P r32, partials of <r, z> and <r, r>
+    if (b->precond) {
+      const int rc = pcg_pass(b, pl.n32, 0, K, 0, 1, true, 1, nullptr, b->r32, b->z32, s);
+      if (rc) return rc;
+    }
   }
-  // partials of <r, r> of the problems resuming from a recomputed residual
-  BHIP(b, pdk::launch_stream_batch(5, make_iter(b, 0, pl.lall, K, -1, 1), nullptr, nullptr,
-                                   b->r64, nullptr, nullptr, s));
+  // partials of <r, r> (preconditioned: z = P r, <r, z> and <r, r>) of the problems resuming
+  // from a recomputed residual
+  if (b->precond) {
+    const int rc = pcg_pass(b, pl.nall, 0, K, -1, 1, false, 2, nullptr, b->r64, b->z64, s);
+    if (rc) return rc;
+  } else
+    BHIP(b, pdk::launch_stream_batch(5, make_iter(b, 0, pl.lall, K, -1, 1), nullptr, nullptr,
+                                     b->r64, nullptr, nullptr, s));
   BHIP(b, pdk::launch_tick(b->d_kbase, b->chunk, s));
   return PD_OK;
 }
@@ -517,7 +578,8 @@ void pd_batch_destroy(pd_batch* b) {
   }
   void* bufs[] = {b->d_kbase, b->st, b->rho, b->tmp, b->nsp, b->corr, b->pnull, b->b64,
                   b->x64, b->r64, b->q64, b->pa64, b->pb64, b->r32, b->pa32, b->pb32,
-                  b->q32, b->d32, b->d_everyone, b->d_g64_all};
+                  b->q32, b->d32, b->d_everyone, b->d_g64_all, b->z64, b->z32, b->res,
+                  b->d_everyone_n};
   for (void* p : bufs) (void)hipFree(p);
   if (b->hst) (void)hipHostFree(b->hst);
   for (hipEvent_t e : {b->ev[0], b->ev[1], b->t0, b->t1})
@@ -546,6 +608,7 @@ int pd_batch_setup(pd_batch** out, int count, const int* ncell, const double* le
   b->dt = dt;
   b->tabs.resize(pdh::kMaxN + 1);
   std::vector<double> pn((pdh::kMaxN + 1) * 81, 0.0);
+  b->pv.assign((pdh::kMaxN + 1) * 90, 0.0);   // preconditioner V[81], lambda[9]
   for (int d = 0; d <= pdh::kMaxN; ++d) {
     pdh::Table1D t;
     std::string e;
@@ -558,7 +621,9 @@ int pd_batch_setup(pd_batch** out, int count, const int* ncell, const double* le
       b->tabs[d].C[i] = t.Cb[i];
       b->tabs[d].R[i] = t.Rb[i];
       pn[d * 81 + i] = t.Pnull[i];
+      b->pv[d * 90 + i] = t.PV[i];
     }
+    for (int i = 0; i < t.n; ++i) b->pv[d * 90 + 81 + i] = t.Plam[i];
     for (int i = 0; i < t.n; ++i) b->tabs[d].w[i] = t.w[i];
   }
   std::vector<BProb> probs(count);
@@ -631,7 +696,9 @@ int pd_batch_setup(pd_batch** out, int count, const int* ncell, const double* le
       (rc = balloc(b, &b->pa64, n)) || (rc = balloc(b, &b->pb64, n)) ||
       (rc = balloc(b, &b->r32, n)) || (rc = balloc(b, &b->pa32, n)) ||
       (rc = balloc(b, &b->pb32, n)) || (rc = balloc(b, &b->q32, n)) ||
-      (rc = balloc(b, &b->d32, n)))
+      (rc = balloc(b, &b->d32, n)) || (rc = balloc(b, &b->z64, n)) ||
+      (rc = balloc(b, &b->z32, n)) ||
+      (rc = balloc(b, &b->res, cnt * 2 * pdk::kMaxStreamPartials)))
     return fin(rc);
   {
     std::vector<int> all(count), h;
@@ -644,6 +711,15 @@ int pd_batch_setup(pd_batch** out, int count, const int* ncell, const double* le
       return fin(PD_EDEVICE);
     }
     b->everyone = to_dev(L, b->d_everyone);
+    std::vector<int> hn;
+    const auto ln = add_lists_by_degree(b, all, &hn);
+    if ((rc = balloc(b, &b->d_everyone_n, hn.size()))) return fin(rc);
+    if (hipMemcpy(b->d_everyone_n, hn.data(), hn.size() * sizeof(int), hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      b->err = "setup: list upload failed";
+      return fin(PD_EDEVICE);
+    }
+    for (const auto& e : ln) b->everyone_n.push_back({e.first, to_dev(e.second, b->d_everyone_n)});
   }
   hipError_t he = hipHostMalloc((void**)&b->hst, 2 * cnt * sizeof(CgState), hipHostMallocDefault);
   if (he == hipSuccess) he = hipEventCreate(&b->ev[0]);
@@ -653,6 +729,7 @@ int pd_batch_setup(pd_batch** out, int count, const int* ncell, const double* le
   if (he == hipSuccess) he = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (he == hipSuccess)
     he = hipMemcpy(b->pnull, pn.data(), pn.size() * sizeof(double), hipMemcpyHostToDevice);
+
   if (he != hipSuccess) {
     b->err = std::string("setup: ") + hipGetErrorString(he);
     return fin(PD_EDEVICE);
@@ -714,6 +791,17 @@ int pd_batch_configure(pd_batch* b, int key, double v) {
       if (!(v > 0.0 && v < 1.0)) return bfail(b, PD_EINVAL, "pause factor must be in (0, 1)");
       b->ru = v;
       break;
+    case PD_BCFG_PRECOND: {
+      if (!(v == 0.0 || v == 1.0)) return bfail(b, PD_EINVAL, "precond must be 0 or 1");
+      const int p = (int)v;
+      if (p != b->precond) {
+        // the captured chunks embed the kernels and operands of the other form
+        (void)hipDeviceSynchronize();
+        for (Plan& pl : b->all) drop_plan(&pl);
+        b->precond = p;
+      }
+      break;
+    }
     default:
       return bfail(b, PD_EINVAL, "unknown configuration key");
   }
@@ -772,11 +860,20 @@ int pd_batch_cg_solve(pd_batch* b, int prec, const void* bvec, void* xvec, doubl
     BHIP(b, pdk::launch_stream_batch(3, all, nullptr, nullptr, b->b64, nullptr, nullptr, s));
     BHIP(b, pdk::launch_finalize_batch(1, all, s));
     // r32 = b / scale with partials of <r32, r32> in the rho slot of iteration 0
-    BHIP(b, pdk::launch_stream_batch(2, make_iter(b, 0, b->everyone, 0, 0, 1), nullptr, nullptr,
-                                     b->b64, nullptr, b->r32, s));
+    const BatchIter i32 = make_iter(b, 0, b->everyone, 0, 0, 1);
+    BHIP(b, pdk::launch_stream_batch(2, i32, nullptr, nullptr, b->b64, nullptr, b->r32, s));
+    // preconditioned: z32 = P r32 with the partials of <r, z> and <r, r> of iteration 0
+    if (b->precond) {
+      const int rcp = pcg_pass(b, b->everyone_n, 0, 0, 0, 1, true, 1, nullptr, b->r32, b->z32, s);
+      if (rcp) return rcp;
+    }
   } else {
     // r = b with partials in the rho slot of iteration 0; tol2 = rtol^2 ||b||^2
     BHIP(b, pdk::launch_stream_batch(4, all, b->b64, nullptr, b->r64, nullptr, nullptr, s));
+    if (b->precond) {
+      const int rcp = pcg_pass(b, b->everyone_n, 0, 0, -1, 0, false, 1, nullptr, b->r64, b->z64, s);
+      if (rcp) return rcp;
+    }
     BHIP(b, pdk::launch_stream_batch(3, all, nullptr, nullptr, b->r64, nullptr, nullptr, s));
     BHIP(b, pdk::launch_finalize_batch(2, all, s));
   }
@@ -872,7 +969,8 @@ int pd_batch_cg_solve(pd_batch* b, int prec, const void* bvec, void* xvec, doubl
       o.fallback_iter = refine ? h.fallback_k : -1;
       o.reserved = 0;
       const double bn = std::sqrt(h.bnorm2);
-      const double rec = (refine && !h.mode64) ? std::sqrt(h.rho) * h.scale : std::sqrt(h.rho);
+      const double r2 = b->precond ? h.res2 : h.rho;   // preconditioned: rho is <r, z>
+      const double rec = (refine && !h.mode64) ? std::sqrt(r2) * h.scale : std::sqrt(r2);
       o.rel_res_recur = bn > 0 ? rec / bn : 0.0;
       o.rel_res_true = bn > 0 ? std::sqrt(h.aux) / bn : 0.0;
       o.ms = ms;

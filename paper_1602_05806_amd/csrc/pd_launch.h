@@ -231,6 +231,9 @@ struct BatchIter {
   double* nsp;           // problems x kNsBlocksBatch x kMaxNC2D node-sum partials
   double* corr;          // problems x kMaxNC2D null-space corrections
   const double* pnull;   // 9 x 81 projectors onto null(R~ - L~), by degree
+  // preconditioned solves (else nullptr): partials of <r, r> (problems x 2 x kMaxStreamPartials,
+  // iteration parity; rho then holds those of <r, z>)
+  double* res;
   const int* kbase;      // device iteration base of the replayed chunk
   int koff;              // iteration offset of this launch within the chunk
 };
@@ -268,6 +271,15 @@ hipError_t launch_stream_batch(int mode, const BatchIter& it, const double* b, c
                                double* r64, double* x64, float* v32, hipStream_t s);
 // what 0: aux = sum; 1: refinement start; 2: FP64 start; 3: chunk-end decision (see kernel)
 hipError_t launch_finalize_batch(int what, const BatchIter& it, hipStream_t s);
+// Cell-block Jacobi preconditioner of the listed problems, which all have degree N (V: the
+// (N+1)^2 eigenbasis, lam: its N+1 eigenvalues). sel 0: the second half of a preconditioned
+// iteration (alpha from the sigma partials, r -= alpha q, z = P r, partials of <r, z> and
+// <r, r> in the slots of the next iteration); sel 1: z = P r of the problems the iterator serves,
+// partials in the slots of iteration koff; sel 2: the same for the problems resuming from a
+// recomputed residual (switched).
+hipError_t launch_pcg_update_batch(const BatchIter& it, int N, bool fp32, int sel,
+                                   const double* V, const double* lam, const void* q, void* r,
+                                   void* z, hipStream_t s);
 hipError_t launch_project_null_batch(const BatchIter& it, double* v, hipStream_t s);
 hipError_t launch_tick(int* kbase, int by, hipStream_t s);
 hipError_t launch_zero_all(bool fp32, void* v, long long n, hipStream_t s);

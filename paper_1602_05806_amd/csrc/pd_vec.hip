@@ -344,14 +344,6 @@ struct PrecArgs {
   double alpha, c0, c1, c2;
 };
 
-// Cells per group of the preconditioner kernel: as many as keep one line of N+1 nodes per
-// direction per thread (n^(d-1) lines per cell and direction, at most kBlock lines).
-__host__ __device__ constexpr int pcg_cells_per_group(int N, int dim) {
-  return (dim == 3 ? kBlock / ((N + 1) * (N + 1)) : kBlock / (N + 1)) < 1
-             ? 1
-             : (dim == 3 ? kBlock / ((N + 1) * (N + 1)) : kBlock / (N + 1));
-}
-
 // UPD = 1: second half of a preconditioned CG iteration k (r -= alpha_k q first, alpha_k from
 // the sigma partials); UPD = 0: z = P r only. Partials of <r, z> and <r, r> per block. Each
 // block takes groups of CPB whole cells (grid-stride over the groups, the next group's r and q
