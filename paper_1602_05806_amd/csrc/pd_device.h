@@ -9,14 +9,6 @@ namespace pdk {
 constexpr int kBlock = 256;          // threads of the streaming kernels
 constexpr int kMaxPartials = 1 << 16;        // blocks of one operator-apply launch
 constexpr int kMaxStreamPartials = 1024;     // blocks of one streaming-kernel launch
-
-// Cells per group of the block-Jacobi preconditioner kernels: as many as keep one line of N+1
-// nodes per direction per thread (n^(d-1) lines per cell and direction, at most kBlock lines).
-__host__ __device__ constexpr int pcg_cells_per_group(int N, int dim) {
-  return (dim == 3 ? kBlock / ((N + 1) * (N + 1)) : kBlock / (N + 1)) < 1
-             ? 1
-             : (dim == 3 ? kBlock / ((N + 1) * (N + 1)) : kBlock / (N + 1));
-}
 constexpr int kMaxNC = 729;          // (N+1)^3 for N = 8
 
 // 1D blocks of the operator of eq. (pSyst) for degree N in precision T, passed as a kernel

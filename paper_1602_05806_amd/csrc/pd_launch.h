@@ -6,6 +6,14 @@
 
 namespace pdk {
 
+// Cells per group of the block-Jacobi preconditioner kernels: as many as keep one line of N+1
+// nodes per direction per thread (n^(d-1) lines per cell and direction, at most kBlock lines).
+__host__ __device__ constexpr int pcg_cells_per_group(int N, int dim) {
+  return (dim == 3 ? kBlock / ((N + 1) * (N + 1)) : kBlock / (N + 1)) < 1
+             ? 1
+             : (dim == 3 ? kBlock / ((N + 1) * (N + 1)) : kBlock / (N + 1));
+}
+
 // FP64 copies of the 1D tables a launch needs (converted to the kernel precision at launch).
 struct OpTables {
   double L[81], C[81], R[81], w[9];
