@@ -56,8 +56,10 @@ __global__ __launch_bounds__(256) void k_apply2d(ApplyArgs<T> a, Blk<T, N> B) {
 
 template <int N>
 struct Tile3D {
-  static constexpr int TX = N == 0 ? 16 : N == 1 ? 8 : N == 2 ? 8 : N <= 4 ? 4 : N == 5 ? 4 : 2;
-  static constexpr int TY = N == 0 ? 16 : N == 1 ? 8 : N == 2 ? 4 : N <= 4 ? 4 : 2;
+  // cells per column tile; N = 5 takes 4 x 4 (557 against 908 us per FP64 apply at 54^3 with
+  // 4 x 2), N = 6..8 keep 2 x 2 (4 x 2 at N = 6: 847 against 694 us at 46^3)
+  static constexpr int TX = N == 0 ? 16 : N == 1 ? 8 : N == 2 ? 8 : N <= 5 ? 4 : 2;
+  static constexpr int TY = N == 0 ? 16 : N == 1 ? 8 : N == 2 ? 4 : N <= 5 ? 4 : 2;
   static constexpr int NTH = TX * TY * (N + 1) * (N + 1);
 };
 
@@ -70,8 +72,10 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   constexpr int NS = NT + 2 * TY + 2 * TX;
   constexpr int NH = NS - NT;
   // the staging buffer alternates between planes when two fit in the 160 KB of LDS, which
-  // removes the barrier at the end of each plane (1.7 % at 64^3 N = 4, 2.7 % at 96^3 N = 2)
-  constexpr bool DB = (2 * NS * NC + NT * NC) * sizeof(T) + 2 * NS * sizeof(int) <= 160 * 1024;
+  // removes the barrier at the end of each plane (1.7 % at 64^3 N = 4, 2.7 % at 96^3 N = 2,
+  // 3 % at 54^3 N = 5); not for N >= 6, where the second buffer costs resident workgroups
+  // (46^3 N = 6: 931 against 694 us per FP64 apply, 40^3 N = 7: 1024 against 637 us)
+  constexpr bool DB = N <= 5 && (2 * NS * NC + NT * NC) * sizeof(T) + 2 * NS * sizeof(int) <= 160 * 1024;
   __shared__ T xsb[DB ? 2 : 1][NS * NC];
   __shared__ T ys[NT * NC];
   __shared__ int hbase[NS];     // in-plane cell index (j*nx + i, wrapped) of every halo slot
