@@ -244,6 +244,71 @@ def bench_batch(args, pd, torch):
     print(json.dumps(line))
 
 
+def next_rows(pd, torch):
+    """Measurements of the extensions beyond the paper's semi-implicit periodic step, on the
+    benchmark's grids: homogeneous Dirichlet pressure walls on every side (64^3 N = 4 pressure
+    solve against the periodic one, with the fused apply's live rate), the explicit-viscosity
+    step and the space-time step (M = 1, 2; explicit viscous flux) of 256^2 N = 6 against the
+    semi-implicit step at the same viscosity (nu = 4e-5, inside the explicit CFL bound)."""
+    import synthetic
+    out = {}
+    # walls: 64^3 N = 4, white right-hand side, FP64 to 1e-10
+    cells, N, dt = (64, 64, 64), 4, 1e-3
+    for name, mask in (("periodic", 7), ("walls", 0)):
+        ctx = pd.pd_setup(3, cells, (1.0, 1.0, 1.0), N, dt, 0.6, 1e-3, periodic_mask=mask)
+        b = torch.tensor(synthetic.random_rhs(17, ctx.ndof), dtype=torch.float64, device="cuda")
+        x = torch.zeros_like(b)
+        pd.pd_cg_solve(ctx, pd.PD_OP_PRESSURE, pd.PD_FP64, b, x, 1e-10, 400000)   # warm-up
+        pd.pd_configure(ctx, pd.PD_CFG_TIMING, TIMING_STRIDE)
+        pd.pd_timing(ctx, pd.PD_FP64, reset=True)
+        x.zero_()
+        info = pd.pd_cg_solve(ctx, pd.PD_OP_PRESSURE, pd.PD_FP64, b, x, 1e-10, 400000)
+        kt = pd.pd_timing(ctx, pd.PD_FP64, reset=True)
+        avg_ms, gbs = kernel_rate(kt)
+        out[f"{name}_rand3d_64_N4_solve"] = dict(
+            iters=info["iters"], solve_ms=info["ms"], rel_res_true=info["rel_res_true"],
+            apply_us=1e3 * avg_ms, apply_gbs=gbs, apply_frac=gbs / HBM_PEAK_GBS if gbs else None)
+        ctx.close()
+        del b, x
+    # explicit viscosity and the space-time step on 256^2 N = 6
+    cfg = dict(synthetic.CONFIGS["rand2d_256_N6"])
+    cfg["nu"] = 4e-5
+    for name, theta, evisc, M in (("semi_implicit", 1.0, 0, None), ("explicit_viscosity", 1.0, 1, None),
+                                  ("space_time_M1", 1.0, 1, 1), ("space_time_M2", 1.0, 1, 2)):
+        ctx = pd.pd_setup(2, cfg["cells"], cfg["lengths"], cfg["N"], cfg["dt"], theta, cfg["nu"])
+        pd.pd_configure(ctx, pd.PD_CFG_P_RTOL, cfg["rtol"])
+        pd.pd_configure(ctx, pd.PD_CFG_EXPLICIT_VISC, evisc)
+        u = initial_state(pd, ctx, cfg, torch)
+        steps, iters, solves = 3, 0, 0
+        if M is None:
+            p = torch.zeros(ctx.ndof, dtype=torch.float64, device="cuda")
+            pd.pd_step(ctx, u, p)                                          # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                info = pd.pd_step(ctx, u, p)
+                iters += info[3]["iters"]
+                solves += 1
+        else:
+            p = torch.zeros((M + 1) * ctx.ndof, dtype=torch.float64, device="cuda")
+            pd.pd_step_st(ctx, M, u, p)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                info = pd.pd_step_st(ctx, M, u, p)
+                for i in info[3:]:
+                    iters += i["iters"]
+                    solves += 1
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        out[f"{name}_rand2d_256_N6"] = dict(ms_per_step=1e3 * secs / steps,
+                                            pressure_solves_per_step=solves / steps,
+                                            pressure_iters_per_step=iters / steps, nu=cfg["nu"])
+        ctx.close()
+        del u, p
+    return out
+
+
 def bench_adjoint(args, pd, torch):
     """Adjoint workload: one step = one gradient of the final kinetic energy with respect to the
     initial velocity (forward rollout with checkpoints, backward with segment recomputation and
@@ -618,6 +683,7 @@ def main():
             print(f"bench.py: timing {wl}", file=sys.stderr, flush=True)
             others.append((wl,) + workload_line(pd, torch, wl, args, args.steps3d, 1, outdir))
         copy_gbs = device_copy_gbs(torch)
+        nxt = None if (args.single or args.no_check) else next_rows(pd, torch)
         checks = [(cfg, main_wl, rep_main)] + [(c, wl, r) for wl, c, s, r in others]
         if args.no_check:
             base, errs = None, None
@@ -670,6 +736,8 @@ def main():
             "note": "FP64 CG working set ~128 MB, held in the 256 MB Infinity Cache",
             **f64["apply_kernel"]} if hbm is not s_main else None,
         "other_workloads": {wl: s for wl, c, s, r in others},
+        # Dirichlet walls, explicit viscosity and the space-time step on the benchmark grids
+        "extensions": nxt,
         "kernel_source_hash": kernel_source_hash(),
     }
     if base is not None:
