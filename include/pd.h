@@ -90,7 +90,7 @@ typedef struct {
  * space of A_p shrinks to the part of the cell-periodic kernel that is odd about the cell centre
  * (none for even N, so A_p is then definite). Walls cover pd_apply, pd_cg_solve,
  * pd_project_null and pd_project_null_noalloc; every velocity, step, adjoint and loss entry
- * point and PD_CFG_PRECOND require a fully periodic context (PD_EINVAL otherwise). On error
+ * point requires a fully periodic context (PD_EINVAL otherwise). On error
  * *out is NULL and the message is available from pd_last_error(NULL). */
 int pd_setup(pd_ctx** out, int dim, const int ncell[3], const double len[3], int N,
              double dt, double theta, double nu, unsigned periodic_mask, void* hip_stream);
@@ -302,7 +302,11 @@ int pd_kinetic_energy(pd_ctx* ctx, void* const u[3], double gscale, void* const 
  *                        eigenbasis of the 1D blocks (C, M) (tensor products of (N+1) x (N+1)
  *                        transforms); beta = <r', z'> / <r, z>; the stopping test stays on
  *                        ||r||_2. Allocates z in both precisions on first use. The one-kernel form
- *                        is not used with it. 0 (default) = the paper's unpreconditioned CG.
+ *                        is not used with it. Every cell uses the interior block C along each
+ *                        direction: next to a Dirichlet wall, and across a periodic direction of a
+ *                        single cell, the true diagonal block also holds the wall or wrap
+ *                        couplings; P stays symmetric positive definite there, only less exact.
+ *                        0 (default) = the paper's unpreconditioned CG.
  *   PD_CFG_EXPLICIT_VISC 1 = the explicit-viscosity variant of Section 2.2: the viscous flux
  *                        -nu grad q is part of the explicit TVD-RK3 step of pd_step and pd_convect
  *                        (broken gradient at the nodes, averaged normal derivatives on faces,

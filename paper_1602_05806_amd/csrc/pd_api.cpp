@@ -255,9 +255,6 @@ int pcg_init(pd_ctx* c, const struct CgRun* R, int slot, hipStream_t s);
 // whose CG state holds tol2 / maxit.
 int cg_prepare(pd_ctx* c, CgRun* R) {
   R->pc = c->precond != 0;
-  if (R->pc && !c->periodic)
-    return fail(c, PD_EINVAL, "PD_CFG_PRECOND: fully periodic grids only (the wall cells' "
-                              "diagonal blocks differ from the interior block)");
   R->nrho = R->pc ? (int)pdk::pcg_grid(c->ncells, c->dim, c->N) : (int)pdk::stream_grid(c->ndof);
   R->rho[0] = c->rhopart;
   R->rho[1] = c->rhopart + pdk::kMaxStreamPartials;
