@@ -11,7 +11,9 @@
 //       thread owns one z-line of one cell and keeps the z-lines of planes k-1, k, k+1 in
 //       registers, so the z coupling never touches LDS and every cell is read from HBM once
 //       (plus two boundary planes per column segment). The x- and y-lines of plane k go through
-//       LDS with the plane's x/y face halos.
+//       LDS with the plane's x/y face halos. A coalesced form (k_apply3d_co) moves each plane's
+//       values in memory order and reads the z-lines back from LDS; it is used where it measured
+//       faster (Co3D).
 // FUSE = 1 is the CG form: the search direction p = r + beta p_old is formed while loading
 // (beta read from the device-resident CG state), stored for the owned cells, and the block sums of
 // <p, A p> feed the grid reduction that sets alpha = rho / <p, A p>. FUSE = 2 adds the deferred x
@@ -364,6 +366,301 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   }
 }
 
+// Coalesced form of the 3D kernel (periodic grids, N <= 5). The tile's cells of one plane lie in
+// global memory as TY rows of TX * (N+1)^3 consecutive values, in the same order as the staging
+// buffer: thread t moves values t, t + NTH, ..., so every wave's load or store covers 64
+// consecutive values (the z-line form above touches (N+1)^2-value pieces of several cells per
+// instruction). The z-line of each thread is then read back from the staging buffer. Both the
+// staging buffer and (when LDS allows) the accumulator alternate between planes: two barriers
+// per plane, and the accumulator of plane k is stored to y, coalesced, during plane k + 1.
+template <typename T, int N>
+struct Co3D {
+  static constexpr int n = N + 1, NC = n * n * n;
+  static constexpr int NT = Tile3D<N>::TX * Tile3D<N>::TY;
+  static constexpr int NS = NT + 2 * Tile3D<N>::TY + 2 * Tile3D<N>::TX;
+  static constexpr long XS = 2L * NS * NC * (long)sizeof(T), YS = (long)NT * NC * (long)sizeof(T);
+  static constexpr bool OK = N <= 5 && XS + YS + NS * 4L <= 160L * 1024;
+  static constexpr bool YDB = XS + 2 * YS + NS * 4L <= 160L * 1024;
+  // where it is used (per-launch means of the fused CG apply, ~33M DoFs, against the z-line
+  // form): FP32 N = 1..4 (128^3 N = 1: 91.5 against 108.8 us; 96^3 N = 2: 174 / 216; 80^3
+  // N = 3: 169 / 194; 64^3 N = 4: 196 / 210) and FP64 N = 1 (208.5 / 219). FP64 N = 2..5 and
+  // FP32 N = 5 stay on the z-line form (64^3 N = 4 FP64: 385 against 378 us; 54^3 N = 5 FP32:
+  // 267 / 249, the coalesced form needs 129 registers there), and so does N = 0 (one value
+  // per cell: nothing to coalesce).
+  static constexpr bool USE = OK && (sizeof(T) == 4 ? (N >= 1 && N <= 4) : N == 1);
+};
+
+template <typename T, int N, int FUSE, int PF>
+__global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, Blk<T, N> B) {
+  constexpr int n = N + 1, NP = n * n, NC = n * n * n;
+  constexpr int TX = Tile3D<N>::TX, TY = Tile3D<N>::TY, NT = TX * TY, NTH = Tile3D<N>::NTH;
+  constexpr int S_XL = NT, S_XR = NT + TY, S_YL = NT + 2 * TY, S_YR = NT + 2 * TY + TX;
+  constexpr int NS = NT + 2 * TY + 2 * TX;
+  constexpr int NH = NS - NT;
+  constexpr bool YDB = Co3D<T, N>::YDB;
+  static_assert(Co3D<T, N>::OK, "coalesced 3D form needs two staging buffers");
+  static_assert(NTH * n == NT * NC, "n values per thread cover the tile's plane");
+  __shared__ T xsb[2][NS * NC];
+  __shared__ T ysb[YDB ? 2 : 1][NT * NC];
+  __shared__ int hbase[NS];
+  const int kit = FUSE ? (a.kbase ? *a.kbase + a.k : a.k) : 0;
+  if (FUSE) {
+    if (!apply_may_run(a.st, kit)) return;
+  }
+  const T* __restrict__ xg = a.x;
+  const T* __restrict__ pg = a.pold;
+  T* __restrict__ png = a.pnew;
+  T* __restrict__ yg = a.y;
+  const unsigned tile = xcd_remap(blockIdx.x, gridDim.x);
+  const int tcol = (int)(tile % (unsigned)(a.ntx * a.nty));
+  const int zseg = (int)(tile / (unsigned)(a.ntx * a.nty));
+  const int tx0 = (tcol % a.ntx) * TX, ty0 = (tcol / a.ntx) * TY;
+  const int k0 = zseg * a.kz;
+  const int k1 = min(k0 + a.kz, a.nz);
+  for (int s = NT + (int)threadIdx.x; s < NS; s += NTH) {
+    int hi, hj;
+    if (s < S_XR) { hi = -1; hj = s - S_XL; }
+    else if (s < S_YL) { hi = TX; hj = s - S_XR; }
+    else if (s < S_YR) { hi = s - S_YL; hj = -1; }
+    else { hi = s - S_YR; hj = TY; }
+    hbase[s] = wrapi(ty0 + hj, a.ny) * a.nx + wrapi(tx0 + hi, a.nx);
+  }
+
+  const int t = threadIdx.x;
+  const int c = t / NP, lp = t - c * NP;          // z-line of this thread: cell c, (l1, l2) = lp
+  const int ci = c % TX, cj = c / TX;
+  const int ui = tx0 + ci, uj = ty0 + cj;
+  const bool valid = ui < a.nx && uj < a.ny;
+  const int gi = wrapi(ui, a.nx), gj = wrapi(uj, a.ny);
+  const size_t plane = (size_t)a.nx * a.ny * NC;  // values per plane
+  // values t + NTH i of the tile's plane: in-plane offset and whether the cell is in the grid
+  // (a ragged tile's cells beyond the edge hold the periodic images, read but never stored)
+  int off[n];
+  unsigned own = 0;
+#pragma unroll
+  for (int i = 0; i < n; ++i) {
+    const int e = t + NTH * i;
+    const int rj = e / (TX * NC), o = e - rj * (TX * NC);
+    const int rc = o / NC, q = o - rc * NC;
+    off[i] = (wrapi(ty0 + rj, a.ny) * a.nx + wrapi(tx0 + rc, a.nx)) * NC + q;
+    if (tx0 + rc < a.nx && ty0 + rj < a.ny) own |= 1u << i;
+  }
+  __syncthreads();   // hbase ready
+
+  T beta = T(0);
+  bool xupd = false;   // FUSE = 2: x += xalpha p_old on the owned values
+  T xalpha = T(0);
+  T zp[n], zc[n];
+  {
+    // planes k0 - 1 and k0 of this thread's z-line; the CG scalars are reduced while they load
+    const size_t bp = (size_t)wrap_small(k0 - 1, a.nz) * plane + ((size_t)gj * a.nx + gi) * NC + lp;
+    const size_t bc = (size_t)k0 * plane + ((size_t)gj * a.nx + gi) * NC + lp;
+    T pp[n], pc[n], xc[FUSE == 2 ? n : 1];
+#pragma unroll
+    for (int l3 = 0; l3 < n; ++l3) {
+      zp[l3] = xg[bp + l3 * NP];
+      zc[l3] = xg[bc + l3 * NP];
+      if (FUSE) {
+        pp[l3] = pg[bp + l3 * NP];
+        pc[l3] = pg[bc + l3 * NP];
+      }
+      if (FUSE == 2) xc[l3] = a.xsol[bc + l3 * NP];
+    }
+    if (FUSE) {
+      const int k = kit;
+      const IterScalars sc = iteration_scalars<NTH>(a.st, k, a.rho_cur, a.nrho, blockIdx.x == 0,
+                                                    false, a.res_cur);
+      if (sc.stop) return;
+      beta = (T)sc.beta;
+      if (FUSE == 2) {
+        xupd = k >= 1 && a.st->xk == k - 1;
+        xalpha = (T)a.st->alpha;
+        if (xupd && blockIdx.x == 0 && threadIdx.x == 0) a.st->xused = k - 1;
+      }
+#pragma unroll
+      for (int l3 = 0; l3 < n; ++l3) {
+        zp[l3] = zp[l3] + beta * pp[l3];
+        zc[l3] = zc[l3] + beta * pc[l3];
+        if (valid) {
+          png[bc + l3 * NP] = zc[l3];
+          if (FUSE == 2 && xupd) a.xsol[bc + l3 * NP] = xc[l3] + xalpha * pc[l3];
+        }
+      }
+    }
+  }
+  const int xl23 = lp;                        // x-line: (l2, l3) = (lp % n, lp / n)
+  const int yl1 = lp % n, yl3 = lp / n;       // y-line: (l1, l3)
+  const int zl1 = lp % n, zl2 = lp / n;       // z-line: (l1, l2)
+  const int sxl = (ci == 0) ? S_XL + cj : c - 1;
+  const int sxr = (ci == TX - 1) ? S_XR + cj : c + 1;
+  const int syl = (cj == 0) ? S_YL + ci : c - TX;
+  const int syr = (cj == TY - 1) ? S_YR + ci : c + TX;
+  const T wx = a.c0 * B.w[xl23 % n] * B.w[xl23 / n];
+  const T wy = a.c1 * B.w[yl1] * B.w[yl3];
+  const T wz = a.c2 * B.w[zl1] * B.w[zl2];
+  const T wm = a.alpha * B.w[zl1] * B.w[zl2];
+  double dot = 0.0;
+
+  // x/y halo cells of a plane: one wave per cell (wave-uniform addressing)
+  constexpr int NWV = NTH / 64;
+  static_assert(NWV >= 1, "3D tile needs at least one full wave");
+  constexpr int HPW = (NH + NWV - 1) / NWV;
+  constexpr int LR = (NC + 63) / 64;
+  constexpr bool PREF = PF && HPW * LR <= 8;
+  constexpr int HR = PREF ? HPW : 1;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int lane = t & 63;
+  T hv[HR][LR], hp[HR][LR];
+  auto halo_load = [&](int k) {
+    const size_t pb = (size_t)wrap_small(k, a.nz) * plane;
+#pragma unroll
+    for (int i = 0; i < HR; ++i) {
+      const int s = NT + wave + NWV * i;
+      if (wave < NWV && s < NS) {
+        const size_t g = pb + (size_t)hbase[s] * NC;
+#pragma unroll
+        for (int r = 0; r < LR; ++r) {
+          const int l = lane + 64 * r;
+          if (l < NC) {
+            hv[i][r] = xg[g + l];
+            if (FUSE) hp[i][r] = pg[g + l];
+          }
+        }
+      }
+    }
+  };
+  auto halo_store = [&](T* xs) {
+#pragma unroll
+    for (int i = 0; i < HR; ++i) {
+      const int s = NT + wave + NWV * i;
+      if (wave < NWV && s < NS) {
+#pragma unroll
+        for (int r = 0; r < LR; ++r) {
+          const int l = lane + 64 * r;
+          if (l < NC) xs[s * NC + l] = FUSE ? (T)(hv[i][r] + beta * hp[i][r]) : hv[i][r];
+        }
+      }
+    }
+  };
+  auto halo_direct = [&](T* xs, int k) {
+    const size_t pb = (size_t)wrap_small(k, a.nz) * plane;
+#pragma unroll 1
+    for (int i = 0; i < HPW; ++i) {
+      const int s = NT + wave + NWV * i;
+      if (wave < NWV && s < NS) {
+        const size_t g = pb + (size_t)hbase[s] * NC;
+        for (int l = lane; l < NC; l += 64)
+          xs[s * NC + l] = FUSE ? (T)(xg[g + l] + beta * pg[g + l]) : xg[g + l];
+      }
+    }
+  };
+  // plane k0 into staging buffer 0
+#pragma unroll
+  for (int l3 = 0; l3 < n; ++l3) xsb[0][c * NC + l3 * NP + lp] = zc[l3];
+  halo_direct(xsb[0], k0);
+  __syncthreads();
+
+  for (int k = k0; k < k1; ++k) {
+    const int cur = (k - k0) & 1;
+    T* xs = xsb[cur];
+    T* xnx = xsb[cur ^ 1];
+    T* ys = ysb[YDB ? cur : 0];
+    const bool store_next = k + 1 < k1;
+    const size_t pbn = (size_t)wrap_small(k + 1, a.nz) * plane;
+    // plane k+1: own values (coalesced) and halo, in flight through the x/y phases
+    T xo[n], po[n], xso[FUSE == 2 ? n : 1];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      xo[i] = xg[pbn + off[i]];
+      if (FUSE) po[i] = pg[pbn + off[i]];
+      if (FUSE == 2 && xupd && store_next && ((own >> i) & 1)) xso[i] = a.xsol[pbn + off[i]];
+    }
+    if constexpr (PREF) {
+      if (store_next) halo_load(k + 1);
+    }
+    {  // x-line (l2, l3) of cell c
+      T vl[n], vc[n], vr[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        vl[m] = xs[sxl * NC + xl23 * n + m];
+        vc[m] = xs[c * NC + xl23 * n + m];
+        vr[m] = xs[sxr * NC + xl23 * n + m];
+      }
+      line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + xl23 * n + l1] = wx * v; });
+    }
+    __syncthreads();
+    {  // y-line (l1, l3) of cell c
+      T vl[n], vc[n], vr[n];
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        vl[m] = xs[syl * NC + yl3 * NP + m * n + yl1];
+        vc[m] = xs[c * NC + yl3 * NP + m * n + yl1];
+        vr[m] = xs[syr * NC + yl3 * NP + m * n + yl1];
+      }
+      line3<T, N>(B, vl, vc, vr,
+                  [&](int l2, T v) { ys[c * NC + yl3 * NP + l2 * n + yl1] += wy * v; });
+    }
+    // plane k+1 into the other staging buffer; p and x of its owned values to global memory
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+      const T v = FUSE ? (T)(xo[i] + beta * po[i]) : xo[i];
+      xnx[t + NTH * i] = v;
+      if (FUSE && store_next && ((own >> i) & 1)) {
+        png[pbn + off[i]] = v;
+        if (FUSE == 2 && xupd) a.xsol[pbn + off[i]] = xso[i] + xalpha * po[i];
+      }
+    }
+    if (store_next) {   // (the last plane's neighbour above is needed for its z-lines only)
+      if constexpr (PREF) halo_store(xnx);
+      else halo_direct(xnx, k + 1);
+    }
+    if constexpr (YDB) {
+      // y of plane k - 1 (its accumulator, completed before this plane's first barrier)
+      if (k > k0) {
+        const T* yp = ysb[cur ^ 1];
+        const size_t pbp = (size_t)(k - 1) * plane;
+#pragma unroll
+        for (int i = 0; i < n; ++i)
+          if ((own >> i) & 1) yg[pbp + off[i]] = yp[t + NTH * i];
+      }
+    }
+    __syncthreads();
+    {  // own z-line (l1, l2): planes k-1, k from registers, k+1 from staging; final values
+      T zn[n];
+#pragma unroll
+      for (int l3 = 0; l3 < n; ++l3) zn[l3] = xnx[c * NC + l3 * NP + lp];
+      const size_t bc = (size_t)k * plane + ((size_t)gj * a.nx + gi) * NC + lp;
+      line3<T, N>(B, zp, zc, zn, [&](int l3, T v) {
+        const T xc = xs[c * NC + l3 * NP + lp];
+        const T val = ys[c * NC + l3 * NP + lp] + wz * v + wm * B.w[l3] * xc;
+        if constexpr (YDB) ys[c * NC + l3 * NP + lp] = val;
+        if (valid) {
+          if constexpr (!YDB) yg[bc + l3 * NP] = val;
+          dot += (double)xc * (double)val;
+        }
+      });
+#pragma unroll
+      for (int l3 = 0; l3 < n; ++l3) {
+        zp[l3] = zc[l3];
+        zc[l3] = zn[l3];
+      }
+    }
+    if constexpr (!YDB) __syncthreads();   // the accumulator is rewritten by the next x-lines
+  }
+  if constexpr (YDB) {
+    __syncthreads();
+    const T* yp = ysb[(k1 - 1 - k0) & 1];
+    const size_t pbp = (size_t)(k1 - 1) * plane;
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+      if ((own >> i) & 1) yg[pbp + off[i]] = yp[t + NTH * i];
+  }
+  if (FUSE) {
+    const double s = block_sum_all<NTH>(dot);
+    if (threadIdx.x == 0) a.sigpart[blockIdx.x] = s;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 template <typename T, int N>
@@ -433,13 +730,18 @@ static long long resident_2d(int fuse, int v, int pf, bool mir) {
 }
 
 // The 3D kernel of fused form 0, 1 or 2 and prefetch flag pf; a grid with walls (mir) runs the
-// halo-prefetch form.
+// halo-prefetch z-line form, a periodic grid the coalesced form where Co3D selects it.
 template <typename T, int N>
 static const void* kernel_3d(int fuse, int pf, bool mir) {
   if (mir) {
     return fuse == 2 ? (const void*)k_apply3d<T, N, 2, 1, true>
          : fuse == 1 ? (const void*)k_apply3d<T, N, 1, 1, true>
                      : (const void*)k_apply3d<T, N, 0, 0, true>;
+  }
+  if constexpr (Co3D<T, N>::USE) {
+    return fuse == 2 ? (pf ? (const void*)k_apply3d_co<T, N, 2, 1> : (const void*)k_apply3d_co<T, N, 2, 0>)
+         : fuse == 1 ? (pf ? (const void*)k_apply3d_co<T, N, 1, 1> : (const void*)k_apply3d_co<T, N, 1, 0>)
+                     : (const void*)k_apply3d_co<T, N, 0, 0>;
   }
   return fuse == 2 ? (pf ? (const void*)k_apply3d<T, N, 2, 1, false> : (const void*)k_apply3d<T, N, 2, 0, false>)
        : fuse == 1 ? (pf ? (const void*)k_apply3d<T, N, 1, 1, false> : (const void*)k_apply3d<T, N, 1, 0, false>)
@@ -617,8 +919,8 @@ hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
 #undef PD_A2D
   } else {
     constexpr int NTH = Tile3D<N>::NTH;
-    if (walls) {
-      const void* f = kernel_3d<T, N>(L.fuse, 1, true);
+    if (walls || Co3D<T, N>::USE) {
+      const void* f = kernel_3d<T, N>(L.fuse, walls ? 1 : (L.fuse && pf ? 1 : 0), walls);
       void* args[] = {&a, (void*)&B};
       const hipError_t e = hipExtLaunchKernel(f, dim3(G), dim3(NTH), args, 0, s, e0, e1, 0);
       if (e != hipSuccess) return e;

@@ -37,6 +37,8 @@ APPLY_CASES = [
     (2, (1, 4), 2), (2, (13, 5), 5),
     (3, (5, 6, 9), 4), (3, (3, 3, 3), 3), (3, (2, 3, 9), 1), (3, (3, 2, 2), 8), (3, (4, 4, 5), 2),
     (3, (9, 2, 3), 0), (3, (3, 2, 6), 6),
+    # ragged and wrapped tiles of the coalesced 3D form (FP32 N = 1..4, FP64 N = 1)
+    (3, (11, 5, 4), 1), (3, (10, 3, 5), 2), (3, (7, 9, 3), 3), (3, (6, 5, 4), 4), (3, (2, 7, 3), 4),
 ]
 
 
