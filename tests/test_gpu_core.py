@@ -146,6 +146,51 @@ def test_cg_iterates_match_oracle_cg(pd, dim, cells, N, m, form):
     assert np.linalg.norm(got - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
 
 
+@pytest.mark.parametrize("cells,N", [((6, 5, 7), 4), ((9, 7, 5), 2), ((11, 5, 6), 1), ((5, 4, 9), 3),
+                                     ((4, 3, 6), 5), ((3, 2, 5), 6)])
+def test_3d_launch_shapes_match_oracle_cg(pd, cells, N):
+    """The 3D operator kernel's launch-shape settings cut the work differently, not what is
+    computed: with the halo prefetch off (PD_CFG_PREFETCH 0) and with column segments of 1 and 3
+    planes (PD_CFG_KZ) the FP64 iterate after m iterations equals the oracle's plain CG iterate
+    (these shapes run both 3D kernel forms, ragged and wrapped tiles, and segments that end at the
+    last plane). In FP32 (refined) the prefetch setting gives bit-identical iterates, the segment
+    length changes only the grouping of the FP64 dot-product partials."""
+    import torch
+    m = 24
+    print(f"3d launch shapes cells={cells} N={N}", flush=True)
+    L = (1.0, 0.8, 1.2)
+    dt = 5e-4
+    g = Grid(cells, L, N)
+    A = pressure_operator(g, dt)
+    bt = layout.blocked_to_tensor(synthetic.random_rhs(300 + N, g.ndof), cells, g.n)
+    bt = project_null(g, bt, [null_basis_tiled(c, N) for c in cells])
+    x_ref, it, _ = cg(A, bt.reshape(-1), 1e-30, m)
+    assert it == m
+    ctx = pd.pd_setup(3, cells, L, N, dt, 0.6, 1e-2)
+    b = dev(layout.tensor_to_blocked(bt, cells, g.n))
+
+    def run(prec, pf, kz):
+        pd.pd_configure(ctx, pd.PD_CFG_PREFETCH, pf)
+        pd.pd_configure(ctx, pd.PD_CFG_KZ, kz)
+        x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+        info = pd.pd_cg_solve(ctx, 0, prec, b, x, 1e-30, m)
+        assert info["status"] == pd.PD_ENOCONV and info["iters"] == m
+        return host(x)
+
+    for pf, kz in [(1, 0), (0, 0), (1, 1), (1, 3), (0, 3)]:
+        got = layout.blocked_to_tensor(run(pd.PD_FP64, pf, kz), cells, g.n).reshape(-1)
+        err = np.linalg.norm(got - x_ref) / np.linalg.norm(x_ref)
+        print(f"  fp64 prefetch={pf} kz={kz}: rel. diff vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-12
+    r0 = run(pd.PD_FP32_REFINE64, 1, 0)
+    assert np.array_equal(r0, run(pd.PD_FP32_REFINE64, 0, 0))
+    for kz in (1, 3):
+        d = np.linalg.norm(run(pd.PD_FP32_REFINE64, 1, kz) - r0) / np.linalg.norm(r0)
+        print(f"  fp32 kz={kz}: rel. diff vs automatic segments {d:.2e}", flush=True)
+        assert d <= 1e-5
+    ctx.close()
+
+
 @pytest.mark.parametrize("one", [1, 0])
 def test_timing_samples_every_sth_launch(pd, one):
     """PD_CFG_TIMING = s times every s-th operator launch of a pressure solve (iterations
