@@ -242,10 +242,12 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
         for (int r = 0; r < LR; ++r) {
           const int l = lane + 64 * r;
           if (l < NC) {
+            // (raw values: a wall's sign is applied when they are staged, so that nothing
+            // here waits for the loads)
             T sg;
             const int ls = hsrc(s, l, sg);
-            hv[i][r] = sg * xg[g + ls];
-            if (FUSE) hp[i][r] = sg * pg[g + ls];
+            hv[i][r] = xg[g + ls];
+            if (FUSE) hp[i][r] = pg[g + ls];
           }
         }
       }
@@ -259,7 +261,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
 #pragma unroll
         for (int r = 0; r < LR; ++r) {
           const int l = lane + 64 * r;
-          if (l < NC) xs[s * NC + l] = FUSE ? (T)(hv[i][r] + beta * hp[i][r]) : hv[i][r];
+          if (l < NC) {
+            T sg;
+            hsrc(s, l, sg);
+            xs[s * NC + l] = sg * (FUSE ? (T)(hv[i][r] + beta * hp[i][r]) : hv[i][r]);
+          }
         }
       }
     }
@@ -291,8 +297,8 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     T pn[n], xn[FUSE == 2 ? n : 1];
 #pragma unroll
     for (int l3 = 0; l3 < n; ++l3) {
-      zn[l3] = sgn * xg[bn + l3 * NP];
-      if (FUSE) pn[l3] = sgn * pg[bn + l3 * NP];
+      zn[l3] = xg[bn + l3 * NP];   // (a wall's sign is applied after the y-lines)
+      if (FUSE) pn[l3] = pg[bn + l3 * NP];
       if (FUSE == 2 && xupd && own_next) xn[l3] = a.xsol[bn + l3 * NP];
     }
 #pragma unroll
@@ -329,12 +335,16 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     if (FUSE) {
 #pragma unroll
       for (int l3 = 0; l3 < n; ++l3) {
-        zn[l3] = zn[l3] + beta * pn[l3];
+        zn[l3] = sgn * (zn[l3] + beta * pn[l3]);   // (sgn = 1 for the owned cells)
         if (own_next) {
           png[bn + l3 * NP] = zn[l3];
           if (FUSE == 2 && xupd) a.xsol[bn + l3 * NP] = xn[l3] + xalpha * pn[l3];
         }
       }
+    }
+    if (!FUSE) {
+#pragma unroll
+      for (int l3 = 0; l3 < n; ++l3) zn[l3] = sgn * zn[l3];
     }
     // the plane above a Dirichlet wall at z = L: odd reflection of the last plane
     if (MIR && a.mir[2] && k + 1 == a.nz) {
