@@ -198,11 +198,6 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
           T rv = xg[g], pv = T(0), qv = T(0);
           if (FUSE) pv = pg[g];
           if (rupd) qv = a.qprev[g];
-          if (MIR && neg) {
-            rv = -rv;
-            pv = -pv;
-            qv = -qv;
-          }
           if (halo) {
             if (j < JH) {
               rvh[bj ? 1 : 0][j] = rv;
@@ -274,6 +269,15 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
                 }
               }
             }
+          }
+          if constexpr (MIR) {
+            // the sign of a reflected element is applied here, not to the loaded value, so
+            // that the loads of a prefetched tile are not waited for when they are issued
+            // (owned cells are never reflected: the values stored above carry no sign)
+            const int ri = tx0 + (halo ? 0 : -1) + e / NC, rj = ty0 + bj - 1;
+            const bool nx_ = a.mir[0] && (ri < 0 || ri >= a.nx);
+            const bool ny_ = a.mir[1] && (rj < 0 || rj >= a.ny);
+            if (nx_ != ny_) v = -v;
           }
           xs[(bj * BX + (halo ? 1 : 0)) * NC + e] = v;
         }
