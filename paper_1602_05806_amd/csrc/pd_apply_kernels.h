@@ -376,7 +376,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
   }
 }
 
-// Coalesced form of the 3D kernel (periodic grids, N <= 5). The tile's cells of one plane lie in
+// Coalesced form of the 3D kernel (N <= 5). The tile's cells of one plane lie in
 // global memory as TY rows of TX * (N+1)^3 consecutive values, in the same order as the staging
 // buffer: thread t moves values t, t + NTH, ..., so every wave's load or store covers 64
 // consecutive values (the z-line form above touches (N+1)^2-value pieces of several cells per
@@ -400,7 +400,8 @@ struct Co3D {
   static constexpr bool USE = OK && (sizeof(T) == 4 ? (N >= 1 && N <= 4) : N == 1);
 };
 
-template <typename T, int N, int FUSE, int PF>
+// MIR: Dirichlet walls, as in the z-line form (the periodic kernel carries none of their code).
+template <typename T, int N, int FUSE, int PF, bool MIR = false>
 __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, Blk<T, N> B) {
   constexpr int n = N + 1, NP = n * n, NC = n * n * n;
   constexpr int TX = Tile3D<N>::TX, TY = Tile3D<N>::TY, NT = TX * TY, NTH = Tile3D<N>::NTH;
@@ -413,6 +414,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
   __shared__ T xsb[2][NS * NC];
   __shared__ T ysb[YDB ? 2 : 1][NT * NC];
   __shared__ int hbase[NS];
+  __shared__ int hmir[MIR ? NS : 1];   // bit 0 / 1: the slot is the odd reflection across an x / y wall
   const int kit = FUSE ? (a.kbase ? *a.kbase + a.k : a.k) : 0;
   if (FUSE) {
     if (!apply_may_run(a.st, kit)) return;
@@ -433,7 +435,17 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
     else if (s < S_YL) { hi = TX; hj = s - S_XR; }
     else if (s < S_YR) { hi = s - S_YL; hj = -1; }
     else { hi = s - S_YR; hj = TY; }
-    hbase[s] = wrapi(ty0 + hj, a.ny) * a.nx + wrapi(tx0 + hi, a.nx);
+    int ri = tx0 + hi, rj = ty0 + hj, m = 0;
+    if (MIR && a.mir[0] && (ri < 0 || ri >= a.nx)) {
+      ri = mirror_index(ri, a.nx);
+      m |= 1;
+    }
+    if (MIR && a.mir[1] && (rj < 0 || rj >= a.ny)) {
+      rj = mirror_index(rj, a.ny);
+      m |= 2;
+    }
+    hbase[s] = wrapi(rj, a.ny) * a.nx + wrapi(ri, a.nx);
+    if constexpr (MIR) hmir[s] = m;
   }
 
   const int t = threadIdx.x;
@@ -441,19 +453,45 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
   const int ci = c % TX, cj = c / TX;
   const int ui = tx0 + ci, uj = ty0 + cj;
   const bool valid = ui < a.nx && uj < a.ny;
-  const int gi = wrapi(ui, a.nx), gj = wrapi(uj, a.ny);
+  // a ragged tile's cells beyond a Dirichlet wall hold the odd reflection of the cells inside:
+  // the z-line of such a cell reads the mirrored source line with the sign flipped
+  int si = ui, sj = uj, slp = lp;
+  T sgn = T(1);
+  if (MIR && a.mir[0] && ui >= a.nx) {
+    si = mirror_index(ui, a.nx);
+    slp = (slp / n) * n + (n - 1 - slp % n);
+    sgn = -sgn;
+  }
+  if (MIR && a.mir[1] && uj >= a.ny) {
+    sj = mirror_index(uj, a.ny);
+    slp = (n - 1 - slp / n) * n + slp % n;
+    sgn = -sgn;
+  }
+  const int gi = wrapi(si, a.nx), gj = wrapi(sj, a.ny);
   const size_t plane = (size_t)a.nx * a.ny * NC;  // values per plane
   // values t + NTH i of the tile's plane: in-plane offset and whether the cell is in the grid
-  // (a ragged tile's cells beyond the edge hold the periodic images, read but never stored)
+  // (a ragged tile's cells beyond the edge hold the periodic images, or beyond a wall the odd
+  // reflections (bit i of neg), read but never stored)
   int off[n];
-  unsigned own = 0;
+  unsigned own = 0, neg = 0;
 #pragma unroll
   for (int i = 0; i < n; ++i) {
     const int e = t + NTH * i;
     const int rj = e / (TX * NC), o = e - rj * (TX * NC);
-    const int rc = o / NC, q = o - rc * NC;
-    off[i] = (wrapi(ty0 + rj, a.ny) * a.nx + wrapi(tx0 + rc, a.nx)) * NC + q;
-    if (tx0 + rc < a.nx && ty0 + rj < a.ny) own |= 1u << i;
+    const int rc = o / NC;
+    int q = o - rc * NC, ri = tx0 + rc, rjj = ty0 + rj;
+    if (ri < a.nx && rjj < a.ny) own |= 1u << i;
+    if (MIR && a.mir[0] && ri >= a.nx) {
+      ri = mirror_index(ri, a.nx);
+      q = q - q % n + (n - 1 - q % n);
+      neg ^= 1u << i;
+    }
+    if (MIR && a.mir[1] && rjj >= a.ny) {
+      rjj = mirror_index(rjj, a.ny);
+      q = q + (n - 1 - 2 * ((q / n) % n)) * n;
+      neg ^= 1u << i;
+    }
+    off[i] = (wrapi(rjj, a.ny) * a.nx + wrapi(ri, a.nx)) * NC + q;
   }
   __syncthreads();   // hbase ready
 
@@ -463,16 +501,16 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
   T zp[n], zc[n];
   {
     // planes k0 - 1 and k0 of this thread's z-line; the CG scalars are reduced while they load
-    const size_t bp = (size_t)wrap_small(k0 - 1, a.nz) * plane + ((size_t)gj * a.nx + gi) * NC + lp;
-    const size_t bc = (size_t)k0 * plane + ((size_t)gj * a.nx + gi) * NC + lp;
+    const size_t bp = (size_t)wrap_small(k0 - 1, a.nz) * plane + ((size_t)gj * a.nx + gi) * NC + slp;
+    const size_t bc = (size_t)k0 * plane + ((size_t)gj * a.nx + gi) * NC + slp;
     T pp[n], pc[n], xc[FUSE == 2 ? n : 1];
 #pragma unroll
     for (int l3 = 0; l3 < n; ++l3) {
-      zp[l3] = xg[bp + l3 * NP];
-      zc[l3] = xg[bc + l3 * NP];
+      zp[l3] = sgn * xg[bp + l3 * NP];
+      zc[l3] = sgn * xg[bc + l3 * NP];
       if (FUSE) {
-        pp[l3] = pg[bp + l3 * NP];
-        pc[l3] = pg[bc + l3 * NP];
+        pp[l3] = sgn * pg[bp + l3 * NP];
+        pc[l3] = sgn * pg[bc + l3 * NP];
       }
       if (FUSE == 2) xc[l3] = a.xsol[bc + l3 * NP];
     }
@@ -496,6 +534,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
           if (FUSE == 2 && xupd) a.xsol[bc + l3 * NP] = xc[l3] + xalpha * pc[l3];
         }
       }
+    }
+    // the plane below a Dirichlet wall at z = 0: odd reflection of plane 0
+    if (MIR && a.mir[2] && k0 == 0) {
+#pragma unroll
+      for (int l3 = 0; l3 < n; ++l3) zp[l3] = -zc[n - 1 - l3];
     }
   }
   const int xl23 = lp;                        // x-line: (l2, l3) = (lp % n, lp / n)
@@ -521,6 +564,21 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int lane = t & 63;
   T hv[HR][LR], hp[HR][LR];
+  // source element of halo element l of slot s (odd reflection across x / y walls)
+  auto hsrc = [&](int s, int l, T& sg) -> int {
+    sg = T(1);
+    if constexpr (!MIR) return l;
+    const int m = hmir[s];
+    if (m & 1) {
+      l = l - l % n + (n - 1 - l % n);
+      sg = -sg;
+    }
+    if (m & 2) {
+      l = l + (n - 1 - 2 * ((l / n) % n)) * n;
+      sg = -sg;
+    }
+    return l;
+  };
   auto halo_load = [&](int k) {
     const size_t pb = (size_t)wrap_small(k, a.nz) * plane;
 #pragma unroll
@@ -532,8 +590,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
         for (int r = 0; r < LR; ++r) {
           const int l = lane + 64 * r;
           if (l < NC) {
-            hv[i][r] = xg[g + l];
-            if (FUSE) hp[i][r] = pg[g + l];
+            // (raw values: a wall's sign is applied when they are staged)
+            T sg;
+            const int ls = hsrc(s, l, sg);
+            hv[i][r] = xg[g + ls];
+            if (FUSE) hp[i][r] = pg[g + ls];
           }
         }
       }
@@ -547,7 +608,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
 #pragma unroll
         for (int r = 0; r < LR; ++r) {
           const int l = lane + 64 * r;
-          if (l < NC) xs[s * NC + l] = FUSE ? (T)(hv[i][r] + beta * hp[i][r]) : hv[i][r];
+          if (l < NC) {
+            T sg;
+            hsrc(s, l, sg);
+            xs[s * NC + l] = sg * (FUSE ? (T)(hv[i][r] + beta * hp[i][r]) : hv[i][r]);
+          }
         }
       }
     }
@@ -559,8 +624,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
       const int s = NT + wave + NWV * i;
       if (wave < NWV && s < NS) {
         const size_t g = pb + (size_t)hbase[s] * NC;
-        for (int l = lane; l < NC; l += 64)
-          xs[s * NC + l] = FUSE ? (T)(xg[g + l] + beta * pg[g + l]) : xg[g + l];
+        for (int l = lane; l < NC; l += 64) {
+          T sg;
+          const int ls = hsrc(s, l, sg);
+          xs[s * NC + l] = sg * (FUSE ? (T)(xg[g + ls] + beta * pg[g + ls]) : xg[g + ls]);
+        }
       }
     }
   };
@@ -614,7 +682,8 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
 #pragma unroll
     for (int i = 0; i < n; ++i) {
       const T v = FUSE ? (T)(xo[i] + beta * po[i]) : xo[i];
-      xnx[t + NTH * i] = v;
+      // (owned values are never reflected: the values stored below carry no sign)
+      xnx[t + NTH * i] = MIR && ((neg >> i) & 1) ? -v : v;
       if (FUSE && store_next && ((own >> i) & 1)) {
         png[pbn + off[i]] = v;
         if (FUSE == 2 && xupd) a.xsol[pbn + off[i]] = xso[i] + xalpha * po[i];
@@ -639,6 +708,11 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
       T zn[n];
 #pragma unroll
       for (int l3 = 0; l3 < n; ++l3) zn[l3] = xnx[c * NC + l3 * NP + lp];
+      // the plane above a Dirichlet wall at z = L: odd reflection of the last plane
+      if (MIR && a.mir[2] && k + 1 == a.nz) {
+#pragma unroll
+        for (int l3 = 0; l3 < n; ++l3) zn[l3] = -zc[n - 1 - l3];
+      }
       const size_t bc = (size_t)k * plane + ((size_t)gj * a.nx + gi) * NC + lp;
       line3<T, N>(B, zp, zc, zn, [&](int l3, T v) {
         const T xc = xs[c * NC + l3 * NP + lp];
@@ -739,10 +813,17 @@ static long long resident_2d(int fuse, int v, int pf, bool mir) {
   return cache[dev][f3][v][pf][w];
 }
 
-// The 3D kernel of fused form 0, 1 or 2 and prefetch flag pf; a grid with walls (mir) runs the
-// halo-prefetch z-line form, a periodic grid the coalesced form where Co3D selects it.
+// The 3D kernel of fused form 0, 1 or 2 and prefetch flag pf: the coalesced form where Co3D
+// selects it, else the z-line form; a grid with walls (mir) runs the halo-prefetch variant.
 template <typename T, int N>
 static const void* kernel_3d(int fuse, int pf, bool mir) {
+  if constexpr (Co3D<T, N>::USE) {
+    if (mir) {
+      return fuse == 2 ? (const void*)k_apply3d_co<T, N, 2, 1, true>
+           : fuse == 1 ? (const void*)k_apply3d_co<T, N, 1, 1, true>
+                       : (const void*)k_apply3d_co<T, N, 0, 0, true>;
+    }
+  }
   if (mir) {
     return fuse == 2 ? (const void*)k_apply3d<T, N, 2, 1, true>
          : fuse == 1 ? (const void*)k_apply3d<T, N, 1, 1, true>
