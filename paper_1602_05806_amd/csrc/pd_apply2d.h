@@ -57,43 +57,86 @@ __device__ __forceinline__ int wrapi(int i, int m) {
 }
 
 
-// One output row l of the 1D three-cell operator: sum_m L[l][m] vl[m] + C[l][m] vc[m] + R[l][m] vr[m],
-// with three independent accumulators (the FMA latency is not serialised over 3(N+1) terms).
-// Called with a run-time row index from a rolled loop, so the coefficients of the rows being
-// computed are scalar-loaded per iteration instead of keeping all 3(N+1)^2 of them live.
+// One output row l of the 1D three-cell operator (row form of the blocks): sum_m L[l][m] vl[m] +
+// C[l][m] vc[m] + R[l][m] vr[m], with three independent accumulators (the FMA latency is not
+// serialised over 3(N+1) terms). Called with a run-time row index from a rolled loop, so the
+// coefficients of the rows being computed are scalar-loaded per iteration instead of keeping
+// all 3(N+1)^2 of them live.
 template <typename T, int N>
 __device__ __forceinline__ T row3(const Blk<T, N>& B, int l, const T (&vl)[N + 1],
                                   const T (&vc)[N + 1], const T (&vr)[N + 1]) {
   constexpr int n = N + 1;
+  const T* L = B.K;
+  const T* C = B.K + n * n;
+  const T* R = B.K + 2 * n * n;
   T al = T(0), ac = T(0), ar = T(0);
 #pragma unroll
   for (int m = 0; m < n; ++m) {
-    al += B.L[l * n + m] * vl[m];
-    ac += B.C[l * n + m] * vc[m];
-    ar += B.R[l * n + m] * vr[m];
+    al += L[l * n + m] * vl[m];
+    ac += C[l * n + m] * vc[m];
+    ar += R[l * n + m] * vr[m];
   }
   return (al + ac) + ar;
 }
 
-// Apply the 1D three-cell operator to one line: out(l) = op(l) for every row l, two rows per
-// iteration where the scalar-register budget allows it.
-template <typename T, int N, typename F>
+// Apply the 1D three-cell operator to one line: out(l) = L vl + C vc + R vr at every row l, in
+// the form line_eo<T, N, DIM> selects (the host fills Blk in that form).
+//   rows      row3 per row, two rows per iteration where the scalar-register budget allows it;
+//   even/odd  with s = vl + J vr and d = vl - J vr (J the node reversal, R = J L J), rows p and
+//             N - p are e + o and e - o, e = 1/2 (L_p + L_{N-p}) s + 1/2 (C_p + C_{N-p}) vc,
+//             o = 1/2 (L_p - L_{N-p}) d + 1/2 (C_p - C_{N-p}) vc: 2 (N+1)^2 FMAs per line.
+template <typename T, int N, int DIM, typename F>
 __device__ __forceinline__ void line3(const Blk<T, N>& B, const T (&vl)[N + 1],
                                       const T (&vc)[N + 1], const T (&vr)[N + 1], F&& out) {
   constexpr int n = N + 1;
-  constexpr bool pairs = 2 * 3 * n * (int)sizeof(T) / 4 <= 36;   // SGPRs of two rows
-  if constexpr (pairs) {
-#pragma unroll 1
-    for (int l = 0; l + 1 < n; l += 2) {
-      const T r0 = row3<T, N>(B, l, vl, vc, vr);
-      const T r1 = row3<T, N>(B, l + 1, vl, vc, vr);
-      out(l, r0);
-      out(l + 1, r1);
+  if constexpr (line_eo<T, N, DIM>()) {
+    constexpr int P = n / 2;
+    T s[n], d[n];
+#pragma unroll
+    for (int m = 0; m < n; ++m) {
+      s[m] = vl[m] + vr[n - 1 - m];
+      d[m] = vl[m] - vr[n - 1 - m];
     }
-    if (n & 1) out(n - 1, row3<T, N>(B, n - 1, vl, vc, vr));
-  } else {
 #pragma unroll 1
-    for (int l = 0; l < n; ++l) out(l, row3<T, N>(B, l, vl, vc, vr));
+    for (int p = 0; p < P; ++p) {
+      const T* c = B.K + 4 * n * p;
+      T e0 = T(0), e1 = T(0), o0 = T(0), o1 = T(0);
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        e0 += c[m] * s[m];
+        e1 += c[n + m] * vc[m];
+        o0 += c[2 * n + m] * d[m];
+        o1 += c[3 * n + m] * vc[m];
+      }
+      const T e = e0 + e1, o = o0 + o1;
+      out(p, e + o);
+      out(n - 1 - p, e - o);
+    }
+    if constexpr (n & 1) {
+      const T* c = B.K + 4 * n * P;
+      T e0 = T(0), e1 = T(0);
+#pragma unroll
+      for (int m = 0; m < n; ++m) {
+        e0 += c[m] * s[m];
+        e1 += c[n + m] * vc[m];
+      }
+      out(P, e0 + e1);
+    }
+  } else {
+    constexpr bool pairs = 2 * 3 * n * (int)sizeof(T) / 4 <= 36;   // SGPRs of two rows
+    if constexpr (pairs) {
+#pragma unroll 1
+      for (int l = 0; l + 1 < n; l += 2) {
+        const T r0 = row3<T, N>(B, l, vl, vc, vr);
+        const T r1 = row3<T, N>(B, l + 1, vl, vc, vr);
+        out(l, r0);
+        out(l + 1, r1);
+      }
+      if (n & 1) out(n - 1, row3<T, N>(B, n - 1, vl, vc, vr));
+    } else {
+#pragma unroll 1
+      for (int l = 0; l < n; ++l) out(l, row3<T, N>(B, l, vl, vc, vr));
+    }
   }
 }
 
@@ -303,7 +346,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
         vr[m] = xs[bc + NC + m];
       }
       const T wgt = a.c0 * B.w[l2];
-      line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + l2 * n + l1] = wgt * v; });
+      line3<T, N, 2>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + l2 * n + l1] = wgt * v; });
     }
     __syncthreads();
     if (PF && tile + t_stride < t_end) stage_load(tile + t_stride, HALF, TY + 2);
@@ -325,7 +368,7 @@ __device__ __forceinline__ void apply2d_body(const ApplyArgs<T>& a, const Blk<T,
       const size_t base = ((size_t)uj * a.nx + ui) * NC;
       const T wgt = a.c1 * B.w[l1];
       const T wm = a.alpha * B.w[l1];
-      line3<T, N>(B, vl, vc, vr, [&](int l2, T v) {
+      line3<T, N, 2>(B, vl, vc, vr, [&](int l2, T v) {
         const T xc = xs[bc + l2 * n];
         const T val = ys[c * NC + l2 * n + l1] + wgt * v + wm * B.w[l2] * xc;
         if (valid) {

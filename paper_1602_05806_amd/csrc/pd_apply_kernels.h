@@ -317,7 +317,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
         vc[m] = xs[c * NC + xl23 * n + m];
         vr[m] = xs[sxr * NC + xl23 * n + m];
       }
-      line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + xl23 * n + l1] = wx * v; });
+      line3<T, N, 3>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + xl23 * n + l1] = wx * v; });
     }
     __syncthreads();
     {  // y-line (l1, l3) of cell c
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
         vc[m] = xs[c * NC + yl3 * NP + m * n + yl1];
         vr[m] = xs[syr * NC + yl3 * NP + m * n + yl1];
       }
-      line3<T, N>(B, vl, vc, vr,
+      line3<T, N, 3>(B, vl, vc, vr,
                   [&](int l2, T v) { ys[c * NC + yl3 * NP + l2 * n + yl1] += wy * v; });
     }
     __syncthreads();
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d(ApplyArgs<T> a, Blk<
     {  // own z-line (l1, l2) from registers; final values
       const size_t bc = zbase(k);
       T* __restrict__ yg = a.y;
-      line3<T, N>(B, zp, zc, zn, [&](int l3, T v) {
+      line3<T, N, 3>(B, zp, zc, zn, [&](int l3, T v) {
         const T xc = xs[c * NC + l3 * NP + lp];
         const T val = ys[c * NC + l3 * NP + lp] + wz * v + wm * B.w[l3] * xc;
         if (valid) {
@@ -664,7 +664,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
         vc[m] = xs[c * NC + xl23 * n + m];
         vr[m] = xs[sxr * NC + xl23 * n + m];
       }
-      line3<T, N>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + xl23 * n + l1] = wx * v; });
+      line3<T, N, 3>(B, vl, vc, vr, [&](int l1, T v) { ys[c * NC + xl23 * n + l1] = wx * v; });
     }
     __syncthreads();
     {  // y-line (l1, l3) of cell c
@@ -675,7 +675,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
         vc[m] = xs[c * NC + yl3 * NP + m * n + yl1];
         vr[m] = xs[syr * NC + yl3 * NP + m * n + yl1];
       }
-      line3<T, N>(B, vl, vc, vr,
+      line3<T, N, 3>(B, vl, vc, vr,
                   [&](int l2, T v) { ys[c * NC + yl3 * NP + l2 * n + yl1] += wy * v; });
     }
     // plane k+1 into the other staging buffer; p and x of its owned values to global memory
@@ -714,7 +714,7 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
         for (int l3 = 0; l3 < n; ++l3) zn[l3] = -zc[n - 1 - l3];
       }
       const size_t bc = (size_t)k * plane + ((size_t)gj * a.nx + gi) * NC + lp;
-      line3<T, N>(B, zp, zc, zn, [&](int l3, T v) {
+      line3<T, N, 3>(B, zp, zc, zn, [&](int l3, T v) {
         const T xc = xs[c * NC + l3 * NP + lp];
         const T val = ys[c * NC + l3 * NP + lp] + wz * v + wm * B.w[l3] * xc;
         if constexpr (YDB) ys[c * NC + l3 * NP + lp] = val;
@@ -748,15 +748,9 @@ __global__ __launch_bounds__(Tile3D<N>::NTH) void k_apply3d_co(ApplyArgs<T> a, B
 // ------------------------------------------------------------------ launchers
 
 template <typename T, int N>
-static Blk<T, N> make_blk(const OpTables& tb) {
+static Blk<T, N> make_blk(const OpTables& tb, int dim) {
   Blk<T, N> B;
-  constexpr int n = N + 1;
-  for (int i = 0; i < n * n; ++i) {
-    B.L[i] = (T)tb.L[i];
-    B.C[i] = (T)tb.C[i];
-    B.R[i] = (T)tb.R[i];
-  }
-  for (int i = 0; i < n; ++i) B.w[i] = (T)tb.w[i];
+  B.fill(tb, dim == 3 ? line_eo<T, N, 3>() : line_eo<T, N, 2>());
   return B;
 }
 
@@ -969,7 +963,7 @@ hipError_t launch_apply_N(const ApplyLaunch& L, hipStream_t s) {
   a.npart = L.npart;
   a.first = L.first;
   if (L.fuse == 3 && L.dim != 2) return hipErrorInvalidValue;
-  const Blk<T, N> B = make_blk<T, N>(*L.tab);
+  const Blk<T, N> B = make_blk<T, N>(*L.tab, L.dim);
   const Geom g = geometry<T, N>(L);
   a.ntx = g.ntx;
   a.nty = g.nty;

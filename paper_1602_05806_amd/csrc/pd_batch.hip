@@ -740,13 +740,7 @@ hipError_t launch_group_N(const BatchIter& it, const BatchGroup& g, bool fuse, c
                           const void* pold, void* pnew, void* y, void* xsol, const OpTables& tb,
                           hipStream_t s) {
   Blk<T, N> B;
-  constexpr int n = N + 1;
-  for (int i = 0; i < n * n; ++i) {
-    B.L[i] = (T)tb.L[i];
-    B.C[i] = (T)tb.C[i];
-    B.R[i] = (T)tb.R[i];
-  }
-  for (int i = 0; i < n; ++i) B.w[i] = (T)tb.w[i];
+  B.fill(tb, line_eo<T, N, 2>());   // (the batched kernel runs the 2D tile body)
   if (fuse)
     hipLaunchKernelGGL((k_apply2d_batch<T, N, V, 2>), dim3(g.blocks), dim3(256), 0, s, it,
                        g.grp, g.toff, g.ng, (const T*)x, (const T*)pold, (T*)pnew, (T*)y,

@@ -15,11 +15,57 @@ constexpr int kMaxNC = 729;          // (N+1)^3 for N = 8
 // argument so that every (uniform) table access is a scalar load from the kernarg segment.
 template <typename T, int N>
 struct Blk {
-  T L[(N + 1) * (N + 1)];   // couples cell i to cell i-1
-  T C[(N + 1) * (N + 1)];   // diagonal block
-  T R[(N + 1) * (N + 1)];   // couples cell i to cell i+1
+  // The 1D blocks in one of two forms (line3 reads the form line_eo selects):
+  //   rows     K = [L | C | R], n x n each, row-major: L couples cell i to cell i-1, C is the
+  //            diagonal block, R couples cell i to cell i+1;
+  //   even/odd with J the node reversal and R = J L J: per row pair (p, N - p), p < (N+1)/2,
+  //            the rows 1/2 (L_p + L_{N-p}), 1/2 (C_p + C_{N-p}), 1/2 (L_p - L_{N-p}),
+  //            1/2 (C_p - C_{N-p}); for odd N + 1 then the middle rows L_{N/2}, C_{N/2}.
+  static constexpr int n = N + 1, P = n / 2;
+  T K[3 * n * n];
   T w[N + 1];               // GL weights (1D mass diagonal)
+  template <typename Tab>
+  __host__ void fill(const Tab& tb, bool eo) {
+    if (!eo) {
+      for (int i = 0; i < n * n; ++i) {
+        K[i] = (T)tb.L[i];
+        K[n * n + i] = (T)tb.C[i];
+        K[2 * n * n + i] = (T)tb.R[i];
+      }
+    } else {
+      for (int i = 0; i < 3 * n * n; ++i) K[i] = T(0);
+      for (int p = 0; p < P; ++p)
+        for (int m = 0; m < n; ++m) {
+          const double lp = tb.L[p * n + m], lq = tb.L[(n - 1 - p) * n + m];
+          const double cp = tb.C[p * n + m], cq = tb.C[(n - 1 - p) * n + m];
+          K[4 * n * p + m] = (T)(0.5 * (lp + lq));
+          K[4 * n * p + n + m] = (T)(0.5 * (cp + cq));
+          K[4 * n * p + 2 * n + m] = (T)(0.5 * (lp - lq));
+          K[4 * n * p + 3 * n + m] = (T)(0.5 * (cp - cq));
+        }
+      if (n & 1)
+        for (int m = 0; m < n; ++m) {
+          K[4 * n * P + m] = (T)tb.L[P * n + m];
+          K[4 * n * P + n + m] = (T)tb.C[P * n + m];
+        }
+    }
+    for (int i = 0; i < n; ++i) w[i] = (T)tb.w[i];
+  }
 };
+
+// Form of the line operator for the kernels of dimension DIM, precision T, degree N: true =
+// even/odd (2 (N+1)^2 FMAs per line instead of 3 (N+1)^2, one more scalar-register row per
+// iteration). Chosen per case by measurement (fused CG apply, ~33M DoFs in 3D, 2D as listed):
+// 3D FP64 N = 4 377 -> 357 us, N = 7 636 -> 615, N = 8 1078 -> 1038; 3D FP32 N = 3 169 -> 165,
+// N = 4 198 -> 183, N = 5 249 -> 235, N = 6 447 -> 421, N = 7 292 -> 278; 2D 512^2 N = 4 FP64
+// 77.6 -> 75.6, FP32 47.2 -> 39.8; 384^2 N = 8 FP64 208 -> 198, FP32 107 -> 99. Elsewhere the
+// extra scalar registers spill into vector registers and cost occupancy (256^2 N = 6: FP64 40.7
+// -> 53.6 us, FP32 28.1 -> 38.5; 3D FP64 N = 6 683 -> 868) or nothing changes (N <= 1).
+template <typename T, int N, int DIM>
+__host__ __device__ constexpr bool line_eo() {
+  return DIM == 2 ? (N == 4 || N == 8)
+                  : (sizeof(T) == 8 ? (N == 4 || N == 7 || N == 8) : (N >= 3 && N <= 7));
+}
 
 // Device-resident scalars of one CG solve. Kernels never synchronise across blocks inside a
 // launch: a kernel writes one partial sum per block (plain stores), and every block of the NEXT
