@@ -45,8 +45,14 @@ int main() {
     CHECK(t.nnull_odd == (N % 2 == 0 ? 0 : 1), "N=%d nnull_odd %d", N, t.nnull_odd);
     for (int p = 0; p < n; ++p)
       for (int q = 0; q < n; ++q) {
-        // L = R^T, C symmetric, V^T M V = I, C V = M V diag(lam)
+        // L = R^T, C symmetric, V^T M V = I, C V = M V diag(lam); mirror symmetry of the
+        // blocks under the node reversal J (R = J L J, C = J C J), which the even/odd form of
+        // the device line operator relies on
         CHECK(t.Lb[p * n + q] == t.Rb[q * n + p], "N=%d L != R^T", N);
+        CHECK(std::fabs(t.Rb[p * n + q] - t.Lb[(n - 1 - p) * n + (n - 1 - q)]) <= 1e-13 * (1.0 + std::fabs(t.Lb[p * n + q])),
+              "N=%d R != J L J at (%d,%d)", N, p, q);
+        CHECK(std::fabs(t.Cb[p * n + q] - t.Cb[(n - 1 - p) * n + (n - 1 - q)]) <= 1e-12 * (1.0 + std::fabs(t.Cb[p * n + q])),
+              "N=%d C != J C J at (%d,%d)", N, p, q);
         CHECK(std::fabs(t.Cb[p * n + q] - t.Cb[q * n + p]) <= 1e-12 * std::fabs(t.Cb[p * n + p]) + 1e-12,
               "N=%d C not symmetric", N);
         double g = 0.0, cv = 0.0;
