@@ -180,14 +180,17 @@ def bench_batch(args, pd, torch):
         x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
         for _ in range(args.warmup):
             pd.pd_batch_cg_solve(B, prec, b, x, cfg["rtol"], cfg["maxit"])
+            print(f"bench.py: batch {name} warm-up solve done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         work, infos = 0, None
-        for _ in range(args.steps):
+        for step in range(args.steps):
             rc, infos = pd.pd_batch_cg_solve(B, prec, b, x, cfg["rtol"], cfg["maxit"])
             if rc != pd.PD_OK:
                 raise RuntimeError(f"batched solve failed ({name}): rc {rc}")
             work += sum(n * i["iters"] for n, i in zip(ndofs, infos))
+            print(f"bench.py: batch {name} step {step + 1}/{args.steps} done", file=sys.stderr,
+                  flush=True)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         bytes_it = 36.0 if prec == pd.PD_FP32_REFINE64 else 72.0   # 9 vector words per DoF
