@@ -10,7 +10,7 @@ import pytest
 
 from oracle import layout
 from oracle.operators import Grid, null_bases, pressure_operator, project_null, viscous_operator
-from oracle.solvers import cg
+from oracle.solvers import FastDiag, cg
 import synthetic
 
 pytestmark = pytest.mark.gpu
@@ -38,6 +38,7 @@ def _draw(seed, count, min_dofs=1):
 
 APPLY = _draw(20261203, 40)
 ITER = _draw(1203, 16, min_dofs=300)   # (no Krylov space exhausted within 12 iterations)
+SOLVE = _draw(3012, 12, min_dofs=300)
 
 
 def _dev(a, dtype=None):
@@ -101,3 +102,39 @@ def test_cg_iterates_random_shapes(pd, case):
     assert info["status"] == pd.PD_ENOCONV and info["iters"] == m
     got = layout.blocked_to_tensor(_host(x), cells, g.n).reshape(-1)
     assert np.linalg.norm(got - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
+
+
+def _mass_norm(g, T):
+    W = np.ones(g.shape())
+    for d in range(g.dim):
+        shp = [1] * g.dim
+        shp[g.dim - 1 - d] = -1
+        W = W * np.tile(g.tab.w, g.cells[d]).reshape(shp)
+    return np.sqrt(np.sum(W * T ** 2))
+
+
+@pytest.mark.parametrize("case", range(len(SOLVE)))
+def test_solves_random_shapes(pd, case):
+    """Pressure solves to rtol 1e-12 (FP64, FP32+refine, and FP64 with the cell-block Jacobi
+    preconditioner) of an unprojected random right-hand side reach the oracle's
+    fast-diagonalisation minimum-norm solution (mass-weighted error <= 1e-9)."""
+    import torch
+    dim, cells, lengths, N, mask = SOLVE[case]
+    print(f"random solve {case}: dim={dim} cells={cells} N={N} mask={mask:b}", flush=True)
+    dt = 5e-4
+    g = Grid(cells, lengths, N, periodic=_flags(dim, mask))
+    b = synthetic.random_rhs(900 + case, g.ndof)
+    ref = FastDiag(g).solve(layout.blocked_to_tensor(b, cells, g.n), 0.0, dt)
+    ctx = pd.pd_setup(dim, cells, lengths, N, dt, 0.6, 1e-2, periodic_mask=mask)
+    for prec, pc in ((pd.PD_FP64, 0), (pd.PD_FP32_REFINE64, 0), (pd.PD_FP64, 1)):
+        pd.pd_configure(ctx, pd.PD_CFG_PRECOND, pc)
+        x = torch.zeros(g.ndof, dtype=torch.float64, device="cuda")
+        info = pd.pd_cg_solve(ctx, 0, prec, _dev(b), x, 1e-12, 400000)
+        got = layout.blocked_to_tensor(_host(x), cells, g.n)
+        err = _mass_norm(g, got - ref) / _mass_norm(g, ref)
+        print(f"  prec={prec} precond={pc}: {info['iters']} it, true {info['rel_res_true']:.1e}, "
+              f"error {err:.1e}", flush=True)
+        assert info["status"] == pd.PD_OK
+        assert info["rel_res_true"] <= 2e-12
+        assert err <= 1e-9
+    ctx.close()
