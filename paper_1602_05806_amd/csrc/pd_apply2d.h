@@ -1,6 +1,6 @@
 // Shared pieces of the operator-apply kernels (single-problem and batched launches): kernel
 // argument block, periodic index wrap, the 1D three-cell line operator and the 2D tile body.
-// See pd_apply.hip for the design notes.
+// The kernel design notes are at the top of pd_apply_kernels.h.
 #pragma once
 #include "pd_device.h"
 

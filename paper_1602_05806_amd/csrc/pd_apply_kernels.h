@@ -392,9 +392,10 @@ struct Co3D {
   static constexpr bool OK = N <= 5 && XS + YS + NS * 4L <= 160L * 1024;
   static constexpr bool YDB = XS + 2 * YS + NS * 4L <= 160L * 1024;
   // where it is used (per-launch means of the fused CG apply, ~33M DoFs, against the z-line
-  // form): FP32 N = 1..4 (128^3 N = 1: 91.5 against 108.8 us; 96^3 N = 2: 174 / 216; 80^3
-  // N = 3: 169 / 194; 64^3 N = 4: 196 / 210) and FP64 N = 1 (208.5 / 219). FP64 N = 2..5 and
-  // FP32 N = 5 stay on the z-line form (64^3 N = 4 FP64: 385 against 378 us; 54^3 N = 5 FP32:
+  // form, both with the row form of the line operator): FP32 N = 1..4 (128^3 N = 1: 91.5
+  // against 108.8 us; 96^3 N = 2: 174 / 216; 80^3 N = 3: 169 / 194; 64^3 N = 4: 196 / 210) and
+  // FP64 N = 1 (208.5 / 219). FP64 N = 2..5 and FP32 N = 5 stay on the z-line form (64^3 N = 4
+  // FP64: 385 against 378 us, with the even/odd line form 358.8 against 357.3; 54^3 N = 5 FP32:
   // 267 / 249, the coalesced form needs 129 registers there), and so does N = 0 (one value
   // per cell: nothing to coalesce).
   static constexpr bool USE = OK && (sizeof(T) == 4 ? (N >= 1 && N <= 4) : N == 1);
