@@ -84,42 +84,51 @@ __device__ __forceinline__ T row3(const Blk<T, N>& B, int l, const T (&vl)[N + 1
 //   rows      row3 per row, two rows per iteration where the scalar-register budget allows it;
 //   even/odd  with s = vl + J vr and d = vl - J vr (J the node reversal, R = J L J), rows p and
 //             N - p are e + o and e - o, e = 1/2 (L_p + L_{N-p}) s + 1/2 (C_p + C_{N-p}) vc,
-//             o = 1/2 (L_p - L_{N-p}) d + 1/2 (C_p - C_{N-p}) vc: 2 (N+1)^2 FMAs per line.
+//             o = 1/2 (L_p - L_{N-p}) d + 1/2 (C_p - C_{N-p}) vc; as C = J C J, the C parts
+//             are sums over m < (N+1)/2 of the half rows on vc[m] + vc[N-m] and vc[m] - vc[N-m]:
+//             about 1.5 (N+1)^2 FMAs per line.
 template <typename T, int N, int DIM, typename F>
 __device__ __forceinline__ void line3(const Blk<T, N>& B, const T (&vl)[N + 1],
                                       const T (&vc)[N + 1], const T (&vr)[N + 1], F&& out) {
   constexpr int n = N + 1;
   if constexpr (line_eo<T, N, DIM>()) {
-    constexpr int P = n / 2;
-    T s[n], d[n];
+    constexpr int P = n / 2, H1 = (n + 1) / 2, H0 = n / 2, PS = 3 * n;
+    T s[n], d[n], ce[H1], co[H0 > 0 ? H0 : 1];
 #pragma unroll
     for (int m = 0; m < n; ++m) {
       s[m] = vl[m] + vr[n - 1 - m];
       d[m] = vl[m] - vr[n - 1 - m];
     }
+#pragma unroll
+    for (int m = 0; m < H0; ++m) {
+      ce[m] = vc[m] + vc[n - 1 - m];
+      co[m] = vc[m] - vc[n - 1 - m];
+    }
+    if constexpr (n & 1) ce[H0] = vc[H0];
 #pragma unroll 1
     for (int p = 0; p < P; ++p) {
-      const T* c = B.K + 4 * n * p;
+      const T* c = B.K + PS * p;
       T e0 = T(0), e1 = T(0), o0 = T(0), o1 = T(0);
 #pragma unroll
       for (int m = 0; m < n; ++m) {
         e0 += c[m] * s[m];
-        e1 += c[n + m] * vc[m];
-        o0 += c[2 * n + m] * d[m];
-        o1 += c[3 * n + m] * vc[m];
+        o0 += c[n + H1 + m] * d[m];
       }
+#pragma unroll
+      for (int m = 0; m < H1; ++m) e1 += c[n + m] * ce[m];
+#pragma unroll
+      for (int m = 0; m < H0; ++m) o1 += c[2 * n + H1 + m] * co[m];
       const T e = e0 + e1, o = o0 + o1;
       out(p, e + o);
       out(n - 1 - p, e - o);
     }
     if constexpr (n & 1) {
-      const T* c = B.K + 4 * n * P;
+      const T* c = B.K + PS * P;
       T e0 = T(0), e1 = T(0);
 #pragma unroll
-      for (int m = 0; m < n; ++m) {
-        e0 += c[m] * s[m];
-        e1 += c[n + m] * vc[m];
-      }
+      for (int m = 0; m < n; ++m) e0 += c[m] * s[m];
+#pragma unroll
+      for (int m = 0; m < H1; ++m) e1 += c[n + m] * ce[m];
       out(P, e0 + e1);
     }
   } else {

@@ -18,9 +18,10 @@ struct Blk {
   // The 1D blocks in one of two forms (line3 reads the form line_eo selects):
   //   rows     K = [L | C | R], n x n each, row-major: L couples cell i to cell i-1, C is the
   //            diagonal block, R couples cell i to cell i+1;
-  //   even/odd with J the node reversal and R = J L J: per row pair (p, N - p), p < (N+1)/2,
-  //            the rows 1/2 (L_p + L_{N-p}), 1/2 (C_p + C_{N-p}), 1/2 (L_p - L_{N-p}),
-  //            1/2 (C_p - C_{N-p}); for odd N + 1 then the middle rows L_{N/2}, C_{N/2}.
+  //   even/odd with J the node reversal, R = J L J and C = J C J: per row pair (p, N - p),
+  //            p < (N+1)/2, the rows 1/2 (L_p + L_{N-p}) and 1/2 (L_p - L_{N-p}) (n entries
+  //            each) and the halves 1/2 (C_p[m] +- C_p[N-m]), m < (N+1)/2, that act on
+  //            vc[m] +- vc[N-m]; for odd N + 1 then the middle rows L_{N/2} and C_{N/2}[m <= N/2].
   static constexpr int n = N + 1, P = n / 2;
   T K[3 * n * n];
   T w[N + 1];               // GL weights (1D mass diagonal)
@@ -33,38 +34,46 @@ struct Blk {
         K[2 * n * n + i] = (T)tb.R[i];
       }
     } else {
+      // per pair p: [AL (n) | ACh (H1) | BL (n) | BCh (H0)], H1 = ceil(n/2), H0 = floor(n/2);
+      // then for odd n the middle row [L_mid (n) | C_mid (H1)]
+      constexpr int H1 = (n + 1) / 2, H0 = n / 2, PS = 3 * n;
       for (int i = 0; i < 3 * n * n; ++i) K[i] = T(0);
-      for (int p = 0; p < P; ++p)
+      for (int p = 0; p < P; ++p) {
+        const int q = n - 1 - p;
+        T* c = K + PS * p;
         for (int m = 0; m < n; ++m) {
-          const double lp = tb.L[p * n + m], lq = tb.L[(n - 1 - p) * n + m];
-          const double cp = tb.C[p * n + m], cq = tb.C[(n - 1 - p) * n + m];
-          K[4 * n * p + m] = (T)(0.5 * (lp + lq));
-          K[4 * n * p + n + m] = (T)(0.5 * (cp + cq));
-          K[4 * n * p + 2 * n + m] = (T)(0.5 * (lp - lq));
-          K[4 * n * p + 3 * n + m] = (T)(0.5 * (cp - cq));
+          c[m] = (T)(0.5 * (tb.L[p * n + m] + tb.L[q * n + m]));
+          c[n + H1 + m] = (T)(0.5 * (tb.L[p * n + m] - tb.L[q * n + m]));
         }
-      if (n & 1)
-        for (int m = 0; m < n; ++m) {
-          K[4 * n * P + m] = (T)tb.L[P * n + m];
-          K[4 * n * P + n + m] = (T)tb.C[P * n + m];
+        for (int m = 0; m < H0; ++m) {
+          c[n + m] = (T)(0.5 * (tb.C[p * n + m] + tb.C[p * n + n - 1 - m]));
+          c[2 * n + H1 + m] = (T)(0.5 * (tb.C[p * n + m] - tb.C[p * n + n - 1 - m]));
         }
+        if (n & 1) c[n + H0] = (T)tb.C[p * n + H0];
+      }
+      if (n & 1) {
+        T* c = K + PS * P;
+        for (int m = 0; m < n; ++m) c[m] = (T)tb.L[P * n + m];
+        for (int m = 0; m < H1; ++m) c[n + m] = (T)tb.C[P * n + m];
+      }
     }
     for (int i = 0; i < n; ++i) w[i] = (T)tb.w[i];
   }
 };
 
 // Form of the line operator for the kernels of dimension DIM, precision T, degree N: true =
-// even/odd (2 (N+1)^2 FMAs per line instead of 3 (N+1)^2, one more scalar-register row per
+// even/odd (about 1.5 (N+1)^2 FMAs per line instead of 3 (N+1)^2, two output rows per
 // iteration). Chosen per case by measurement (fused CG apply, ~33M DoFs in 3D, 2D as listed):
-// 3D FP64 N = 4 377 -> 357 us, N = 7 636 -> 615, N = 8 1078 -> 1038; 3D FP32 N = 3 169 -> 165,
-// N = 4 198 -> 183, N = 5 249 -> 235, N = 6 447 -> 421, N = 7 292 -> 278; 2D 512^2 N = 4 FP64
-// 77.6 -> 75.6, FP32 47.2 -> 39.8; 384^2 N = 8 FP64 208 -> 198, FP32 107 -> 99. Elsewhere the
-// extra scalar registers spill into vector registers and cost occupancy (256^2 N = 6: FP64 40.7
-// -> 53.6 us, FP32 28.1 -> 38.5; 3D FP64 N = 6 683 -> 868) or nothing changes (N <= 1).
+// 3D FP64 N = 4 377 -> 350 us, N = 7 636 -> 608, N = 8 1078 -> 1006; 3D FP32 N = 3 169 -> 163,
+// N = 4 198 -> 178, N = 5 249 -> 227, N = 6 447 -> 411, N = 7 292 -> 276, N = 8 643 -> 591;
+// 2D 512^2 N = 4 FP64 77.6 -> 68.4, FP32 47.2 -> 39.4; 384^2 N = 8 FP32 107 -> 98. Elsewhere
+// the two rows' live values cost vector registers and occupancy (256^2 N = 6: FP64 40.8 ->
+// 56.2 us, FP32 28.0 -> 34.5; 384^2 N = 8 FP64 207 -> 232; 3D FP64 N = 5 557 -> 705, N = 6
+// 690 -> 871) or nothing changes (N <= 1).
 template <typename T, int N, int DIM>
 __host__ __device__ constexpr bool line_eo() {
-  return DIM == 2 ? (N == 4 || N == 8)
-                  : (sizeof(T) == 8 ? (N == 4 || N == 7 || N == 8) : (N >= 3 && N <= 7));
+  return DIM == 2 ? (N == 4 || (N == 8 && sizeof(T) == 4))
+                  : (sizeof(T) == 8 ? (N == 4 || N == 7 || N == 8) : (N >= 3 && N <= 8));
 }
 
 // Device-resident scalars of one CG solve. Kernels never synchronise across blocks inside a
