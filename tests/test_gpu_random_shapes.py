@@ -138,3 +138,53 @@ def test_solves_random_shapes(pd, case):
         assert info["rel_res_true"] <= 2e-12
         assert err <= 1e-9
     ctx.close()
+
+
+def _draw_batch(seed, count):
+    """`count` periodic 2D problems (cells, lengths, N) from a fixed seed, 300..20000 DoFs each."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        N = int(rng.integers(0, 9))
+        cells = (int(rng.integers(1, 40)), int(rng.integers(1, 40)))
+        if not 300 <= cells[0] * cells[1] * (N + 1) ** 2 <= 20000:
+            continue
+        out.append((cells, (float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.5, 2.0))), N))
+    return out
+
+
+BATCH = _draw_batch(4251, 14)   # (degrees 0, 1, 2, 4, 5, 6, 7, 8)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "refine", "pcg"])
+def test_batch_random_mix(pd, mode):
+    """A batch of 14 periodic 2D problems of seeded random sizes, cell lengths and degrees (every
+    problem its own tile shape and iteration count) solved to rtol 1e-12 in FP64, FP32+refine or
+    preconditioned FP64: each problem reaches the oracle's minimum-norm solution (<= 1e-9)."""
+    import torch
+    print(f"batch random mix {mode}: {[(c, N) for c, _, N in BATCH]}", flush=True)
+    dt = 5e-4
+    B = pd.pd_batch_setup([c for c, _, _ in BATCH], [ln for _, ln, _ in BATCH],
+                          [N for _, _, N in BATCH], dt)
+    pd.pd_batch_configure(B, pd.PD_BCFG_PRECOND, 1 if mode == "pcg" else 0)
+    parts = [synthetic.random_rhs(1500 + j, c[0] * c[1] * (N + 1) ** 2)
+             for j, (c, _, N) in enumerate(BATCH)]
+    x = torch.zeros(B.total, dtype=torch.float64, device="cuda")
+    prec = pd.PD_FP32_REFINE64 if mode == "refine" else pd.PD_FP64
+    rc, infos = pd.pd_batch_cg_solve(B, prec, _dev(np.concatenate(parts)), x, 1e-12, 400000)
+    xh = _host(x)
+    offs = list(B.offsets)
+    B.close()
+    assert rc == pd.PD_OK, infos
+    for j, (cells, lengths, N) in enumerate(BATCH):
+        g = Grid(cells, lengths, N)
+        ref = FastDiag(g).solve(layout.blocked_to_tensor(parts[j], cells, N + 1), 0.0, dt)
+        got = layout.blocked_to_tensor(xh[offs[j]:offs[j + 1]], cells, N + 1)
+        err = _mass_norm(g, got - ref) / _mass_norm(g, ref)
+        print(f"  problem {j}: cells={cells} N={N} {infos[j]['iters']} it, "
+              f"true {infos[j]['rel_res_true']:.1e}, error {err:.1e}", flush=True)
+        assert infos[j]["status"] == pd.PD_OK
+        # (the FP64 evaluation of b - A x for the N = 7, 8 problems has a rounding floor near
+        # 1e-12: the FP64 batch ends there, e.g. 1.9e-12 for 8 x 14 cells at N = 7)
+        assert infos[j]["rel_res_true"] <= 1e-11
+        assert err <= 1e-9
